@@ -1,0 +1,260 @@
+"""FP64 CPU oracle of the splat renderer (ctypes wrapper around oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark use it.  The product path never imports this package, and
+this package imports nothing from the product path; the only thing both sides
+share is the seeded input generator package ``workloads``.
+
+Camera arguments are ``workloads.Camera`` objects (or anything with R, t, fx,
+fy, cx, cy, width, height).  All arrays are widened exactly from float32 to
+float64 before the call.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ALPHA_MIN = 1e-5
+T_MIN = 1e-5
+ALPHA_MAX = 0.99
+Z_NEAR = 0.01
+
+
+@dataclass
+class Params:
+    """Renderer thresholds.  ``Params.untruncated()`` gives the literal
+    Eq. (6)-(7) sum over every point (no cull, no early stop, no clamp)."""
+    alpha_min: float = ALPHA_MIN
+    t_min: float = T_MIN
+    alpha_max: float = ALPHA_MAX
+    z_near: float = Z_NEAR
+    sh_frame: int = 0          # 0 = camera-frame direction (Eq. 3), 1 = world frame
+
+    @staticmethod
+    def untruncated(z_near: float = Z_NEAR, sh_frame: int = 0) -> "Params":
+        return Params(0.0, 0.0, 1.0, z_near, sh_frame)
+
+    def array(self) -> np.ndarray:
+        return np.array([self.alpha_min, self.t_min, self.alpha_max, self.z_near], np.float64)
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain C99, OpenMP, no FP contraction)."""
+    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        L.oracle_sh_basis.argtypes = [i32, P, i64, P, P]
+        L.oracle_project.argtypes = [i64, P, P, i32, P, P, f64, i32, P, P]
+        L.oracle_depth_order.argtypes = [i64, P, P, f64, P, P]
+        L.oracle_render.argtypes = [i64, P, P, i32, P, P, P, i32, i32, P, i32, i32, i64, P,
+                                    P, P, P, P, i32]
+        L.oracle_backward.argtypes = [i64, P, P, i32, P, P, P, i32, i32, P, i32, i32, i64, P,
+                                      P, P, P, P, P, i32]
+        L.oracle_max_threads.argtypes = []
+        for f in (L.oracle_sh_basis, L.oracle_project, L.oracle_depth_order, L.oracle_render,
+                  L.oracle_backward, L.oracle_max_threads):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32), dtype=np.float64)
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def cam_array(cam) -> np.ndarray:
+    R = np.asarray(cam.R, np.float32).reshape(9)
+    t = np.asarray(cam.t, np.float32).reshape(3)
+    v = np.concatenate([R, t, np.array([cam.fx, cam.fy, cam.cx, cam.cy], np.float32)])
+    return v.astype(np.float64)
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
+
+
+def sh_basis(degree: int, dirs: np.ndarray, grad: bool = False):
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    K = (degree + 1) ** 2
+    Y = np.zeros((dirs.shape[0], K))
+    dY = np.zeros((dirs.shape[0], K, 3)) if grad else None
+    rc = lib().oracle_sh_basis(degree, _p(dirs), dirs.shape[0], _p(Y), _p(dY))
+    if rc:
+        raise ValueError("bad SH degree")
+    return (Y, dY) if grad else Y
+
+
+def project(scene, cam, params: Params = Params()):
+    """Per-point quantities of one view.  Returns a dict of float64 arrays
+    (px, py, sx, sy, z, color[N,3], dir[N,3], valid[N] bool) and zkey float32."""
+    xyz, sh, rad = _d(scene.xyz), _d(scene.sh), _d(scene.radius)
+    n = xyz.shape[0]
+    out = np.zeros((n, 12))
+    zk = np.zeros(n, np.float32)
+    rc = lib().oracle_project(n, _p(xyz), _p(sh), scene.sh_degree, _p(rad), _p(cam_array(cam)),
+                              params.z_near, params.sh_frame, _p(out), _p(zk))
+    if rc:
+        raise ValueError("oracle_project failed")
+    return dict(px=out[:, 0], py=out[:, 1], sx=out[:, 2], sy=out[:, 3], z=out[:, 4],
+                color=out[:, 5:8], dir=out[:, 8:11], valid=out[:, 11] > 0.5, zkey=zk)
+
+
+def depth_order(scene, cam, params: Params = Params()) -> np.ndarray:
+    xyz = _d(scene.xyz)
+    n = xyz.shape[0]
+    order = np.zeros(max(n, 1), np.int64)
+    m = np.zeros(1, np.int64)
+    lib().oracle_depth_order(n, _p(xyz), _p(cam_array(cam)), params.z_near, _p(order), _p(m))
+    return order[: int(m[0])]
+
+
+@dataclass
+class RenderResult:
+    image: np.ndarray      # [npix, 3] (or [H, W, 3] for a full frame)
+    trans: np.ndarray      # [npix]    (or [H, W])
+    ncontrib: np.ndarray   # number of blended splats per pixel
+    stopped: np.ndarray    # early stop fired
+
+
+def render(scene, cam, params: Params = Params(), pixels: Optional[np.ndarray] = None,
+           mode: str = "grid", threads: int = 0) -> RenderResult:
+    """Forward render of one view.  ``pixels``: linear indices y*W+x, or None
+    for the full frame (then the outputs are shaped [H, W, ...])."""
+    xyz, sh, op, rad = _d(scene.xyz), _d(scene.sh), _d(scene.opacity), _d(scene.radius)
+    n = xyz.shape[0]
+    W, H = cam.width, cam.height
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
+    npix = W * H if pix is None else pix.shape[0]
+    img = np.zeros((npix, 3))
+    tr = np.zeros(npix)
+    nc = np.zeros(npix, np.int64)
+    st = np.zeros(npix, np.int32)
+    m = {"brute": 0, "grid": 1}[mode]
+    rc = lib().oracle_render(n, _p(xyz), _p(sh), scene.sh_degree, _p(op), _p(rad), _p(cam_array(cam)),
+                             W, H, _p(params.array()), params.sh_frame, m, npix, _p(pix),
+                             _p(img), _p(tr), _p(nc), _p(st), threads)
+    if rc:
+        raise ValueError("oracle_render failed")
+    if pix is None:
+        return RenderResult(img.reshape(H, W, 3), tr.reshape(H, W), nc.reshape(H, W), st.reshape(H, W))
+    return RenderResult(img, tr, nc, st)
+
+
+@dataclass
+class Grads:
+    xyz: np.ndarray
+    sh: np.ndarray
+    opacity: np.ndarray
+
+
+def backward(scene, cams: Sequence, dL_dimage: Sequence[np.ndarray],
+             dL_dtrans: Optional[Sequence[Optional[np.ndarray]]] = None,
+             params: Params = Params(), pixels: Optional[Sequence[Optional[np.ndarray]]] = None,
+             mode: str = "grid", threads: int = 0) -> Grads:
+    """Analytic gradients summed over views.  dL_dimage[v] is [H,W,3] (full
+    frame) or [npix,3] matching pixels[v]."""
+    xyz, sh, op, rad = _d(scene.xyz), _d(scene.sh), _d(scene.opacity), _d(scene.radius)
+    n = xyz.shape[0]
+    gx = np.zeros((n, 3))
+    gs = np.zeros(sh.shape)
+    go = np.zeros(n)
+    m = {"brute": 0, "grid": 1}[mode]
+    for v, cam in enumerate(cams):
+        W, H = cam.width, cam.height
+        pix = None if pixels is None or pixels[v] is None else np.ascontiguousarray(pixels[v], np.int64)
+        npix = W * H if pix is None else pix.shape[0]
+        gI = np.ascontiguousarray(dL_dimage[v], np.float64).reshape(npix, 3)
+        gT = None
+        if dL_dtrans is not None and dL_dtrans[v] is not None:
+            gT = np.ascontiguousarray(dL_dtrans[v], np.float64).reshape(npix)
+        rc = lib().oracle_backward(n, _p(xyz), _p(sh), scene.sh_degree, _p(op), _p(rad),
+                                   _p(cam_array(cam)), W, H, _p(params.array()), params.sh_frame, m,
+                                   npix, _p(pix), _p(gI), _p(gT), _p(gx), _p(gs), _p(go), threads)
+        if rc:
+            raise ValueError("oracle_backward failed")
+    return Grads(gx, gs, go)
+
+
+def render_double(xyz, sh, opacity, radius, cam, params: Params = Params(), pixels=None,
+                  mode: str = "brute", threads: int = 0) -> RenderResult:
+    """Forward render from float64 arrays as given (no float32 rounding of the
+    inputs), used by the finite-difference checks of the gradients.  The depth
+    key is still the float32 key of the (rounded) positions."""
+    class _S:
+        pass
+    s = _S()
+    s.xyz = np.ascontiguousarray(xyz, np.float64)
+    s.sh = np.ascontiguousarray(sh, np.float64)
+    s.opacity = np.ascontiguousarray(opacity, np.float64)
+    s.radius = np.ascontiguousarray(radius, np.float64)
+    s.sh_degree = {1: 0, 4: 1, 9: 2, 16: 3}[s.sh.shape[1]]
+    W, H = cam.width, cam.height
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
+    npix = W * H if pix is None else pix.shape[0]
+    img = np.zeros((npix, 3))
+    tr = np.zeros(npix)
+    nc = np.zeros(npix, np.int64)
+    st = np.zeros(npix, np.int32)
+    m = {"brute": 0, "grid": 1}[mode]
+    n = s.xyz.shape[0]
+    rc = lib().oracle_render(n, _p(s.xyz), _p(s.sh), s.sh_degree, _p(s.opacity), _p(s.radius),
+                             _p(cam_array(cam)), W, H, _p(params.array()), params.sh_frame, m, npix,
+                             _p(pix), _p(img), _p(tr), _p(nc), _p(st), threads)
+    if rc:
+        raise ValueError("oracle_render failed")
+    return RenderResult(img, tr, nc, st)
+
+
+def backward_double(xyz, sh, opacity, radius, cam, dL_dimage, dL_dtrans=None, params: Params = Params(),
+                    pixels=None, mode: str = "brute", threads: int = 0) -> Grads:
+    """Analytic gradients from float64 arrays as given (one view)."""
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    sh = np.ascontiguousarray(sh, np.float64)
+    op = np.ascontiguousarray(opacity, np.float64)
+    rad = np.ascontiguousarray(radius, np.float64)
+    deg = {1: 0, 4: 1, 9: 2, 16: 3}[sh.shape[1]]
+    n = xyz.shape[0]
+    W, H = cam.width, cam.height
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
+    npix = W * H if pix is None else pix.shape[0]
+    gI = np.ascontiguousarray(dL_dimage, np.float64).reshape(npix, 3)
+    gT = None if dL_dtrans is None else np.ascontiguousarray(dL_dtrans, np.float64).reshape(npix)
+    gx = np.zeros((n, 3))
+    gs = np.zeros(sh.shape)
+    go = np.zeros(n)
+    m = {"brute": 0, "grid": 1}[mode]
+    rc = lib().oracle_backward(n, _p(xyz), _p(sh), deg, _p(op), _p(rad), _p(cam_array(cam)), W, H,
+                               _p(params.array()), params.sh_frame, m, npix, _p(pix), _p(gI), _p(gT),
+                               _p(gx), _p(gs), _p(go), threads)
+    if rc:
+        raise ValueError("oracle_backward failed")
+    return Grads(gx, gs, go)
