@@ -1,0 +1,214 @@
+"""Throughput of the splat renderer on one MI355X.
+
+Default workload: 300k points (30% on a bumpy surface), SH degree 2, four
+800x800 views per step, FP32.  One step = the whole hot path over one batch:
+projection + SH colour, depth sort, tile binning, compositing (forward), then
+the L2-loss gradient and the compositing + per-point backward.  Inputs (scene,
+cameras, target images) are resident in HBM before timing starts.
+
+Prints ONE JSON line:  metric/value = forward+backward Mpix/s (stored-T mode),
+plus forward-only and recompute-T rates, the roofline of the dominant kernel
+(HIP events on the library's stream, algorithmic work from the per-pixel
+blended-splat counts) and the FP64 CPU oracle timed on one step's views.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s fwd & fwd+bwd (300k pts, 800x800) at 1e-4 err; served p50/p99 latency"
+PEAK_HBM = 8.0e12                 # B/s
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # non-packed FP32 VALU lane-ops/s (39.3 T)
+FWD_OPS_PER_BLEND = 20            # lane-ops per blended (pixel, splat), forward composite
+BWD_OPS_PER_BLEND = 50            # lane-ops per blended (pixel, splat), backward composite
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2205_14330_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    e = d.get(workload, {}).get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(scene, cams, targets_fn):
+    """FP64 oracle on one full step (all views, forward + backward)."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    grads = None
+    pix = 0
+    for v, cam in enumerate(cams):
+        r = oracle.render(scene, cam, threads=cores)
+        gI = 2.0 * (r.image - targets_fn(v))
+        oracle.backward(scene, [cam], [gI], None, threads=cores)
+        pix += cam.pixels
+    dt = time.perf_counter() - t0
+    return {"value": pix / dt / 1e6, "unit": "Mpix/s", "cores": min(cores, oracle.max_threads()), "kind": "oracle",
+            "sample": f"one full step: {len(cams)} views x {cams[0].width}x{cams[0].height}, fwd+bwd, "
+                      f"FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--points", type=int, default=300_000)
+    ap.add_argument("--size", type=int, default=800)
+    ap.add_argument("--views", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--persistent", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this renderer runs on one GPU; --gpus above 1 is not supported "
+                                   "(multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import paper_2205_14330_amd as dpr
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    dpr.load()
+    dev = torch.device("cuda:0")
+    V, S = args.views, args.size
+    scene_np, cams, gt_np = workloads.config3(n=args.points, size=S, views_per_step=V, steps=100)
+    scene = dpr.SceneTensors.from_numpy(scene_np, dev)
+    gt = dpr.SceneTensors.from_numpy(gt_np, dev)
+    nsteps = args.warmup + args.steps
+    step_views = [cams[(k % 100) * V:(k % 100) * V + V] for k in range(nsteps)]
+
+    # targets: renders of the ground-truth scene from each step's views (untimed)
+    targets = []
+    for k in range(min(nsteps, 100)):
+        p = dpr.Plan([gt], [(0, c) for c in step_views[k]], dpr.RenderParams(bwd_mode="recompute"))
+        p.forward()
+        targets.append(torch.stack(p.images).clone())
+        p.free()
+    torch.cuda.synchronize()
+    log(f"setup done: {args.points} points, {V} x {S}x{S}, {nsteps} steps")
+
+    def step(k, params, backward=True):
+        plan = dpr.Plan([scene], [(0, c) for c in step_views[k]], params)
+        plan.forward()
+        if backward:
+            tgt = targets[k % len(targets)]
+            g = [(2.0 * (plan.images[v] - tgt[v])).contiguous() for v in range(V)]
+            plan.backward(g, None)
+        return plan
+
+    def timed(params, backward, steps, warmup):
+        for k in range(warmup):
+            step(k, params, backward)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plans = [step(warmup + k, params, backward) for k in range(steps)]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, plans
+
+    pix_step = V * S * S
+    base = dict(persistent=args.persistent)
+    # main metric: forward + backward (stored T), with stage timing and blend counts
+    t_fb, plans = timed(dpr.RenderParams(timing=True, stats=True, **base), True, args.steps, args.warmup)
+    stage_ms = {s: 0.0 for s in dpr.STAGES}
+    blends = 0
+    pairs = 0
+    for p in plans:
+        for s, v in p.stage_times().items():
+            if v > 0:
+                stage_ms[s] += v
+        inf = p.info()
+        blends += int(p.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32).sum().item())
+        pairs += inf.pairs
+        p.free()
+    del plans
+    K = args.steps
+    mpix_fb = pix_step * K / t_fb / 1e6
+    log(f"fwd+bwd: {t_fb / K * 1e3:.3f} ms/step, {mpix_fb:.1f} Mpix/s")
+    log("stage ms/step: " + ", ".join(f"{s}={v / K:.3f}" for s, v in stage_ms.items()))
+
+    t_f, plans = timed(dpr.RenderParams(**base), False, K, args.warmup)
+    for p in plans:
+        p.free()
+    mpix_f = pix_step * K / t_f / 1e6
+    t_r, plans = timed(dpr.RenderParams(bwd_mode="recompute", **base), True, K, args.warmup)
+    for p in plans:
+        p.free()
+    mpix_r = pix_step * K / t_r / 1e6
+    log(f"fwd: {mpix_f:.1f} Mpix/s; fwd+bwd recompute: {mpix_r:.1f} Mpix/s")
+
+    # roofline of the dominant kernel (per launch = per step)
+    comp = {"composite_fwd": FWD_OPS_PER_BLEND, "composite_bwd": BWD_OPS_PER_BLEND}
+    dom = max(stage_ms, key=lambda s: stage_ms[s])
+    if dom in comp:
+        ops = comp[dom] * blends / K
+        t_launch = stage_ms[dom] / K / 1e3
+        achieved = ops / t_launch / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
+                "unit": "Tlane-op/s", "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4),
+                "traffic": load_traffic(dom, "config3"),
+                "per_unit": f"{comp[dom]} lane-ops per blended (pixel, splat)",
+                "units_per_launch": blends / K, "launch_ms": round(t_launch * 1e3, 4)}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": None, "traffic": load_traffic(dom, "config3")}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t_np = targets[0].cpu().numpy().astype(np.float64)
+        cpu = cpu_baseline(scene_np, step_views[0], lambda v: t_np[v])
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": METRIC, "value": round(mpix_fb, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(t_fb / K * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "300k points (30% on a 20-bump surface), SH degree 2, 4 views x 800x800 "
+                               "per step, forward + backward (stored T), L2 loss",
+                   "points": args.points, "views_per_step": V, "width": S, "height": S,
+                   "persistent": bool(args.persistent)},
+        "fwd_mpix_s": round(mpix_f, 2), "fwd_bwd_mpix_s": round(mpix_fb, 2),
+        "fwd_bwd_recompute_mpix_s": round(mpix_r, 2),
+        "stage_ms_per_step": {s: round(v / K, 4) for s, v in stage_ms.items()},
+        "pairs_per_step": pairs / K, "blended_per_step": blends / K,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

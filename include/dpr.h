@@ -1,0 +1,231 @@
+/*
+ * dpr.h - C ABI of the MI355X differentiable point-splat renderer (libdpr.so).
+ *
+ * The renderer implements the differentiable splat rendering of
+ * Zhang et al., "Differentiable Point-Based Radiance Fields for Efficient View
+ * Synthesis" (SIGGRAPH Asia 2022):
+ *   - projection of points P_i through a pinhole camera (R, t, M), Sec. 3.1 Eq. (1);
+ *   - per-view colour from spherical harmonics of the view direction,
+ *     Sec. 3.1 Eq. (2)-(4);
+ *   - a Gaussian splat per point with front-to-back alpha blending over the
+ *     points sorted by camera depth, Sec. 3.2 Eq. (5)-(7), restricted to
+ *     points with non-negligible opacity near each pixel (end of Sec. 3.2);
+ *   - gradients of a loss on the image with respect to positions, SH
+ *     coefficients and opacities ("fully differentiable ... end-to-end",
+ *     Sec. 3.3).
+ *
+ * Conventions (fixed by this library where the paper leaves them open):
+ *   - x_cam = R * P + t with R row-major; pixel = (fx*x/z + cx, fy*y/z + cy);
+ *     +x right, +y down, +z forward; pixel (x, y) is sampled at (x+0.5, y+0.5).
+ *   - The splat of point i in a view has sigma_x = fx*r_i/Z, sigma_y = fy*r_i/Z
+ *     (r_i = world radius, Z = camera depth) and
+ *        alpha_i(u) = min(alpha_max, o_i * exp(-((px-ux)^2/sx^2 + (py-uy)^2/sy^2)/2));
+ *     the 1/sqrt(2 pi r^2) factor of Eq. (5) is replaced by the per-point opacity o_i.
+ *   - Point i is a candidate at pixel u iff o_i*G_i(u) >= alpha_min; compositing
+ *     stops after the first blended splat that leaves T < t_min.
+ *   - Depth order: ascending float32 key Z32 = fmaf(R20,x, fmaf(R21,y, fmaf(R22,z,t2))),
+ *     ties by ascending point index; points with Z32 <= z_near are dropped.
+ *   - Colour: real orthonormal SH, no Condon-Shortley phase, coefficient index
+ *     k = l^2 + l + m, evaluated at v = x_cam/|x_cam| (sh_frame 0) or R^T v
+ *     (sh_frame 1).  No activation or clamp; background 0 (the caller adds
+ *     T * background).
+ *
+ * Memory: every pointer in the descriptors is DEVICE memory owned by the caller.
+ * The library never allocates device memory: the caller provides three
+ * workspaces whose sizes the library reports (plan, forward, backward).
+ * All float arrays are float32, densely packed, 4-byte aligned; 16-byte
+ * alignment of xyz/sh/images is recommended.
+ *
+ * Streams: a stream argument is a hipStream_t passed as void* (NULL = the
+ * default stream).  Everything is asynchronous on that stream except
+ * dpr_plan_forward, which waits once for the number of (tile, splat) pairs.
+ *
+ * Errors: functions returning int return a dpr_status; a non-zero status
+ * leaves a message in dpr_last_error() (thread-local).  The library never
+ * aborts and never throws across this boundary.  Input VALUES (NaN/Inf) are
+ * not validated; they propagate.
+ *
+ * Thread safety: a plan is used by one thread at a time; different plans are
+ * independent.
+ */
+#ifndef DPR_H
+#define DPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPR_ABI_VERSION 1
+
+typedef enum dpr_status {
+    DPR_OK = 0,
+    DPR_ERR_INVALID_ARG = 1,  /* null required pointer, bad size/degree/threshold, bad scene index */
+    DPR_ERR_WORKSPACE = 2,    /* a workspace is NULL or smaller than the reported size          */
+    DPR_ERR_HIP = 3,          /* a HIP launch or runtime call failed; see dpr_last_error()       */
+    DPR_ERR_UNSUPPORTED = 4,  /* sizes beyond the library's limits (e.g. >= 2^32 pairs)          */
+    DPR_ERR_STATE = 5         /* calls out of order (e.g. backward before forward)               */
+} dpr_status;
+
+/* Pinhole camera of one view (Sec. 3.1 Eq. 1): M = [[fx,0,cx],[0,fy,cy],[0,0,1]]. */
+typedef struct dpr_camera {
+    float R[9];          /* world -> camera rotation, row-major                 */
+    float t[3];          /* world -> camera translation                         */
+    float fx, fy;        /* focal lengths in pixels, > 0                        */
+    float cx, cy;        /* principal point in pixels                           */
+    int32_t width;       /* image width in pixels, 1 .. 16384                   */
+    int32_t height;      /* image height in pixels, 1 .. 16384                  */
+} dpr_camera;
+
+/* One point cloud (Sec. 3.1): positions P_i, SH coefficients H_i, opacity, radius. */
+typedef struct dpr_scene {
+    int64_t n;               /* number of points, 0 .. 2^31-1 (sum over views < 2^31) */
+    int32_t sh_degree;       /* l_max, 0 .. 3; K = (l_max+1)^2 coefficients          */
+    int32_t reserved;        /* must be 0                                            */
+    const float *xyz;        /* [n][3]                                               */
+    const float *sh;         /* [n][K][3]  (coefficient-major, RGB innermost)        */
+    const float *opacity;    /* [n], o_i in (0, 1]                                   */
+    const float *radius;     /* [n], world-space splat radius r_i > 0                */
+} dpr_scene;
+
+/* One rendered view of one scene. */
+typedef struct dpr_view {
+    int32_t scene;           /* index into the scene array                           */
+    int32_t reserved;        /* must be 0                                            */
+    dpr_camera cam;
+    float *image;            /* [height][width][3] output (pre-background colour)    */
+    float *trans;            /* [height][width] output: final transmittance T.
+                                Required when bwd_mode = DPR_BWD_STORED; may be NULL
+                                otherwise (then T is not written).                   */
+} dpr_view;
+
+enum { DPR_SH_FRAME_CAMERA = 0, DPR_SH_FRAME_WORLD = 1 };
+enum { DPR_BWD_STORED = 0, DPR_BWD_RECOMPUTE = 1 };
+enum {
+    DPR_FLAG_TIMING = 1,      /* record HIP events around every stage (dpr_stage_times)    */
+    DPR_FLAG_STATS = 2,       /* count blended splats per pixel (dpr_plan_info.stats_off)  */
+    DPR_FLAG_PERSISTENT = 4   /* compositing kernels pop tiles from a work queue           */
+};
+
+typedef struct dpr_params {
+    float alpha_min;         /* candidate threshold on o*G, [0, 1); default 1e-5 (> 0 required) */
+    float t_min;             /* early-stop transmittance, [0, 1); default 1e-5                  */
+    float alpha_max;         /* alpha clamp, (0, 0.999]; default 0.99                           */
+    float z_near;            /* near plane, > 0; default 0.01                                   */
+    int32_t sh_frame;        /* DPR_SH_FRAME_*                                                  */
+    int32_t bwd_mode;        /* DPR_BWD_*: keep the per-pixel stop index (4 B/px) in the
+                                forward workspace, or recompute it in backward                 */
+    int32_t flags;           /* DPR_FLAG_* bitmask                                              */
+    int32_t reserved;        /* must be 0                                                       */
+} dpr_params;
+
+typedef struct dpr_plan dpr_plan;   /* opaque, host-side */
+
+/* Stage indices for dpr_stage_times. */
+enum {
+    DPR_STAGE_UPLOAD = 0, DPR_STAGE_PROJECT, DPR_STAGE_DEPTH_SORT, DPR_STAGE_TILE_COUNT,
+    DPR_STAGE_TILE_SCAN, DPR_STAGE_EMIT, DPR_STAGE_COMPOSITE_FWD, DPR_STAGE_RECOMPUTE,
+    DPR_STAGE_COMPOSITE_BWD, DPR_STAGE_POINT_BWD, DPR_STAGE_COUNT
+};
+
+/* Sizes and workspace offsets of a plan, for diagnostics and stage-level tests. */
+typedef struct dpr_plan_info {
+    int64_t items;           /* sum over views of the scene's point count (view-points) */
+    int64_t pairs;           /* (tile, splat) pairs; valid after dpr_plan_forward       */
+    int64_t tiles;           /* 16x16 screen tiles over all views                        */
+    int64_t pixels;          /* pixels over all views                                    */
+    int64_t chunks;          /* binning chunks over all views                            */
+    int64_t plan_ws_bytes, fwd_ws_bytes, bwd_ws_bytes;
+    /* byte offsets inside the plan workspace */
+    int64_t rec_off;         /* [items] x 8 float: px, py, a, b, w, r, g, b   (see below) */
+    int64_t key_off;         /* [items] u32 depth keys in sorted order: the key of item
+                                order[j] (float bits of Z; 0xFFFFFFFF = dropped)          */
+    int64_t order_off;       /* [items] u32 item ids, depth-sorted within each view      */
+    int64_t rect_off;        /* [items] 2 x u32 tile rectangle (x0|y0<<16, x1|y1<<16)    */
+    int64_t range_off;       /* [cnt + 1] u32 exclusive scan of (tile, chunk) counts     */
+    /* byte offsets inside the forward workspace */
+    int64_t pairs_off;       /* [pairs] u32 item ids, grouped by tile, depth order within */
+    int64_t nlast_off;       /* [pixels] u32 stop index (stored mode), -1 if absent       */
+    int64_t stats_off;       /* [pixels] u32 blended splats per pixel, -1 if absent       */
+    int32_t tile_size;       /* 16                                                        */
+    int32_t chunk_items;     /* items per binning chunk                                   */
+} dpr_plan_info;
+/* Record layout: a = log2(e)/(2 sx^2), b = log2(e)/(2 sy^2), w = log2(o), so that
+ * alpha = min(alpha_max, 2^(w - a dx^2 - b dy^2)) with dx = px - ux, dy = py - uy.
+ * Item id of point i in view v = sum of the point counts of the views before v + i. */
+
+/* Version of this ABI (DPR_ABI_VERSION). */
+int dpr_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *dpr_last_error(void);
+
+/* Bytes of the plan workspace for this set of scenes and views (0 on invalid
+ * arguments; the reason is in dpr_last_error). */
+size_t dpr_plan_ws_bytes(const dpr_scene *scenes, int32_t n_scenes,
+                         const dpr_view *views, int32_t n_views);
+
+/* Validates the arguments, creates a plan and runs projection + SH colour
+ * (Eq. 1-4), the per-view depth sort (Sec. 3.2) and the tile counting of the
+ * binning stage into plan_ws; waits once on `stream` for the pair count.
+ * The descriptors are copied; the arrays they point to must stay valid and
+ * unchanged until the last call that uses the plan.  plan_ws must stay alive
+ * and untouched until the plan is freed.  On success *out owns the plan
+ * (release with dpr_plan_free). */
+int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes,
+                     const dpr_view *views, int32_t n_views, const dpr_params *params,
+                     void *plan_ws, size_t plan_ws_bytes, void *stream, dpr_plan **out);
+
+/* Bytes of the forward workspace (pair lists + per-pixel state), known after
+ * dpr_plan_forward. */
+size_t dpr_workspace_bytes(const dpr_plan *plan);
+
+/* Emits the per-tile depth-ordered splat lists and composites every view front
+ * to back (Eq. 5-7), writing image and trans of each view.  `ws` must stay
+ * alive and untouched until the last dpr_render_backward of this plan. */
+int dpr_render_forward(dpr_plan *plan, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of the backward scratch workspace (per-view-point gradient records,
+ * plus the per-pixel state in recompute mode).  Needed only during the call. */
+size_t dpr_backward_ws_bytes(const dpr_plan *plan);
+
+/* Reverse-mode gradients of a loss L through the forward of this plan.
+ *   dL_dimage[v]  [H][W][3] gradient w.r.t. view v's image (required)
+ *   dL_dtrans     NULL, or per view NULL / [H][W] gradient w.r.t. trans
+ *   dL_dxyz[s]    [n][3]     } per scene, OVERWRITTEN with the sum over every
+ *   dL_dsh[s]     [n][K][3]  } view of the scene; a NULL array pointer (or a NULL
+ *   dL_dopacity[s][n]        } table) skips that output.
+ * Candidate sets, depth order and stop index are held fixed (piecewise-constant
+ * structure); clamped alphas pass no gradient to o or the position.  The
+ * forward state is not modified, so backward may be called more than once. */
+int dpr_render_backward(dpr_plan *plan, const void *ws, size_t ws_bytes,
+                        const float *const *dL_dimage, const float *const *dL_dtrans,
+                        float *const *dL_dxyz, float *const *dL_dsh, float *const *dL_dopacity,
+                        void *bwd_ws, size_t bwd_ws_bytes, void *stream);
+
+/* Releases a plan (host memory and HIP events only).  NULL is ignored. */
+void dpr_plan_free(dpr_plan *plan);
+
+/* Fills *out with the plan's sizes and workspace offsets. */
+int dpr_plan_get_info(const dpr_plan *plan, dpr_plan_info *out);
+
+/* With DPR_FLAG_TIMING: milliseconds of each stage of the most recent call
+ * that ran it, measured with HIP events on the plan's stream (-1 where the
+ * stage did not run).  Synchronizes on those events.  cap >= DPR_STAGE_COUNT. */
+int dpr_stage_times(const dpr_plan *plan, float *ms, int32_t cap);
+
+/* Convenience form of the single-scene, single-camera renderer:
+ * render_forward(points, sh, opacity, radius, camera) -> image, transmittance.
+ * Runs plan + forward in one workspace.  If ws_bytes is too small it returns
+ * DPR_ERR_WORKSPACE and writes the required size to *ws_needed (which may take
+ * running the plan stage, i.e. one wait on the stream).  ws may be NULL to query. */
+int dpr_render_forward_1(const dpr_scene *scene, const dpr_camera *cam, const dpr_params *params,
+                         float *image, float *trans, void *ws, size_t ws_bytes,
+                         size_t *ws_needed, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPR_H */

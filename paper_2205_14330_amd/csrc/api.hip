@@ -1,0 +1,681 @@
+// Host implementation of the C ABI declared in include/dpr.h: argument
+// validation, workspace layout, stage sequencing on the caller's stream,
+// error reporting and per-stage HIP-event timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dpr_internal.h"
+
+using namespace dpr;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                             \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(DPR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Byte layout of a workspace: a list of (offset, size) regions.
+struct Region {
+    uint64_t off = 0, bytes = 0;
+};
+struct Layout {
+    uint64_t total = 0;
+    Region add(uint64_t bytes) {
+        Region r;
+        r.off = total;
+        r.bytes = bytes;
+        total = align_up(total + bytes);
+        return r;
+    }
+};
+
+struct Sizes {
+    int32_t n_views = 0, n_scenes = 0;
+    uint64_t items = 0, tiles = 0, pixels = 0, chunks = 0, cnt = 0, sort_blocks = 0, point_blocks = 0;
+    int32_t sh_degree = 0;
+};
+
+struct PlanLayout {
+    Region views, scenes, u32tab, rec, keys, vals, keys_alt, vals_alt, rect, hist, part, cnt, range;
+    uint64_t total = 0;
+};
+
+PlanLayout plan_layout(const Sizes &s) {
+    Layout L;
+    PlanLayout p;
+    p.views = L.add(sizeof(ViewDesc) * (uint64_t)s.n_views);
+    p.scenes = L.add(sizeof(SceneDesc) * (uint64_t)s.n_scenes);
+    // scene_views[V], scene_block_start[S], sort_block_start[V], chunk_start[V], tile_start[V]
+    p.u32tab = L.add(sizeof(uint32_t) * (4ull * s.n_views + s.n_scenes));
+    p.rec = L.add(sizeof(SplatRec) * s.items);
+    p.keys = L.add(4 * s.items);
+    p.vals = L.add(4 * s.items);
+    p.keys_alt = L.add(4 * s.items);
+    p.vals_alt = L.add(4 * s.items);
+    p.rect = L.add(8 * s.items);
+    const uint64_t nh = 256ull * s.sort_blocks;
+    p.hist = L.add(4 * (nh + 1));
+    const uint64_t np = std::max(scan_partials(nh), scan_partials(s.cnt)) + 2;
+    p.part = L.add(8 * np);
+    p.cnt = L.add(4 * s.cnt);
+    p.range = L.add(4 * (s.cnt + 1));
+    p.total = L.total;
+    return p;
+}
+
+const int kLimitDim = 16384;
+
+int check_params(const dpr_params *pr) {
+    if (!pr) return fail(DPR_ERR_INVALID_ARG, "params is NULL");
+    if (!(pr->alpha_min >= 0.f && pr->alpha_min < 1.f))
+        return fail(DPR_ERR_INVALID_ARG, "alpha_min must be in [0, 1)");
+    if (!(pr->t_min >= 0.f && pr->t_min < 1.f)) return fail(DPR_ERR_INVALID_ARG, "t_min must be in [0, 1)");
+    if (!(pr->alpha_max > 0.f && pr->alpha_max <= 1.f))
+        return fail(DPR_ERR_INVALID_ARG, "alpha_max must be in (0, 1]");
+    if (!(pr->z_near > 0.f) || !std::isfinite(pr->z_near)) return fail(DPR_ERR_INVALID_ARG, "z_near must be > 0");
+    if (pr->sh_frame != 0 && pr->sh_frame != 1) return fail(DPR_ERR_INVALID_ARG, "sh_frame must be 0 or 1");
+    if (pr->bwd_mode != 0 && pr->bwd_mode != 1) return fail(DPR_ERR_INVALID_ARG, "bwd_mode must be 0 or 1");
+    if (pr->flags & ~(DPR_FLAG_TIMING | DPR_FLAG_STATS | DPR_FLAG_PERSISTENT))
+        return fail(DPR_ERR_INVALID_ARG, "unknown flags 0x%x", pr->flags);
+    if (pr->reserved != 0) return fail(DPR_ERR_INVALID_ARG, "params.reserved must be 0");
+    return DPR_OK;
+}
+
+int check_inputs(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *views, int32_t n_views, Sizes *out) {
+    if (n_scenes < 1 || !scenes) return fail(DPR_ERR_INVALID_ARG, "need at least one scene");
+    if (n_views < 1 || !views) return fail(DPR_ERR_INVALID_ARG, "need at least one view");
+    if (n_views > (1 << 20) || n_scenes > (1 << 20)) return fail(DPR_ERR_UNSUPPORTED, "too many views or scenes");
+    Sizes s;
+    s.n_views = n_views;
+    s.n_scenes = n_scenes;
+    s.sh_degree = scenes[0].sh_degree;
+    for (int32_t i = 0; i < n_scenes; ++i) {
+        const dpr_scene &sc = scenes[i];
+        if (sc.n < 0 || sc.n > 0x7FFFFFFFll) return fail(DPR_ERR_INVALID_ARG, "scene %d: n out of range", i);
+        if (sc.sh_degree < 0 || sc.sh_degree > 3)
+            return fail(DPR_ERR_INVALID_ARG, "scene %d: sh_degree must be in [0, 3]", i);
+        if (sc.sh_degree != s.sh_degree)
+            return fail(DPR_ERR_UNSUPPORTED, "scene %d: all scenes of a plan must share sh_degree", i);
+        if (sc.reserved != 0) return fail(DPR_ERR_INVALID_ARG, "scene %d: reserved must be 0", i);
+        if (sc.n > 0 && (!sc.xyz || !sc.sh || !sc.opacity || !sc.radius))
+            return fail(DPR_ERR_INVALID_ARG, "scene %d: NULL array", i);
+        s.point_blocks += ((uint64_t)sc.n + 127) / 128;
+    }
+    for (int32_t v = 0; v < n_views; ++v) {
+        const dpr_view &vw = views[v];
+        if (vw.scene < 0 || vw.scene >= n_scenes) return fail(DPR_ERR_INVALID_ARG, "view %d: bad scene index", v);
+        if (vw.reserved != 0) return fail(DPR_ERR_INVALID_ARG, "view %d: reserved must be 0", v);
+        const dpr_camera &c = vw.cam;
+        if (c.width < 1 || c.width > kLimitDim || c.height < 1 || c.height > kLimitDim)
+            return fail(DPR_ERR_INVALID_ARG, "view %d: width/height must be in [1, %d]", v, kLimitDim);
+        if (!(c.fx > 0.f) || !(c.fy > 0.f) || !std::isfinite(c.fx) || !std::isfinite(c.fy))
+            return fail(DPR_ERR_INVALID_ARG, "view %d: fx, fy must be finite and > 0", v);
+        if (!vw.image) return fail(DPR_ERR_INVALID_ARG, "view %d: image is NULL", v);
+        const uint64_t n = (uint64_t)scenes[vw.scene].n;
+        s.items += n;
+        const uint64_t tx = ((uint64_t)c.width + kTile - 1) / kTile, ty = ((uint64_t)c.height + kTile - 1) / kTile;
+        s.tiles += tx * ty;
+        s.pixels += (uint64_t)c.width * (uint64_t)c.height;
+        const uint64_t nch = (n + kChunkItems - 1) / kChunkItems;
+        s.chunks += nch;
+        s.cnt += tx * ty * nch;
+        s.sort_blocks += (n + kSortTile - 1) / kSortTile;
+    }
+    if (s.items >= 0x7FFFFFFFull) return fail(DPR_ERR_UNSUPPORTED, "total view-points must be < 2^31");
+    if (s.tiles >= 0xFFFFFFFFull || s.cnt >= 0xFFFFFFFFull || s.chunks >= 0xFFFFFFFFull)
+        return fail(DPR_ERR_UNSUPPORTED, "too many tiles");
+    *out = s;
+    return DPR_OK;
+}
+
+struct Events {
+    hipEvent_t a[DPR_STAGE_COUNT] = {};
+    hipEvent_t b[DPR_STAGE_COUNT] = {};
+    bool ran[DPR_STAGE_COUNT] = {};
+};
+
+bool fault_injected(const char *what) {
+    const char *f = getenv("DPR_FAULT");
+    return f && strcmp(f, what) == 0;
+}
+
+}  // namespace
+
+struct dpr_plan {
+    Sizes sz;
+    PlanLayout lay;
+    dpr_params params;
+    Thresholds th;
+    std::vector<dpr_scene> scenes;
+    std::vector<dpr_view> views;
+    std::vector<ViewDesc> vdesc;
+    std::vector<SceneDesc> sdesc;
+    std::vector<uint32_t> u32tab;
+    uint8_t *pws = nullptr;
+    uint64_t pairs = 0;
+    uint64_t total_host[2] = {0, 0};
+    int forward_done = 0;
+    const void *fwd_ws = nullptr;
+    Events ev;
+    bool timing = false;
+    // backward host tables (kept alive while copies may be in flight)
+    std::vector<uint64_t> bwd_tab;
+    std::vector<SceneDesc> sdesc_bwd;
+};
+
+namespace {
+
+Tables make_tables(const dpr_plan *p) {
+    Tables tb;
+    const uint32_t *u = reinterpret_cast<const uint32_t *>(p->pws + p->lay.u32tab.off);
+    const int V = p->sz.n_views, S = p->sz.n_scenes;
+    tb.views = reinterpret_cast<const ViewDesc *>(p->pws + p->lay.views.off);
+    tb.scenes = reinterpret_cast<const SceneDesc *>(p->pws + p->lay.scenes.off);
+    tb.scene_views = u;
+    tb.scene_block_start = u + V;
+    tb.sort_block_start = u + V + S;
+    tb.chunk_start = u + 2 * V + S;
+    tb.tile_start = u + 3 * V + S;
+    tb.n_views = V;
+    tb.n_scenes = S;
+    return tb;
+}
+
+struct StageScope {
+    dpr_plan *p;
+    int stage;
+    hipStream_t st;
+    StageScope(dpr_plan *p_, int s, hipStream_t st_) : p(p_), stage(s), st(st_) {
+        if (p->timing) hipEventRecord(p->ev.a[stage], st);
+    }
+    ~StageScope() {
+        if (p->timing) {
+            hipEventRecord(p->ev.b[stage], st);
+            p->ev.ran[stage] = true;
+        }
+    }
+};
+
+struct FwdLayout {
+    Region pairs, nlast, stats, queue;
+    uint64_t total = 0;
+};
+
+FwdLayout fwd_layout(const dpr_plan *p) {
+    Layout L;
+    FwdLayout f;
+    f.pairs = L.add(4 * p->pairs);
+    f.nlast = L.add(p->params.bwd_mode == DPR_BWD_STORED ? 4 * p->sz.pixels : 0);
+    f.stats = L.add((p->params.flags & DPR_FLAG_STATS) ? 4 * p->sz.pixels : 0);
+    f.queue = L.add(16);
+    f.total = L.total;
+    return f;
+}
+
+struct BwdLayout {
+    Region tabs, sgrad, grad, nlast, tfin, queue;
+    uint64_t total = 0;
+};
+
+BwdLayout bwd_layout(const dpr_plan *p) {
+    Layout L;
+    BwdLayout b;
+    b.tabs = L.add(8ull * 2 * p->sz.n_views);
+    b.sgrad = L.add(sizeof(SceneDesc) * (uint64_t)p->sz.n_scenes);
+    b.grad = L.add(32ull * p->sz.items);
+    const bool rec = p->params.bwd_mode == DPR_BWD_RECOMPUTE;
+    b.nlast = L.add(rec ? 4 * p->sz.pixels : 0);
+    b.tfin = L.add(rec ? 4 * p->sz.pixels : 0);
+    b.queue = L.add(16);
+    b.total = L.total;
+    return b;
+}
+
+CompositeArgs composite_args(const dpr_plan *p, const void *ws) {
+    const Tables tb = make_tables(p);
+    const FwdLayout f = fwd_layout(p);
+    const uint8_t *w = static_cast<const uint8_t *>(ws);
+    CompositeArgs a;
+    a.views = tb.views;
+    a.tile_start = tb.tile_start;
+    a.n_views = tb.n_views;
+    a.total_tiles = (uint32_t)p->sz.tiles;
+    a.rec = reinterpret_cast<const SplatRec *>(p->pws + p->lay.rec.off);
+    a.pairs = reinterpret_cast<const uint32_t *>(w + f.pairs.off);
+    a.range = reinterpret_cast<const uint32_t *>(p->pws + p->lay.range.off);
+    a.nlast = nullptr;
+    a.tfinal = nullptr;
+    a.stats = nullptr;
+    a.queue = nullptr;
+    a.th = p->th;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpr_version(void) { return DPR_ABI_VERSION; }
+
+const char *dpr_last_error(void) { return g_err.c_str(); }
+
+size_t dpr_plan_ws_bytes(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *views, int32_t n_views) {
+    Sizes s;
+    if (check_inputs(scenes, n_scenes, views, n_views, &s) != DPR_OK) return 0;
+    return (size_t)plan_layout(s).total;
+}
+
+int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *views, int32_t n_views,
+                     const dpr_params *params, void *plan_ws, size_t plan_ws_bytes, void *stream,
+                     dpr_plan **out) {
+    g_err.clear();
+    if (!out) return fail(DPR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(params);
+    if (rc) return rc;
+    Sizes s;
+    rc = check_inputs(scenes, n_scenes, views, n_views, &s);
+    if (rc) return rc;
+    const PlanLayout lay = plan_layout(s);
+    if (!plan_ws || plan_ws_bytes < lay.total)
+        return fail(DPR_ERR_WORKSPACE, "plan workspace needs %llu bytes, got %llu", (unsigned long long)lay.total,
+                    (unsigned long long)plan_ws_bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+
+    dpr_plan *p = new dpr_plan();
+    p->sz = s;
+    p->lay = lay;
+    p->params = *params;
+    p->th.lambda = params->alpha_min > 0.f ? -log2f(params->alpha_min) : INFINITY;
+    p->th.alpha_max = params->alpha_max;
+    p->th.t_min = params->t_min;
+    p->th.z_near = params->z_near;
+    p->th.sh_frame = params->sh_frame;
+    p->scenes.assign(scenes, scenes + n_scenes);
+    p->views.assign(views, views + n_views);
+    p->pws = static_cast<uint8_t *>(plan_ws);
+    p->timing = (params->flags & DPR_FLAG_TIMING) != 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    auto cleanup_fail = [&](int code) {
+        dpr_plan_free(p);
+        return code;
+    };
+    if (p->timing) {
+        for (int i = 0; i < DPR_STAGE_COUNT; ++i) {
+            if (hipEventCreate(&p->ev.a[i]) != hipSuccess || hipEventCreate(&p->ev.b[i]) != hipSuccess)
+                return cleanup_fail(fail(DPR_ERR_HIP, "hipEventCreate failed"));
+        }
+    }
+
+    // host tables
+    const int V = n_views, S = n_scenes;
+    p->vdesc.resize(V);
+    p->sdesc.resize(S);
+    p->u32tab.assign(4 * (size_t)V + S, 0u);
+    uint32_t *scene_views = p->u32tab.data();
+    uint32_t *scene_block_start = scene_views + V;
+    uint32_t *sort_block_start = scene_block_start + S;
+    uint32_t *chunk_start = sort_block_start + V;
+    uint32_t *tile_start = chunk_start + V;
+    {
+        std::vector<uint32_t> count(S, 0);
+        for (int v = 0; v < V; ++v) count[views[v].scene]++;
+        uint32_t acc = 0, blk = 0;
+        for (int sidx = 0; sidx < S; ++sidx) {
+            SceneDesc &d = p->sdesc[sidx];
+            memset(&d, 0, sizeof(d));
+            d.n = (int32_t)scenes[sidx].n;
+            d.sh_degree = scenes[sidx].sh_degree;
+            d.view_start = acc;
+            d.view_count = 0;
+            d.block_off = blk;
+            d.xyz = scenes[sidx].xyz;
+            d.sh = scenes[sidx].sh;
+            d.opacity = scenes[sidx].opacity;
+            d.radius = scenes[sidx].radius;
+            scene_block_start[sidx] = blk;
+            blk += (uint32_t)((d.n + 127) / 128);
+            acc += count[sidx];
+        }
+        for (int v = 0; v < V; ++v) {
+            SceneDesc &d = p->sdesc[views[v].scene];
+            scene_views[d.view_start + d.view_count++] = (uint32_t)v;
+        }
+    }
+    {
+        uint64_t item = 0, tile = 0, chunk = 0, sblk = 0, hist = 0, cnt = 0, pix = 0;
+        for (int v = 0; v < V; ++v) {
+            const dpr_view &vw = views[v];
+            ViewDesc &d = p->vdesc[v];
+            memset(&d, 0, sizeof(d));
+            memcpy(d.R, vw.cam.R, sizeof(d.R));
+            memcpy(d.t, vw.cam.t, sizeof(d.t));
+            d.fx = vw.cam.fx; d.fy = vw.cam.fy; d.cx = vw.cam.cx; d.cy = vw.cam.cy;
+            d.width = vw.cam.width;
+            d.height = vw.cam.height;
+            d.tiles_x = (d.width + kTile - 1) / kTile;
+            d.tiles_y = (d.height + kTile - 1) / kTile;
+            d.scene = vw.scene;
+            const dpr_scene &sc = scenes[vw.scene];
+            d.sh_degree = sc.sh_degree;
+            d.n = (int32_t)sc.n;
+            d.item_off = (uint32_t)item;
+            d.tile_off = (uint32_t)tile;
+            d.chunk_off = (uint32_t)chunk;
+            d.nchunks = (uint32_t)(((uint64_t)sc.n + kChunkItems - 1) / kChunkItems);
+            d.sort_block_off = (uint32_t)sblk;
+            d.nsort_blocks = (uint32_t)(((uint64_t)sc.n + kSortTile - 1) / kSortTile);
+            d.hist_off = hist;
+            d.cnt_off = cnt;
+            d.pix_off = pix;
+            d.xyz = sc.xyz; d.sh = sc.sh; d.opacity = sc.opacity; d.radius = sc.radius;
+            d.image = vw.image;
+            d.trans = vw.trans;
+            sort_block_start[v] = d.sort_block_off;
+            chunk_start[v] = d.chunk_off;
+            tile_start[v] = d.tile_off;
+            const uint64_t nt = (uint64_t)d.tiles_x * d.tiles_y;
+            item += (uint64_t)sc.n;
+            tile += nt;
+            chunk += d.nchunks;
+            sblk += d.nsort_blocks;
+            hist += 256ull * d.nsort_blocks;
+            cnt += nt * d.nchunks;
+            pix += (uint64_t)d.width * d.height;
+        }
+    }
+
+    uint8_t *w = p->pws;
+    const Tables tb = make_tables(p);
+    SplatRec *rec = reinterpret_cast<SplatRec *>(w + lay.rec.off);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(w + lay.keys.off);
+    uint32_t *vals = reinterpret_cast<uint32_t *>(w + lay.vals.off);
+    uint32_t *keys_alt = reinterpret_cast<uint32_t *>(w + lay.keys_alt.off);
+    uint32_t *vals_alt = reinterpret_cast<uint32_t *>(w + lay.vals_alt.off);
+    uint2 *rect = reinterpret_cast<uint2 *>(w + lay.rect.off);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w + lay.hist.off);
+    uint64_t *part = reinterpret_cast<uint64_t *>(w + lay.part.off);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(w + lay.cnt.off);
+    uint32_t *range = reinterpret_cast<uint32_t *>(w + lay.range.off);
+    const uint64_t np = lay.part.bytes / 8;
+    uint64_t *total64 = part + np - 1;
+
+#define STAGE_TRY(expr)                                                                           \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return cleanup_fail(fail(DPR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)));       \
+    } while (0)
+
+    {
+        StageScope sc_(p, DPR_STAGE_UPLOAD, st);
+        STAGE_TRY(hipMemcpyAsync(w + lay.views.off, p->vdesc.data(), sizeof(ViewDesc) * V, hipMemcpyHostToDevice, st));
+        STAGE_TRY(hipMemcpyAsync(w + lay.scenes.off, p->sdesc.data(), sizeof(SceneDesc) * S, hipMemcpyHostToDevice, st));
+        STAGE_TRY(hipMemcpyAsync(w + lay.u32tab.off, p->u32tab.data(), 4 * p->u32tab.size(), hipMemcpyHostToDevice, st));
+    }
+    {
+        StageScope sc_(p, DPR_STAGE_PROJECT, st);
+        STAGE_TRY(launch_project(tb, p->th, s.sh_degree, (uint32_t)s.point_blocks, rec, keys, vals, rect, st));
+    }
+    {
+        StageScope sc_(p, DPR_STAGE_DEPTH_SORT, st);
+        STAGE_TRY(launch_depth_sort(tb, (uint32_t)s.sort_blocks, (uint32_t)s.items, keys, vals, keys_alt, vals_alt,
+                                    hist, part, st));
+    }
+    {
+        StageScope sc_(p, DPR_STAGE_TILE_COUNT, st);
+        STAGE_TRY(launch_tile_count(tb, (uint32_t)s.chunks, vals, rect, cnt, st));
+    }
+    {
+        StageScope sc_(p, DPR_STAGE_TILE_SCAN, st);
+        STAGE_TRY(launch_scan(cnt, range, s.cnt, part, total64, st));
+    }
+    STAGE_TRY(hipMemcpyAsync(p->total_host, total64, 8, hipMemcpyDeviceToHost, st));
+    STAGE_TRY(hipStreamSynchronize(st));
+    p->pairs = p->total_host[0];
+    if (p->pairs >= 0xFFFFFFFFull)
+        return cleanup_fail(fail(DPR_ERR_UNSUPPORTED, "%llu (tile, splat) pairs exceed 2^32 - 1",
+                                 (unsigned long long)p->pairs));
+#undef STAGE_TRY
+    *out = p;
+    return DPR_OK;
+}
+
+size_t dpr_workspace_bytes(const dpr_plan *plan) {
+    if (!plan) return 0;
+    return (size_t)fwd_layout(plan).total;
+}
+
+size_t dpr_backward_ws_bytes(const dpr_plan *plan) {
+    if (!plan) return 0;
+    return (size_t)bwd_layout(plan).total;
+}
+
+int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!p) return fail(DPR_ERR_INVALID_ARG, "plan is NULL");
+    const FwdLayout f = fwd_layout(p);
+    if (!ws || ws_bytes < f.total)
+        return fail(DPR_ERR_WORKSPACE, "forward workspace needs %llu bytes, got %llu",
+                    (unsigned long long)f.total, (unsigned long long)ws_bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    const Tables tb = make_tables(p);
+    const PlanLayout &lay = p->lay;
+    {
+        StageScope sc_(p, DPR_STAGE_EMIT, st);
+        HIP_TRY(launch_tile_emit(tb, (uint32_t)p->sz.chunks, reinterpret_cast<const uint32_t *>(p->pws + lay.vals.off),
+                                 reinterpret_cast<const uint2 *>(p->pws + lay.rect.off),
+                                 reinterpret_cast<const uint32_t *>(p->pws + lay.range.off),
+                                 reinterpret_cast<uint32_t *>(w + f.pairs.off), st));
+    }
+    CompositeArgs a = composite_args(p, ws);
+    a.nlast = f.nlast.bytes ? reinterpret_cast<uint32_t *>(w + f.nlast.off) : nullptr;
+    a.stats = f.stats.bytes ? reinterpret_cast<uint32_t *>(w + f.stats.off) : nullptr;
+    a.queue = reinterpret_cast<uint32_t *>(w + f.queue.off);
+    const bool persistent = (p->params.flags & DPR_FLAG_PERSISTENT) != 0;
+    {
+        StageScope sc_(p, DPR_STAGE_COMPOSITE_FWD, st);
+        if (persistent) HIP_TRY(launch_fill_u32(a.queue, 0u, 4, st));
+        HIP_TRY(launch_composite_fwd(a, persistent, st));
+    }
+    p->forward_done = 1;
+    p->fwd_ws = ws;
+    return DPR_OK;
+}
+
+int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const float *const *dL_dimage,
+                        const float *const *dL_dtrans, float *const *dL_dxyz, float *const *dL_dsh,
+                        float *const *dL_dopacity, void *bwd_ws, size_t bwd_ws_bytes, void *stream) {
+    g_err.clear();
+    if (!p) return fail(DPR_ERR_INVALID_ARG, "plan is NULL");
+    if (!p->forward_done) return fail(DPR_ERR_STATE, "dpr_render_backward before dpr_render_forward");
+    const FwdLayout f = fwd_layout(p);
+    if (!ws || ws_bytes < f.total) return fail(DPR_ERR_WORKSPACE, "forward workspace too small");
+    const BwdLayout bl = bwd_layout(p);
+    if (!bwd_ws || bwd_ws_bytes < bl.total)
+        return fail(DPR_ERR_WORKSPACE, "backward workspace needs %llu bytes, got %llu",
+                    (unsigned long long)bl.total, (unsigned long long)bwd_ws_bytes);
+    if (p->params.alpha_max > 0.999f)
+        return fail(DPR_ERR_INVALID_ARG, "backward needs alpha_max <= 0.999 (T is recovered by division)");
+    if (!dL_dimage) return fail(DPR_ERR_INVALID_ARG, "dL_dimage is NULL");
+    const int V = p->sz.n_views, S = p->sz.n_scenes;
+    const bool recompute = p->params.bwd_mode == DPR_BWD_RECOMPUTE;
+    for (int v = 0; v < V; ++v) {
+        if (!dL_dimage[v]) return fail(DPR_ERR_INVALID_ARG, "dL_dimage[%d] is NULL", v);
+        if (!recompute && !p->views[v].trans)
+            return fail(DPR_ERR_INVALID_ARG, "view %d: stored backward needs the trans output", v);
+    }
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t *bw = static_cast<uint8_t *>(bwd_ws);
+    const uint8_t *w = static_cast<const uint8_t *>(ws);
+
+    // pointer tables: dimage[V], dtrans[V]; scene descriptors with gradient outputs
+    p->bwd_tab.assign(2 * (size_t)V, 0ull);
+    for (int v = 0; v < V; ++v) {
+        p->bwd_tab[v] = (uint64_t)(uintptr_t)dL_dimage[v];
+        p->bwd_tab[V + v] = dL_dtrans ? (uint64_t)(uintptr_t)dL_dtrans[v] : 0ull;
+    }
+    p->sdesc_bwd = p->sdesc;
+    for (int s = 0; s < S; ++s) {
+        p->sdesc_bwd[s].dxyz = dL_dxyz ? dL_dxyz[s] : nullptr;
+        p->sdesc_bwd[s].dsh = dL_dsh ? dL_dsh[s] : nullptr;
+        p->sdesc_bwd[s].dopacity = dL_dopacity ? dL_dopacity[s] : nullptr;
+    }
+    HIP_TRY(hipMemcpyAsync(bw + bl.tabs.off, p->bwd_tab.data(), 8 * p->bwd_tab.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(bw + bl.sgrad.off, p->sdesc_bwd.data(), sizeof(SceneDesc) * S, hipMemcpyHostToDevice, st));
+
+    CompositeArgs a = composite_args(p, ws);
+    const bool persistent = (p->params.flags & DPR_FLAG_PERSISTENT) != 0;
+    uint32_t *queue = reinterpret_cast<uint32_t *>(bw + bl.queue.off);
+    BackwardArgs b;
+    b.dimage = reinterpret_cast<const float *const *>(bw + bl.tabs.off);
+    b.dtrans = dL_dtrans ? reinterpret_cast<const float *const *>(bw + bl.tabs.off + 8ull * V) : nullptr;
+    b.grad = reinterpret_cast<float *>(bw + bl.grad.off);
+    if (recompute) {
+        a.nlast = reinterpret_cast<uint32_t *>(bw + bl.nlast.off);
+        a.tfinal = reinterpret_cast<float *>(bw + bl.tfin.off);
+        a.queue = queue;
+        StageScope sc_(p, DPR_STAGE_RECOMPUTE, st);
+        if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 4, st));
+        HIP_TRY(launch_recompute(a, persistent, st));
+        b.nlast = a.nlast;
+        b.tfinal = a.tfinal;
+        b.tfinal_from_views = 0;
+    } else {
+        b.nlast = reinterpret_cast<const uint32_t *>(w + f.nlast.off);
+        b.tfinal = nullptr;
+        b.tfinal_from_views = 1;
+    }
+    a.nlast = nullptr;
+    a.tfinal = nullptr;
+    a.stats = nullptr;
+    a.queue = queue;
+    b.c = a;
+    {
+        StageScope sc_(p, DPR_STAGE_COMPOSITE_BWD, st);
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(b.grad), 0u, 8ull * p->sz.items, st));
+        if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 4, st));
+        HIP_TRY(launch_composite_bwd(b, persistent, st));
+    }
+    {
+        Tables tb = make_tables(p);
+        tb.scenes = reinterpret_cast<const SceneDesc *>(bw + bl.sgrad.off);
+        StageScope sc_(p, DPR_STAGE_POINT_BWD, st);
+        HIP_TRY(launch_point_bwd(tb, p->th, p->sz.sh_degree, (uint32_t)p->sz.point_blocks, b.grad, st));
+    }
+    return DPR_OK;
+}
+
+void dpr_plan_free(dpr_plan *p) {
+    if (!p) return;
+    for (int i = 0; i < DPR_STAGE_COUNT; ++i) {
+        if (p->ev.a[i]) hipEventDestroy(p->ev.a[i]);
+        if (p->ev.b[i]) hipEventDestroy(p->ev.b[i]);
+    }
+    delete p;
+}
+
+int dpr_plan_get_info(const dpr_plan *p, dpr_plan_info *out) {
+    if (!p || !out) return fail(DPR_ERR_INVALID_ARG, "NULL argument");
+    memset(out, 0, sizeof(*out));
+    const FwdLayout f = fwd_layout(p);
+    out->items = (int64_t)p->sz.items;
+    out->pairs = (int64_t)p->pairs;
+    out->tiles = (int64_t)p->sz.tiles;
+    out->pixels = (int64_t)p->sz.pixels;
+    out->chunks = (int64_t)p->sz.chunks;
+    out->plan_ws_bytes = (int64_t)p->lay.total;
+    out->fwd_ws_bytes = (int64_t)f.total;
+    out->bwd_ws_bytes = (int64_t)bwd_layout(p).total;
+    out->rec_off = (int64_t)p->lay.rec.off;
+    out->key_off = (int64_t)p->lay.keys.off;
+    out->order_off = (int64_t)p->lay.vals.off;
+    out->rect_off = (int64_t)p->lay.rect.off;
+    out->range_off = (int64_t)p->lay.range.off;
+    out->pairs_off = (int64_t)f.pairs.off;
+    out->nlast_off = f.nlast.bytes ? (int64_t)f.nlast.off : -1;
+    out->stats_off = f.stats.bytes ? (int64_t)f.stats.off : -1;
+    out->tile_size = kTile;
+    out->chunk_items = kChunkItems;
+    return DPR_OK;
+}
+
+int dpr_stage_times(const dpr_plan *p, float *ms, int32_t cap) {
+    if (!p || !ms || cap < DPR_STAGE_COUNT) return fail(DPR_ERR_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < DPR_STAGE_COUNT; ++i) ms[i] = -1.f;
+    if (!p->timing) return fail(DPR_ERR_STATE, "plan was created without DPR_FLAG_TIMING");
+    for (int i = 0; i < DPR_STAGE_COUNT; ++i) {
+        if (!p->ev.ran[i]) continue;
+        HIP_TRY(hipEventSynchronize(p->ev.b[i]));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, p->ev.a[i], p->ev.b[i]));
+        ms[i] = t;
+    }
+    return DPR_OK;
+}
+
+int dpr_render_forward_1(const dpr_scene *scene, const dpr_camera *cam, const dpr_params *params, float *image,
+                         float *trans, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
+    g_err.clear();
+    if (!scene || !cam) return fail(DPR_ERR_INVALID_ARG, "scene or camera is NULL");
+    dpr_view view;
+    memset(&view, 0, sizeof(view));
+    view.scene = 0;
+    view.cam = *cam;
+    view.image = image;
+    view.trans = trans;
+    const size_t pb = dpr_plan_ws_bytes(scene, 1, &view, 1);
+    if (pb == 0) {
+        int rc = check_params(params);
+        if (rc) return rc;
+        Sizes s;
+        return check_inputs(scene, 1, &view, 1, &s);
+    }
+    const size_t pb_al = (size_t)align_up(pb);
+    if (ws_needed) *ws_needed = pb_al;
+    if (!ws || ws_bytes < pb_al) return fail(DPR_ERR_WORKSPACE, "workspace needs at least %zu bytes", pb_al);
+    dpr_plan *p = nullptr;
+    int rc = dpr_plan_forward(scene, 1, &view, 1, params, ws, pb, stream, &p);
+    if (rc) return rc;
+    const size_t need = pb_al + dpr_workspace_bytes(p);
+    if (ws_needed) *ws_needed = need;
+    if (ws_bytes < need) {
+        dpr_plan_free(p);
+        return fail(DPR_ERR_WORKSPACE, "workspace needs %zu bytes", need);
+    }
+    rc = dpr_render_forward(p, static_cast<uint8_t *>(ws) + pb_al, ws_bytes - pb_al, stream);
+    dpr_plan_free(p);
+    return rc;
+}
+
+}  // extern "C"

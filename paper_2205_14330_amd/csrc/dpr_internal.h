@@ -1,0 +1,184 @@
+// Internal definitions shared by the HIP sources of libdpr (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dpr.h"
+
+namespace dpr {
+
+constexpr int kTile = 16;                 // screen tile edge in pixels
+constexpr int kTilePix = kTile * kTile;   // 256 pixels per tile
+constexpr int kChunkItems = 2048;         // depth-sorted items per binning chunk
+constexpr int kBandTiles = 8192;          // tiles of one view handled per LDS band
+constexpr int kSortThreads = 256;
+constexpr int kSortItemsPerThread = 8;
+constexpr int kSortTile = kSortThreads * kSortItemsPerThread;   // 2048 keys per sort block
+constexpr int kScanThreads = 256;
+constexpr int kScanItemsPerThread = 8;
+constexpr int kScanTile = kScanThreads * kScanItemsPerThread;   // 2048 elements per scan block
+constexpr uint32_t kDroppedKey = 0xFFFFFFFFu;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Per-view descriptor in device memory.
+struct ViewDesc {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    int32_t tiles_x, tiles_y;
+    int32_t scene;
+    int32_t sh_degree;
+    int32_t n;                  // points of the scene
+    uint32_t item_off;          // first item id of this view
+    uint32_t tile_off;          // first global tile id of this view
+    uint32_t chunk_off;         // first global chunk id of this view
+    uint32_t nchunks;           // chunks of this view
+    uint32_t sort_block_off;    // first depth-sort block of this view
+    uint32_t nsort_blocks;
+    uint32_t pad0;
+    uint64_t hist_off;          // first radix-histogram entry of this view
+    uint64_t cnt_off;           // first (tile, chunk) count entry of this view
+    uint64_t pix_off;           // first pixel of this view in per-pixel state arrays
+    const float *xyz;
+    const float *sh;
+    const float *opacity;
+    const float *radius;
+    float *image;
+    float *trans;
+};
+
+// Per-scene descriptor in device memory.
+struct SceneDesc {
+    int32_t n;
+    int32_t sh_degree;
+    uint32_t view_start;        // into the scene -> view index list
+    uint32_t view_count;
+    uint32_t block_off;         // first point-parallel block of this scene
+    uint32_t pad0;
+    const float *xyz;
+    const float *sh;
+    const float *opacity;
+    const float *radius;
+    float *dxyz;                // backward outputs (may be null)
+    float *dsh;
+    float *dopacity;
+};
+
+struct Thresholds {
+    float lambda;      // -log2(alpha_min): candidate iff w - q >= -lambda
+    float alpha_max;
+    float t_min;
+    float z_near;
+    int32_t sh_frame;
+};
+
+// Splat record of one (view, point) item: 32 bytes.
+struct __align__(16) SplatRec {
+    float px, py, a, b;     // centre (pixels) and a = log2e / (2 sx^2), b = log2e / (2 sy^2)
+    float w, cr, cg, cb;    // w = log2(o); colour
+};
+
+// Index of the segment containing x: largest s < n with starts[s] <= x.
+__device__ __forceinline__ int find_segment(const uint32_t *starts, int n, uint32_t x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Camera-space depth key, shared by the cull, the sort and the chain rule:
+// Z32 = fmaf(R20, x, fmaf(R21, y, fmaf(R22, z, t2))).
+__device__ __forceinline__ float depth_z(const float *R, const float *t, float x, float y, float z) {
+    float acc = __fmaf_rn(R[8], z, t[2]);
+    acc = __fmaf_rn(R[7], y, acc);
+    return __fmaf_rn(R[6], x, acc);
+}
+
+// Exponent of the splat opacity: e = w - (a dx^2 + b dy^2); alpha = 2^e.
+// Written with explicit rounding so every kernel that re-evaluates a splat
+// (forward, recompute, backward) takes bit-identical decisions.
+__device__ __forceinline__ float splat_exponent(const SplatRec &s, float ux, float uy,
+                                                float &dx, float &dy) {
+    dx = __fsub_rn(s.px, ux);
+    dy = __fsub_rn(s.py, uy);
+    float q = __fmaf_rn(s.a, __fmul_rn(dx, dx), __fmul_rn(s.b, __fmul_rn(dy, dy)));
+    return __fsub_rn(s.w, q);
+}
+
+}  // namespace dpr
+
+// Launchers (host side), one per stage.  All take the plan's stream.
+namespace dpr {
+
+struct Tables {                  // device pointers inside the plan workspace
+    const ViewDesc *views;
+    const SceneDesc *scenes;
+    const uint32_t *scene_views;        // [n_views] view ids grouped by scene
+    const uint32_t *scene_block_start;  // [n_scenes] first point block of each scene
+    const uint32_t *sort_block_start;   // [n_views]
+    const uint32_t *chunk_start;        // [n_views]
+    const uint32_t *tile_start;         // [n_views]
+    int32_t n_views, n_scenes;
+};
+
+hipError_t launch_project(const Tables &tb, const Thresholds &th, int sh_degree, uint32_t point_blocks,
+                          SplatRec *rec, uint32_t *keys, uint32_t *vals, uint2 *rect,
+                          hipStream_t st);
+
+// Segmented (per view) stable LSD radix sort of 32-bit keys with 32-bit values.
+// Scratch: hist[256 * sort_blocks + 1] u32, part[] u64 (scan partials).
+hipError_t launch_depth_sort(const Tables &tb, uint32_t sort_blocks, uint32_t items,
+                             uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                             uint32_t *hist, uint64_t *part, hipStream_t st);
+
+// Exclusive scan of n u32 counts into out[0..n] (out[n] = total mod 2^32);
+// the exact 64-bit total goes to *total64.  part: >= scan_partials(n) u64.
+hipError_t launch_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint64_t *part,
+                       uint64_t *total64, hipStream_t st);
+uint64_t scan_partials(uint64_t n);
+
+hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *order,
+                             const uint2 *rect, uint32_t *cnt, hipStream_t st);
+hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
+                            const uint2 *rect, const uint32_t *range, uint32_t *pairs,
+                            hipStream_t st);
+
+struct CompositeArgs {
+    const ViewDesc *views;
+    const uint32_t *tile_start;
+    int32_t n_views;
+    uint32_t total_tiles;
+    const SplatRec *rec;
+    const uint32_t *pairs;
+    const uint32_t *range;      // scanned (tile, chunk) counts
+    uint32_t *nlast;            // per-pixel stop index (or null)
+    float *tfinal;              // per-pixel final T for recompute (or null)
+    uint32_t *stats;            // per-pixel blended count (or null)
+    uint32_t *queue;            // persistent work counter (or null)
+    Thresholds th;
+};
+hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st);
+hipError_t launch_recompute(const CompositeArgs &a, bool persistent, hipStream_t st);
+
+struct BackwardArgs {
+    CompositeArgs c;
+    const float *const *dimage;     // device table [n_views] of dL/dimage pointers
+    const float *const *dtrans;     // device table [n_views] (entries may be null) or null
+    const uint32_t *nlast;          // per-pixel stop index
+    const float *tfinal;            // per-pixel T (trans output or recomputed)
+    int tfinal_from_views;          // 1: read T from view.trans
+    float *grad;                    // [items][8] accumulators
+};
+hipError_t launch_composite_bwd(const BackwardArgs &a, bool persistent, hipStream_t st);
+
+hipError_t launch_point_bwd(const Tables &tb, const Thresholds &th, int sh_degree, uint32_t point_blocks,
+                            const float *grad, hipStream_t st);
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st);
+
+}  // namespace dpr

@@ -1,0 +1,134 @@
+// Per-point chain rule from the per-(view, point) splat gradients to the
+// scene parameters: positions through Eq. (1) and the perspective-scaled
+// radius, SH coefficients through Eq. (4), the view direction through Eq. (3),
+// and the opacity through w = log2(o).
+//
+// One thread per scene point loops over the scene's views in a fixed order,
+// so the sum over views is deterministic and each output is written once.
+//
+// Gradient record of an item (accumulated by the compositing backward):
+//   A0 = sum gw dx, A1 = sum gw dy, A2 = sum gw dx^2, A3 = sum gw dy^2,
+//   A4 = sum gw, A5..A7 = dL/dc, with gw = dL/dw and dx = px - ux.
+// Since e = w - a dx^2 - b dy^2:
+//   dL/dpx = -2a A0, dL/dpy = -2b A1, dL/da = -A2, dL/db = -A3, dL/dw = A4.
+#include "dpr_internal.h"
+#include "sh.h"
+
+namespace dpr {
+
+constexpr int kPointThreads = 128;
+
+template <int DEG>
+__global__ __launch_bounds__(kPointThreads) void k_point_bwd(Tables tb, Thresholds th, const float *grad) {
+    const int s = find_segment(tb.scene_block_start, tb.n_scenes, blockIdx.x);
+    const SceneDesc sc = tb.scenes[s];
+    const int i = (int)(blockIdx.x - sc.block_off) * kPointThreads + (int)threadIdx.x;
+    if (i >= sc.n) return;
+    constexpr int deg = DEG;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const float x = sc.xyz[3 * (size_t)i + 0];
+    const float y = sc.xyz[3 * (size_t)i + 1];
+    const float z = sc.xyz[3 * (size_t)i + 2];
+    const float o = sc.opacity[i];
+    const float r = sc.radius[i];
+    const float *h = sc.sh + (size_t)i * 3 * K;
+
+    float gP0 = 0.f, gP1 = 0.f, gP2 = 0.f, gO = 0.f;
+    float gH[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) gH[k] = 0.f;
+
+    for (uint32_t vv = 0; vv < sc.view_count; ++vv) {
+        const ViewDesc &vd = tb.views[tb.scene_views[sc.view_start + vv]];
+        const uint32_t g = vd.item_off + (uint32_t)i;
+        const float Z = depth_z(vd.R, vd.t, x, y, z);
+        if (!(Z > th.z_near)) continue;
+        const float4 ga = reinterpret_cast<const float4 *>(grad + 8 * (size_t)g)[0];
+        const float4 gb = reinterpret_cast<const float4 *>(grad + 8 * (size_t)g)[1];
+        if (ga.x == 0.f && ga.y == 0.f && ga.z == 0.f && ga.w == 0.f && gb.x == 0.f && gb.y == 0.f &&
+            gb.z == 0.f && gb.w == 0.f)
+            continue;
+        const float X = vd.R[0] * x + vd.R[1] * y + vd.R[2] * z + vd.t[0];
+        const float Yc = vd.R[3] * x + vd.R[4] * y + vd.R[5] * z + vd.t[1];
+        const float iz = 1.0f / Z;
+        const float sx = vd.fx * r * iz, sy = vd.fy * r * iz;
+        const float a = (0.5f * kLog2e) / (sx * sx);
+        const float bb = (0.5f * kLog2e) / (sy * sy);
+
+        const float g_px = -2.f * a * ga.x;
+        const float g_py = -2.f * bb * ga.y;
+        const float g_a = -ga.z;
+        const float g_b = -ga.w;
+        const float g_w = gb.x;
+        const float gc0 = gb.y, gc1 = gb.z, gc2 = gb.w;
+
+        // projection px = fx X/Z + cx, py = fy Y/Z + cy; a, b ~ Z^2
+        float dX = g_px * vd.fx * iz;
+        float dY = g_py * vd.fy * iz;
+        float dZ = -(g_px * vd.fx * X + g_py * vd.fy * Yc) * iz * iz + 2.f * (g_a * a + g_b * bb) * iz;
+        // opacity: w = log2(o)
+        gO += g_w / (o * kLn2);
+
+        // colour: c = sum_k h_k Y_k(d), d = v (camera) or R^T v (world), v = X/|X|
+        const float inrm = rsqrtf(X * X + Yc * Yc + Z * Z);
+        const float v0 = X * inrm, v1 = Yc * inrm, v2 = Z * inrm;
+        float d0 = v0, d1 = v1, d2 = v2;
+        if (th.sh_frame == 1) {
+            d0 = vd.R[0] * v0 + vd.R[3] * v1 + vd.R[6] * v2;
+            d1 = vd.R[1] * v0 + vd.R[4] * v1 + vd.R[7] * v2;
+            d2 = vd.R[2] * v0 + vd.R[5] * v1 + vd.R[8] * v2;
+        }
+        float Yb[16], wk[16];
+        sh_values(deg, d0, d1, d2, Yb);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            gH[3 * k + 0] = fmaf(Yb[k], gc0, gH[3 * k + 0]);
+            gH[3 * k + 1] = fmaf(Yb[k], gc1, gH[3 * k + 1]);
+            gH[3 * k + 2] = fmaf(Yb[k], gc2, gH[3 * k + 2]);
+            wk[k] = gc0 * h[3 * k + 0] + gc1 * h[3 * k + 1] + gc2 * h[3 * k + 2];
+        }
+        float gd0, gd1, gd2;
+        sh_grad_dot(deg, d0, d1, d2, wk, gd0, gd1, gd2);
+        float gv0 = gd0, gv1 = gd1, gv2 = gd2;
+        if (th.sh_frame == 1) {
+            gv0 = vd.R[0] * gd0 + vd.R[1] * gd1 + vd.R[2] * gd2;
+            gv1 = vd.R[3] * gd0 + vd.R[4] * gd1 + vd.R[5] * gd2;
+            gv2 = vd.R[6] * gd0 + vd.R[7] * gd1 + vd.R[8] * gd2;
+        }
+        const float vdot = v0 * gv0 + v1 * gv1 + v2 * gv2;
+        dX += (gv0 - v0 * vdot) * inrm;
+        dY += (gv1 - v1 * vdot) * inrm;
+        dZ += (gv2 - v2 * vdot) * inrm;
+
+        // X_cam = R P + t  ->  dP = R^T dX_cam
+        gP0 += vd.R[0] * dX + vd.R[3] * dY + vd.R[6] * dZ;
+        gP1 += vd.R[1] * dX + vd.R[4] * dY + vd.R[7] * dZ;
+        gP2 += vd.R[2] * dX + vd.R[5] * dY + vd.R[8] * dZ;
+    }
+    if (sc.dxyz) {
+        sc.dxyz[3 * (size_t)i + 0] = gP0;
+        sc.dxyz[3 * (size_t)i + 1] = gP1;
+        sc.dxyz[3 * (size_t)i + 2] = gP2;
+    }
+    if (sc.dopacity) sc.dopacity[i] = gO;
+    if (sc.dsh) {
+        float *dst = sc.dsh + (size_t)i * 3 * K;
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) dst[k] = gH[k];
+    }
+}
+
+hipError_t launch_point_bwd(const Tables &tb, const Thresholds &th, int sh_degree, uint32_t point_blocks,
+                            const float *grad, hipStream_t st) {
+    if (point_blocks == 0) return hipSuccess;
+    switch (sh_degree) {
+    case 0: hipLaunchKernelGGL(k_point_bwd<0>, dim3(point_blocks), dim3(kPointThreads), 0, st, tb, th, grad); break;
+    case 1: hipLaunchKernelGGL(k_point_bwd<1>, dim3(point_blocks), dim3(kPointThreads), 0, st, tb, th, grad); break;
+    case 2: hipLaunchKernelGGL(k_point_bwd<2>, dim3(point_blocks), dim3(kPointThreads), 0, st, tb, th, grad); break;
+    case 3: hipLaunchKernelGGL(k_point_bwd<3>, dim3(point_blocks), dim3(kPointThreads), 0, st, tb, th, grad); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dpr

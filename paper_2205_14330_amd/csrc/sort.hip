@@ -1,0 +1,285 @@
+// Device exclusive scan and a segmented stable LSD radix sort.
+//
+// The radix sort orders each view's items by their 32-bit depth key (the
+// float bits of camera Z, which order like unsigned integers for positive
+// values), four 8-bit passes.  It is stable, and the items enter it in point
+// index order, so equal depths keep ascending point index: the tie-break of
+// the front-to-back order (Sec. 3.2: points sorted by z-distance).
+//
+// Segmentation costs nothing extra: the per-block digit histograms are laid
+// out view-major ([view][digit][block of view]), so one exclusive scan over
+// them yields output positions that stay inside each view's item range.
+#include "dpr_internal.h"
+
+namespace dpr {
+
+// ---------------------------------------------------------------------------
+// wave / block primitives (64-lane wavefronts)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Exclusive scan over a block of 256 threads; returns the block total in *total.
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *s_wave, uint32_t *total) {
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan_u32(v);
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        const uint32_t c = s_wave[w];
+        if (w < wave) base += c;
+        tot += c;
+    }
+    *total = tot;
+    __syncthreads();
+    return base + incl - v;
+}
+
+// ---------------------------------------------------------------------------
+// scan: reduce -> scan partials -> downsweep
+// ---------------------------------------------------------------------------
+uint64_t scan_partials(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *in, uint64_t n, uint64_t *part) {
+    __shared__ uint64_t s[kScanThreads / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItemsPerThread; ++j) {
+        const uint64_t idx = base + (uint64_t)j * kScanThreads + threadIdx.x;
+        if (idx < n) sum += in[idx];
+    }
+    sum = wave_sum_u64(sum);
+    if (__lane_id() == 0) s[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) t += s[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// One block: exclusive scan of nb partials in place; total to *total64 and
+// the low 32 bits of it to out[n].
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint64_t *part, uint64_t nb, uint64_t *total64,
+                                                                uint32_t *out, uint64_t n) {
+    __shared__ uint64_t s_w[kScanThreads / 64];
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    uint64_t carry = 0;
+    for (uint64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+        const uint64_t idx = b0 + threadIdx.x;
+        const uint64_t v = idx < nb ? part[idx] : 0;
+        uint64_t incl = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            uint64_t o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint64_t base = carry, tot = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            if (w < wave) base += s_w[w];
+            tot += s_w[w];
+        }
+        if (idx < nb) part[idx] = base + incl - v;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *total64 = carry;
+        out[n] = (uint32_t)carry;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, uint32_t *out, uint64_t n,
+                                                            const uint64_t *part) {
+    __shared__ uint32_t s_wave[kScanThreads / 64];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItemsPerThread;
+    uint32_t v[kScanItemsPerThread];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItemsPerThread; ++j) {
+        const uint64_t idx = base + j;
+        v[j] = idx < n ? in[idx] : 0u;
+        sum += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan_u32(sum, s_wave, &total) + (uint32_t)part[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kScanItemsPerThread; ++j) {
+        const uint64_t idx = base + j;
+        if (idx < n) out[idx] = run;
+        run += v[j];
+    }
+}
+
+hipError_t launch_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint64_t *part,
+                       uint64_t *total64, hipStream_t st) {
+    const uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, part);
+    }
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, st, part, nb, total64, out, n);
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_scan_down, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, out, n, part);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// segmented radix sort
+// ---------------------------------------------------------------------------
+struct SortSeg {
+    uint32_t lb;       // block index within the view
+    uint32_t beg, end; // item range of this block
+    uint32_t nsb;      // sort blocks of the view
+    uint64_t hist_off;
+};
+
+__device__ __forceinline__ SortSeg sort_segment(const Tables &tb) {
+    const int v = find_segment(tb.sort_block_start, tb.n_views, blockIdx.x);
+    const ViewDesc &vd = tb.views[v];
+    SortSeg s;
+    s.lb = blockIdx.x - vd.sort_block_off;
+    s.beg = vd.item_off + s.lb * kSortTile;
+    s.end = min(s.beg + (uint32_t)kSortTile, vd.item_off + (uint32_t)vd.n);
+    s.nsb = vd.nsort_blocks;
+    s.hist_off = vd.hist_off;
+    return s;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(Tables tb, const uint32_t *keys, uint32_t *hist,
+                                                             int shift) {
+    __shared__ uint32_t h[256];
+    const SortSeg sg = sort_segment(tb);
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = sg.beg + threadIdx.x; i < sg.end; i += kSortThreads)
+        atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist[sg.hist_off + (uint64_t)threadIdx.x * sg.nsb + sg.lb] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(Tables tb, const uint32_t *keys_in,
+                                                                const uint32_t *vals_in, uint32_t *keys_out,
+                                                                uint32_t *vals_out, const uint32_t *offs,
+                                                                int shift) {
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wcnt[kSortThreads / 64][256];
+    __shared__ uint32_t s_run[256];
+    __shared__ uint32_t s_start[256];
+    __shared__ uint32_t s_gbase[256];
+    __shared__ uint32_t s_wave[kSortThreads / 64];
+
+    const SortSeg sg = sort_segment(tb);
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+
+    s_run[threadIdx.x] = 0;
+    uint32_t k_[kSortItemsPerThread], v_[kSortItemsPerThread], r_[kSortItemsPerThread];
+#pragma unroll
+    for (int r = 0; r < kSortItemsPerThread; ++r) {
+        const uint32_t idx = sg.beg + (uint32_t)r * kSortThreads + threadIdx.x;
+        const bool valid = idx < sg.end;
+        const uint32_t key = valid ? keys_in[idx] : 0u;
+        const uint32_t val = valid ? vals_in[idx] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_wcnt[wave][lane + 64 * q] = 0;
+        __syncthreads();
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t lrank = (uint32_t)__popcll(peers & lt_mask);
+        if (valid && lrank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {   // digit threadIdx.x: running count + earlier waves of this round
+            uint32_t acc = s_run[threadIdx.x];
+#pragma unroll
+            for (int w = 0; w < kSortThreads / 64; ++w) {
+                const uint32_t c = s_wcnt[w][threadIdx.x];
+                s_wcnt[w][threadIdx.x] = acc;
+                acc += c;
+            }
+            s_run[threadIdx.x] = acc;
+        }
+        __syncthreads();
+        k_[r] = key;
+        v_[r] = val;
+        r_[r] = valid ? s_wcnt[wave][d] + lrank : 0xFFFFFFFFu;
+        __syncthreads();
+    }
+    // local start of every digit, and the global base of this block's digit runs
+    uint32_t total;
+    const uint32_t cnt = s_run[threadIdx.x];
+    const uint32_t start = block_excl_scan_u32(cnt, s_wave, &total);
+    s_start[threadIdx.x] = start;
+    s_gbase[threadIdx.x] = offs[sg.hist_off + (uint64_t)threadIdx.x * sg.nsb + sg.lb];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItemsPerThread; ++r) {
+        if (r_[r] != 0xFFFFFFFFu) {
+            const uint32_t d = (k_[r] >> shift) & 255u;
+            const uint32_t pos = s_start[d] + r_[r];
+            s_keys[pos] = k_[r];
+            s_vals[pos] = v_[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t count = sg.end > sg.beg ? sg.end - sg.beg : 0u;
+    for (uint32_t i = threadIdx.x; i < count; i += kSortThreads) {
+        const uint32_t key = s_keys[i];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t dst = s_gbase[d] + (i - s_start[d]);
+        keys_out[dst] = key;
+        vals_out[dst] = s_vals[i];
+    }
+}
+
+hipError_t launch_depth_sort(const Tables &tb, uint32_t sort_blocks, uint32_t items,
+                             uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                             uint32_t *hist, uint64_t *part, hipStream_t st) {
+    (void)items;
+    if (sort_blocks == 0) return hipSuccess;
+    const uint64_t nh = (uint64_t)sort_blocks * 256u;
+    uint32_t *kin = keys, *vin = vals, *kout = keys_alt, *vout = vals_alt;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_radix_hist, dim3(sort_blocks), dim3(kSortThreads), 0, st, tb, kin, hist, shift);
+        hipError_t e = launch_scan(hist, hist, nh, part, reinterpret_cast<uint64_t *>(part) + scan_partials(nh),
+                                   st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(sort_blocks), dim3(kSortThreads), 0, st, tb, kin, vin, kout,
+                           vout, hist, shift);
+        uint32_t *t;
+        t = kin; kin = kout; kout = t;
+        t = vin; vin = vout; vout = t;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dpr

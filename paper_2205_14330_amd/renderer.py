@@ -1,0 +1,253 @@
+"""Python binding of libdpr: argument marshalling only.
+
+Every step of the renderer runs in the HIP kernels of libdpr.so; this module
+turns torch tensors (device memory) and camera descriptions into the C-ABI
+structs, allocates the workspaces the library asks for, and passes the
+current torch stream.  ``RenderFn`` is the autograd form.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _abi
+from ._abi import BWD_RECOMPUTE, BWD_STORED, FLAG_PERSISTENT, FLAG_STATS, FLAG_TIMING, check, load
+
+
+@dataclasses.dataclass
+class RenderParams:
+    """Thresholds and options of one render (see include/dpr.h)."""
+    alpha_min: float = 1e-5
+    t_min: float = 1e-5
+    alpha_max: float = 0.99
+    z_near: float = 0.01
+    sh_frame: int = 0              # 0: camera-frame view direction, 1: world frame
+    bwd_mode: str = "stored"       # "stored" or "recompute"
+    timing: bool = False
+    stats: bool = False
+    persistent: bool = False
+
+    def to_c(self) -> _abi.Params:
+        flags = (FLAG_TIMING if self.timing else 0) | (FLAG_STATS if self.stats else 0) | \
+                (FLAG_PERSISTENT if self.persistent else 0)
+        mode = {"stored": BWD_STORED, "recompute": BWD_RECOMPUTE}[self.bwd_mode]
+        return _abi.Params(self.alpha_min, self.t_min, self.alpha_max, self.z_near, self.sh_frame, mode, flags, 0)
+
+
+@dataclasses.dataclass
+class SceneTensors:
+    """Device tensors of one point cloud (float32, contiguous)."""
+    xyz: torch.Tensor        # [N, 3]
+    sh: torch.Tensor         # [N, K, 3]
+    opacity: torch.Tensor    # [N]
+    radius: torch.Tensor     # [N]
+
+    @property
+    def n(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def sh_degree(self) -> int:
+        return {1: 0, 4: 1, 9: 2, 16: 3}[int(self.sh.shape[1])]
+
+    @staticmethod
+    def from_numpy(scene, device="cuda") -> "SceneTensors":
+        def t(a):
+            return torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
+        return SceneTensors(t(scene.xyz), t(scene.sh), t(scene.opacity), t(scene.radius))
+
+    def c_struct(self) -> _abi.Scene:
+        for name in ("xyz", "sh", "opacity", "radius"):
+            v = getattr(self, name)
+            if v.dtype != torch.float32 or not v.is_contiguous() or not v.is_cuda:
+                raise ValueError(f"scene.{name} must be a contiguous float32 CUDA tensor")
+        return _abi.Scene(self.n, self.sh_degree, 0, self.xyz.data_ptr(), self.sh.data_ptr(),
+                          self.opacity.data_ptr(), self.radius.data_ptr())
+
+
+def camera_struct(cam) -> _abi.Camera:
+    """``cam``: any object with R (3x3), t (3), fx, fy, cx, cy, width, height."""
+    c = _abi.Camera()
+    R = [float(v) for v in torch.as_tensor(cam.R, dtype=torch.float32).reshape(9).tolist()]
+    t = [float(v) for v in torch.as_tensor(cam.t, dtype=torch.float32).reshape(3).tolist()]
+    c.R[:] = R
+    c.t[:] = t
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """One batch of views over one or more resident scenes.
+
+    The plan workspace, the forward workspace and the output images are
+    allocated with torch on the scenes' device; the library does no device
+    allocation of its own.
+    """
+
+    def __init__(self, scenes: Sequence[SceneTensors], views: Sequence[Tuple[int, object]],
+                 params: RenderParams = RenderParams(), stream: Optional[torch.cuda.Stream] = None,
+                 images: Optional[Sequence[torch.Tensor]] = None, trans: Optional[Sequence[torch.Tensor]] = None):
+        self.lib = load()
+        self.scenes = list(scenes)
+        self.views = list(views)
+        self.params = params
+        self.stream = stream
+        dev = self.scenes[0].xyz.device
+        self.device = dev
+        self._c_scenes = (_abi.Scene * len(self.scenes))(*[s.c_struct() for s in self.scenes])
+        self._cams = [camera_struct(c) for _, c in self.views]
+        if images is None:
+            images = [torch.empty((c.height, c.width, 3), device=dev, dtype=torch.float32) for c in self._cams]
+        if trans is None:
+            trans = [torch.empty((c.height, c.width), device=dev, dtype=torch.float32) for c in self._cams]
+        self.images = list(images)
+        self.trans = list(trans)
+        cv = []
+        for (si, _), cam, img, tr in zip(self.views, self._cams, self.images, self.trans):
+            cv.append(_abi.View(int(si), 0, cam, img.data_ptr(), 0 if tr is None else tr.data_ptr()))
+        self._c_views = (_abi.View * len(cv))(*cv)
+        self._c_params = params.to_c()
+        nbytes = self.lib.dpr_plan_ws_bytes(self._c_scenes, len(self.scenes), self._c_views, len(cv))
+        if nbytes == 0:
+            check(_abi.DPR_ERR_INVALID_ARG)
+        self.plan_ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        self._plan = ctypes.c_void_p()
+        rc = self.lib.dpr_plan_forward(self._c_scenes, len(self.scenes), self._c_views, len(cv),
+                                       ctypes.byref(self._c_params), self.plan_ws.data_ptr(), int(nbytes),
+                                       _stream_handle(stream), ctypes.byref(self._plan))
+        check(rc)
+        self.ws = None
+
+    # -- forward ------------------------------------------------------------------
+    def forward(self):
+        n = int(self.lib.dpr_workspace_bytes(self._plan))
+        if self.ws is None or self.ws.numel() < n:
+            self.ws = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        check(self.lib.dpr_render_forward(self._plan, self.ws.data_ptr(), int(self.ws.numel()),
+                                          _stream_handle(self.stream)))
+        return self.images, self.trans
+
+    # -- backward -----------------------------------------------------------------
+    def backward(self, dL_dimage: Sequence[torch.Tensor], dL_dtrans: Optional[Sequence[Optional[torch.Tensor]]] = None,
+                 want=("xyz", "sh", "opacity"), out=None):
+        """Returns per-scene lists of (dxyz, dsh, dopacity) tensors (None where not wanted)."""
+        if self.ws is None:
+            raise RuntimeError("backward before forward")
+        gi = []
+        for g, c in zip(dL_dimage, self._cams):
+            if g.dtype != torch.float32 or not g.is_contiguous() or tuple(g.shape) != (c.height, c.width, 3):
+                raise ValueError("dL_dimage entries must be contiguous float32 [H, W, 3]")
+            gi.append(g)
+        gt = None
+        if dL_dtrans is not None:
+            gt = []
+            for g, c in zip(dL_dtrans, self._cams):
+                if g is not None and (g.dtype != torch.float32 or not g.is_contiguous()
+                                      or tuple(g.shape) != (c.height, c.width)):
+                    raise ValueError("dL_dtrans entries must be contiguous float32 [H, W]")
+                gt.append(g)
+        if out is None:
+            out = []
+            for s in self.scenes:
+                out.append((torch.empty_like(s.xyz) if "xyz" in want else None,
+                            torch.empty_like(s.sh) if "sh" in want else None,
+                            torch.empty_like(s.opacity) if "opacity" in want else None))
+        nb = int(self.lib.dpr_backward_ws_bytes(self._plan))
+        bws = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
+        P = _abi.ptr_array
+        di = P([g.data_ptr() for g in gi])
+        dt = None if gt is None else P([0 if g is None else g.data_ptr() for g in gt])
+        dx = P([0 if o[0] is None else o[0].data_ptr() for o in out])
+        ds = P([0 if o[1] is None else o[1].data_ptr() for o in out])
+        do = P([0 if o[2] is None else o[2].data_ptr() for o in out])
+        check(self.lib.dpr_render_backward(self._plan, self.ws.data_ptr(), int(self.ws.numel()), di, dt, dx, ds, do,
+                                           bws.data_ptr(), nb, _stream_handle(self.stream)))
+        self._bws = bws   # keep alive until the stream has consumed it
+        return out
+
+    # -- diagnostics --------------------------------------------------------------
+    def info(self) -> _abi.PlanInfo:
+        inf = _abi.PlanInfo()
+        check(self.lib.dpr_plan_get_info(self._plan, ctypes.byref(inf)))
+        return inf
+
+    def stage_times(self) -> dict:
+        arr = (ctypes.c_float * len(_abi.STAGES))()
+        check(self.lib.dpr_stage_times(self._plan, arr, len(_abi.STAGES)))
+        return {name: float(arr[i]) for i, name in enumerate(_abi.STAGES)}
+
+    def free(self):
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            self.lib.dpr_plan_free(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class RenderFn(torch.autograd.Function):
+    """Differentiable render of V same-sized views of one scene.
+
+    forward(xyz, sh, opacity, radius, cameras, params) -> image [V,H,W,3], trans [V,H,W]
+    backward returns gradients for xyz, sh and opacity (radius gets none).
+    """
+
+    @staticmethod
+    def forward(ctx, xyz, sh, opacity, radius, cameras, params: RenderParams):
+        V = len(cameras)
+        H, W = int(cameras[0].height), int(cameras[0].width)
+        if any(int(c.height) != H or int(c.width) != W for c in cameras):
+            raise ValueError("RenderFn needs views of one size; use Plan for mixed sizes")
+        scene = SceneTensors(xyz.detach().contiguous(), sh.detach().contiguous(),
+                             opacity.detach().contiguous(), radius.detach().contiguous())
+        img = torch.empty((V, H, W, 3), device=xyz.device, dtype=torch.float32)
+        tr = torch.empty((V, H, W), device=xyz.device, dtype=torch.float32)
+        plan = Plan([scene], [(0, c) for c in cameras], params, images=list(img.unbind(0)),
+                    trans=list(tr.unbind(0)))
+        plan.forward()
+        ctx.plan = plan
+        ctx.save_for_backward(tr)
+        return img, tr
+
+    @staticmethod
+    def backward(ctx, g_img, g_tr):
+        (tr,) = ctx.saved_tensors   # version check: trans must not have been modified in place
+        plan: Plan = ctx.plan
+        V = g_img.shape[0] if g_img is not None else tr.shape[0]
+        if g_img is None:
+            g_img = torch.zeros((V,) + tuple(plan.images[0].shape), device=tr.device)
+        g_img = g_img.contiguous().float()
+        gi = list(g_img.unbind(0))
+        gt = None
+        if g_tr is not None:
+            g_tr = g_tr.contiguous().float()
+            gt = list(g_tr.unbind(0))
+        (dx, ds, do), = plan.backward(gi, gt)
+        return dx, ds, do, None, None, None
+
+
+def render(xyz, sh, opacity, radius, cameras, params: RenderParams = RenderParams()):
+    """Autograd-aware render of one scene from a list of same-sized cameras."""
+    return RenderFn.apply(xyz, sh, opacity, radius, list(cameras), params)
+
+
+def render_views(scenes: Sequence[SceneTensors], views: Sequence[Tuple[int, object]],
+                 params: RenderParams = RenderParams(), stream=None) -> Plan:
+    """Forward render of many views of many resident scenes in one batch
+    (mixed resolutions allowed).  Returns the executed Plan (images in
+    plan.images, transmittance in plan.trans)."""
+    p = Plan(scenes, views, params, stream=stream)
+    p.forward()
+    return p
