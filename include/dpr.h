@@ -144,7 +144,7 @@ typedef struct dpr_plan_info {
                                 order[j] (float bits of Z; 0xFFFFFFFF = dropped)          */
     int64_t order_off;       /* [items] u32 item ids, depth-sorted within each view      */
     int64_t rect_off;        /* [items] 2 x u32 tile rectangle (x0|y0<<16, x1|y1<<16)    */
-    int64_t range_off;       /* [cnt + 1] u32 exclusive scan of (tile, chunk) counts     */
+    int64_t range_off;       /* [tiles + 1] u32: tile t's list is pairs[range[t] .. range[t+1]) */
     /* byte offsets inside the forward workspace */
     int64_t pairs_off;       /* [pairs] u32 item ids, grouped by tile, depth order within */
     int64_t nlast_off;       /* [pixels] u32 stop index (stored mode), -1 if absent       */

@@ -4,6 +4,10 @@ Every HIP source under csrc/ is compiled and linked into one shared library
 next to this file.  Flags:
   --offload-arch=gfx950      MI355X (CDNA4) code object only
   -munsafe-fp-atomics        hardware float atomics for the gradient scatter
+  -amdgpu-atomic-optimizer-strategy=None
+                             the gradient atomics are issued by one lane after an
+                             explicit wave reduction; the compiler's own wave
+                             reduction around each atomic would only add a loop
   -target-feature -packed-fp32-ops
                              no packed FP32 instructions are generated
 """
@@ -32,6 +36,7 @@ def hipcc() -> str:
 def compile_flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
             "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
 
 

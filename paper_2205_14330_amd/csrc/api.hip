@@ -58,11 +58,13 @@ struct Layout {
 struct Sizes {
     int32_t n_views = 0, n_scenes = 0;
     uint64_t items = 0, tiles = 0, pixels = 0, chunks = 0, cnt = 0, sort_blocks = 0, point_blocks = 0;
+    uint64_t max_view_tiles = 0, max_view_segs = 0, segs = 0;
     int32_t sh_degree = 0;
 };
 
 struct PlanLayout {
-    Region views, scenes, u32tab, rec, keys, vals, keys_alt, vals_alt, rect, hist, part, cnt, range;
+    Region views, scenes, u32tab, rec, keys, vals, keys_alt, vals_alt, rect, hist, part, cnt, segs, tile_total,
+        tile_base;
     uint64_t total = 0;
 };
 
@@ -81,10 +83,12 @@ PlanLayout plan_layout(const Sizes &s) {
     p.rect = L.add(8 * s.items);
     const uint64_t nh = 256ull * s.sort_blocks;
     p.hist = L.add(4 * (nh + 1));
-    const uint64_t np = std::max(scan_partials(nh), scan_partials(s.cnt)) + 2;
+    const uint64_t np = std::max(scan_partials(nh), scan_partials(s.tiles)) + 2;
     p.part = L.add(8 * np);
     p.cnt = L.add(4 * s.cnt);
-    p.range = L.add(4 * (s.cnt + 1));
+    p.segs = L.add(4 * s.segs);
+    p.tile_total = L.add(4 * s.tiles);
+    p.tile_base = L.add(4 * (s.tiles + 1));
     p.total = L.total;
     return p;
 }
@@ -141,10 +145,14 @@ int check_inputs(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *view
         s.items += n;
         const uint64_t tx = ((uint64_t)c.width + kTile - 1) / kTile, ty = ((uint64_t)c.height + kTile - 1) / kTile;
         s.tiles += tx * ty;
+        s.max_view_tiles = std::max(s.max_view_tiles, tx * ty);
         s.pixels += (uint64_t)c.width * (uint64_t)c.height;
         const uint64_t nch = (n + kChunkItems - 1) / kChunkItems;
+        const uint64_t nseg = (nch + kSegChunks - 1) / kSegChunks;
         s.chunks += nch;
         s.cnt += tx * ty * nch;
+        s.segs += tx * ty * nseg;
+        s.max_view_segs = std::max(s.max_view_segs, nseg);
         s.sort_blocks += (n + kSortTile - 1) / kSortTile;
     }
     if (s.items >= 0x7FFFFFFFull) return fail(DPR_ERR_UNSUPPORTED, "total view-points must be < 2^31");
@@ -204,6 +212,9 @@ Tables make_tables(const dpr_plan *p) {
     tb.tile_start = u + 3 * V + S;
     tb.n_views = V;
     tb.n_scenes = S;
+    tb.max_view_tiles = (uint32_t)p->sz.max_view_tiles;
+    tb.max_view_segs = (uint32_t)p->sz.max_view_segs;
+    tb.total_tiles = (uint32_t)p->sz.tiles;
     return tb;
 }
 
@@ -268,7 +279,7 @@ CompositeArgs composite_args(const dpr_plan *p, const void *ws) {
     a.total_tiles = (uint32_t)p->sz.tiles;
     a.rec = reinterpret_cast<const SplatRec *>(p->pws + p->lay.rec.off);
     a.pairs = reinterpret_cast<const uint32_t *>(w + f.pairs.off);
-    a.range = reinterpret_cast<const uint32_t *>(p->pws + p->lay.range.off);
+    a.tile_base = reinterpret_cast<const uint32_t *>(p->pws + p->lay.tile_base.off);
     a.nlast = nullptr;
     a.tfinal = nullptr;
     a.stats = nullptr;
@@ -370,7 +381,7 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
         }
     }
     {
-        uint64_t item = 0, tile = 0, chunk = 0, sblk = 0, hist = 0, cnt = 0, pix = 0;
+        uint64_t item = 0, tile = 0, chunk = 0, sblk = 0, hist = 0, cnt = 0, seg = 0, pix = 0;
         for (int v = 0; v < V; ++v) {
             const dpr_view &vw = views[v];
             ViewDesc &d = p->vdesc[v];
@@ -394,6 +405,7 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
             d.nsort_blocks = (uint32_t)(((uint64_t)sc.n + kSortTile - 1) / kSortTile);
             d.hist_off = hist;
             d.cnt_off = cnt;
+            d.seg_off = seg;
             d.pix_off = pix;
             d.xyz = sc.xyz; d.sh = sc.sh; d.opacity = sc.opacity; d.radius = sc.radius;
             d.image = vw.image;
@@ -408,6 +420,7 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
             sblk += d.nsort_blocks;
             hist += 256ull * d.nsort_blocks;
             cnt += nt * d.nchunks;
+            seg += nt * ((d.nchunks + kSegChunks - 1) / kSegChunks);
             pix += (uint64_t)d.width * d.height;
         }
     }
@@ -423,7 +436,9 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
     uint32_t *hist = reinterpret_cast<uint32_t *>(w + lay.hist.off);
     uint64_t *part = reinterpret_cast<uint64_t *>(w + lay.part.off);
     uint32_t *cnt = reinterpret_cast<uint32_t *>(w + lay.cnt.off);
-    uint32_t *range = reinterpret_cast<uint32_t *>(w + lay.range.off);
+    uint32_t *segs = reinterpret_cast<uint32_t *>(w + lay.segs.off);
+    uint32_t *tile_total = reinterpret_cast<uint32_t *>(w + lay.tile_total.off);
+    uint32_t *tile_base = reinterpret_cast<uint32_t *>(w + lay.tile_base.off);
     const uint64_t np = lay.part.bytes / 8;
     uint64_t *total64 = part + np - 1;
 
@@ -455,7 +470,8 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
     }
     {
         StageScope sc_(p, DPR_STAGE_TILE_SCAN, st);
-        STAGE_TRY(launch_scan(cnt, range, s.cnt, part, total64, st));
+        STAGE_TRY(launch_tile_colscan(tb, cnt, segs, tile_total, st));
+        STAGE_TRY(launch_scan(tile_total, tile_base, s.tiles, part, total64, st));
     }
     STAGE_TRY(hipMemcpyAsync(p->total_host, total64, 8, hipMemcpyDeviceToHost, st));
     STAGE_TRY(hipStreamSynchronize(st));
@@ -494,7 +510,8 @@ int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
         StageScope sc_(p, DPR_STAGE_EMIT, st);
         HIP_TRY(launch_tile_emit(tb, (uint32_t)p->sz.chunks, reinterpret_cast<const uint32_t *>(p->pws + lay.vals.off),
                                  reinterpret_cast<const uint2 *>(p->pws + lay.rect.off),
-                                 reinterpret_cast<const uint32_t *>(p->pws + lay.range.off),
+                                 reinterpret_cast<const uint32_t *>(p->pws + lay.cnt.off),
+                                 reinterpret_cast<const uint32_t *>(p->pws + lay.tile_base.off),
                                  reinterpret_cast<uint32_t *>(w + f.pairs.off), st));
     }
     CompositeArgs a = composite_args(p, ws);
@@ -599,8 +616,8 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
 void dpr_plan_free(dpr_plan *p) {
     if (!p) return;
     for (int i = 0; i < DPR_STAGE_COUNT; ++i) {
-        if (p->ev.a[i]) hipEventDestroy(p->ev.a[i]);
-        if (p->ev.b[i]) hipEventDestroy(p->ev.b[i]);
+        if (p->ev.a[i]) (void)hipEventDestroy(p->ev.a[i]);
+        if (p->ev.b[i]) (void)hipEventDestroy(p->ev.b[i]);
     }
     delete p;
 }
@@ -621,7 +638,7 @@ int dpr_plan_get_info(const dpr_plan *p, dpr_plan_info *out) {
     out->key_off = (int64_t)p->lay.keys.off;
     out->order_off = (int64_t)p->lay.vals.off;
     out->rect_off = (int64_t)p->lay.rect.off;
-    out->range_off = (int64_t)p->lay.range.off;
+    out->range_off = (int64_t)p->lay.tile_base.off;
     out->pairs_off = (int64_t)f.pairs.off;
     out->nlast_off = f.nlast.bytes ? (int64_t)f.nlast.off : -1;
     out->stats_off = f.stats.bytes ? (int64_t)f.stats.off : -1;

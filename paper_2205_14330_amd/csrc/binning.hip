@@ -4,12 +4,14 @@
 // Instead of sorting (tile, depth) pairs, the depth-sorted item list of each
 // view is cut into chunks of kChunkItems consecutive items and binned with a
 // stable counting scatter:
-//   count: per chunk, an LDS histogram of how many of its splats touch each
-//          tile, stored tile-major as cnt[view][tile][chunk];
-//   scan : one exclusive scan over all counts gives, for every (tile, chunk),
-//          the first output slot; tile t's list is [scan(t, 0), scan(t+1, 0));
-//   emit : per chunk, items are walked in depth order and appended to each
-//          tile they touch through an LDS cursor per tile.
+//   count  : per chunk, an LDS histogram of how many of its splats touch each
+//            tile, written as one coalesced row cnt[view][chunk][tile];
+//   colscan: per tile, an exclusive scan down the chunk column (in place) and
+//            the column total; an exclusive scan of the totals (tile_base)
+//            gives every tile's list range [tile_base[t], tile_base[t + 1]);
+//   emit   : per chunk, one wave walks the items in depth order and appends
+//            each to every tile it touches through an LDS cursor per tile,
+//            starting at tile_base[t] + cnt[chunk][t].
 // Within a tile the lists come out in chunk order, and inside a chunk in item
 // order, i.e. exactly ascending (depth, point index): the front-to-back order
 // of Eq. (6)-(7).  The only pass over all pairs is the 4-byte write of emit.
@@ -18,14 +20,16 @@
 namespace dpr {
 
 constexpr int kCountThreads = 256;
-constexpr int kEmitThreads = 256;     // 4 waves; wave w owns tile rows with (row & 3) == w
+constexpr int kEmitLanes = 64;
+constexpr int kColThreads = 256;
 
 struct ChunkInfo {
     uint32_t c;          // chunk index within the view
     uint32_t beg, end;   // sorted-item range
-    uint32_t nchunks;
-    int32_t tiles_x, tiles_y;
-    uint64_t cnt_off;
+    uint32_t ntiles;
+    int32_t tiles_x;
+    uint32_t tile_off;
+    uint64_t row;        // first count entry of this chunk's row
 };
 
 __device__ __forceinline__ ChunkInfo chunk_info(const Tables &tb) {
@@ -35,20 +39,19 @@ __device__ __forceinline__ ChunkInfo chunk_info(const Tables &tb) {
     ci.c = blockIdx.x - vd.chunk_off;
     ci.beg = vd.item_off + ci.c * (uint32_t)kChunkItems;
     ci.end = min(ci.beg + (uint32_t)kChunkItems, vd.item_off + (uint32_t)vd.n);
-    ci.nchunks = vd.nchunks;
     ci.tiles_x = vd.tiles_x;
-    ci.tiles_y = vd.tiles_y;
-    ci.cnt_off = vd.cnt_off;
+    ci.ntiles = (uint32_t)vd.tiles_x * (uint32_t)vd.tiles_y;
+    ci.tile_off = vd.tile_off;
+    ci.row = vd.cnt_off + (uint64_t)ci.c * ci.ntiles;
     return ci;
 }
 
 __global__ __launch_bounds__(kCountThreads) void k_tile_count(Tables tb, const uint32_t *order, const uint2 *rect,
-                                                               uint32_t *cnt) {
-    __shared__ uint32_t s_h[kBandTiles];
+                                                               uint32_t *cnt, uint32_t band_tiles) {
+    extern __shared__ uint32_t s_h[];
     const ChunkInfo ci = chunk_info(tb);
-    const uint32_t ntiles = (uint32_t)ci.tiles_x * (uint32_t)ci.tiles_y;
-    for (uint32_t band = 0; band < ntiles; band += kBandTiles) {
-        const uint32_t bend = min(band + (uint32_t)kBandTiles, ntiles);
+    for (uint32_t band = 0; band < ci.ntiles; band += band_tiles) {
+        const uint32_t bend = min(band + band_tiles, ci.ntiles);
         for (uint32_t t = threadIdx.x; t < bend - band; t += kCountThreads) s_h[t] = 0;
         __syncthreads();
         for (uint32_t s = ci.beg + threadIdx.x; s < ci.end; s += kCountThreads) {
@@ -64,55 +67,183 @@ __global__ __launch_bounds__(kCountThreads) void k_tile_count(Tables tb, const u
             }
         }
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < bend - band; t += kCountThreads)
-            cnt[ci.cnt_off + (uint64_t)(band + t) * ci.nchunks + ci.c] = s_h[t];
+        for (uint32_t t = threadIdx.x; t < bend - band; t += kCountThreads) cnt[ci.row + band + t] = s_h[t];
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uint32_t *order, const uint2 *rect,
-                                                             const uint32_t *range, uint32_t *pairs) {
-    __shared__ uint32_t s_pos[kBandTiles];
+// ---------------------------------------------------------------------------
+// column scan: grid (tiles / 256, segments); segment s covers chunks
+// [s * kSegChunks, (s + 1) * kSegChunks) of every tile column.
+// ---------------------------------------------------------------------------
+struct ColCtx {
+    bool ok;
+    uint32_t t, ntiles, nchunks, nseg;
+    uint64_t cnt_off, seg_off;
+    uint32_t gtile;
+};
+
+__device__ __forceinline__ ColCtx col_ctx(const Tables &tb) {
+    ColCtx c;
+    c.gtile = blockIdx.x * kColThreads + threadIdx.x;
+    c.ok = c.gtile < tb.total_tiles;
+    if (!c.ok) return c;
+    const int v = find_segment(tb.tile_start, tb.n_views, c.gtile);
+    const ViewDesc &vd = tb.views[v];
+    c.t = c.gtile - vd.tile_off;
+    c.ntiles = (uint32_t)vd.tiles_x * (uint32_t)vd.tiles_y;
+    c.nchunks = vd.nchunks;
+    c.nseg = (vd.nchunks + kSegChunks - 1) / kSegChunks;
+    c.cnt_off = vd.cnt_off;
+    c.seg_off = vd.seg_off;
+    return c;
+}
+
+__global__ __launch_bounds__(kColThreads) void k_col_segsum(Tables tb, const uint32_t *cnt, uint32_t *segs) {
+    const ColCtx c = col_ctx(tb);
+    const uint32_t s = blockIdx.y;
+    if (!c.ok || s >= c.nseg) return;
+    const uint32_t c0 = s * kSegChunks, c1 = min(c0 + (uint32_t)kSegChunks, c.nchunks);
+    uint32_t sum = 0;
+#pragma unroll 4
+    for (uint32_t k = c0; k < c1; ++k) sum += cnt[c.cnt_off + (uint64_t)k * c.ntiles + c.t];
+    segs[c.seg_off + (uint64_t)s * c.ntiles + c.t] = sum;
+}
+
+__global__ __launch_bounds__(kColThreads) void k_col_segscan(Tables tb, uint32_t *segs, uint32_t *tile_total) {
+    const ColCtx c = col_ctx(tb);
+    if (!c.ok) return;
+    uint32_t run = 0;
+    for (uint32_t s = 0; s < c.nseg; ++s) {
+        uint32_t *p = segs + c.seg_off + (uint64_t)s * c.ntiles + c.t;
+        const uint32_t v = *p;
+        *p = run;
+        run += v;
+    }
+    tile_total[c.gtile] = run;
+}
+
+__global__ __launch_bounds__(kColThreads) void k_col_down(Tables tb, uint32_t *cnt, const uint32_t *segs) {
+    const ColCtx c = col_ctx(tb);
+    const uint32_t s = blockIdx.y;
+    if (!c.ok || s >= c.nseg) return;
+    const uint32_t c0 = s * kSegChunks, c1 = min(c0 + (uint32_t)kSegChunks, c.nchunks);
+    uint32_t run = segs[c.seg_off + (uint64_t)s * c.ntiles + c.t];
+    for (uint32_t k = c0; k < c1; ++k) {
+        uint32_t *p = cnt + c.cnt_off + (uint64_t)k * c.ntiles + c.t;
+        const uint32_t v = *p;
+        *p = run;
+        run += v;
+    }
+}
+
+hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, uint32_t *tile_total,
+                               hipStream_t st) {
+    if (tb.total_tiles == 0) return hipSuccess;
+    const uint32_t bx = (tb.total_tiles + kColThreads - 1) / kColThreads;
+    const uint32_t ns = tb.max_view_segs > 0 ? tb.max_view_segs : 1;
+    hipLaunchKernelGGL(k_col_segsum, dim3(bx, ns), dim3(kColThreads), 0, st, tb, cnt, segs);
+    hipLaunchKernelGGL(k_col_segscan, dim3(bx), dim3(kColThreads), 0, st, tb, segs, tile_total);
+    hipLaunchKernelGGL(k_col_down, dim3(bx, ns), dim3(kColThreads), 0, st, tb, cnt, segs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// emit
+// ---------------------------------------------------------------------------
+// Tile of the k-th cell of rectangle (x0, y0, w) in row-major order.
+__device__ __forceinline__ uint32_t rect_tile(uint32_t k, uint32_t x0, uint32_t y0, uint32_t w, float inv_w,
+                                              uint32_t tiles_x) {
+    const uint32_t r = (uint32_t)(((float)k + 0.5f) * inv_w);   // exact for k < 2^20, w <= 1024
+    return (y0 + r) * tiles_x + x0 + (k - r * w);
+}
+
+struct EmitItem {
+    uint32_t g, x0, y0, w, n;
+    float inv_w;
+};
+
+__device__ __forceinline__ EmitItem emit_item(uint32_t g, uint32_t ra, uint32_t rb) {
+    EmitItem it;
+    it.g = g;
+    it.x0 = ra & 0xFFFFu;
+    it.y0 = ra >> 16;
+    const uint32_t x1 = rb & 0xFFFFu, y1 = rb >> 16;
+    it.w = x1 > it.x0 ? x1 - it.x0 : 0u;
+    const uint32_t h = y1 > it.y0 ? y1 - it.y0 : 0u;
+    it.n = it.w * h;
+    it.inv_w = it.w ? __builtin_amdgcn_rcpf((float)it.w) : 0.f;
+    return it;
+}
+
+// One wave per chunk.  Items are appended strictly in depth order; four items
+// are interleaved so that their LDS cursor updates are in flight together
+// (LDS operations of one wave complete in program order, so a tile touched by
+// two of them still receives them in order).  Lanes without a tile update a
+// private dummy cursor so the atomics need no branches.
+__global__ __launch_bounds__(kEmitLanes) void k_tile_emit(Tables tb, const uint32_t *order, const uint2 *rect,
+                                                           const uint32_t *pre, const uint32_t *tile_base,
+                                                           uint32_t *pairs, uint32_t band_tiles) {
+    extern __shared__ uint32_t s_pos[];    // [band_tiles + 64]
     const ChunkInfo ci = chunk_info(tb);
-    const uint32_t ntiles = (uint32_t)ci.tiles_x * (uint32_t)ci.tiles_y;
-    const int lane = __lane_id();
-    const uint32_t wave = threadIdx.x >> 6;
-    for (uint32_t band = 0; band < ntiles; band += kBandTiles) {
-        const uint32_t bend = min(band + (uint32_t)kBandTiles, ntiles);
-        for (uint32_t t = threadIdx.x; t < bend - band; t += kEmitThreads)
-            s_pos[t] = range[ci.cnt_off + (uint64_t)(band + t) * ci.nchunks + ci.c];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t tx = (uint32_t)ci.tiles_x;
+    for (uint32_t band = 0; band < ci.ntiles; band += band_tiles) {
+        const uint32_t bend = min(band + band_tiles, ci.ntiles);
+        const uint32_t nb_t = bend - band;
+        const uint32_t dummy = nb_t + lane;
+        for (uint32_t t = lane; t < nb_t; t += kEmitLanes)
+            s_pos[t] = tile_base[ci.tile_off + band + t] + pre[ci.row + band + t];
+        s_pos[dummy] = 0;
         __syncthreads();
-        // every wave walks the whole chunk in depth order; it only appends to
-        // the tile rows it owns, so no two waves touch the same cursor
-        for (uint32_t s0 = ci.beg; s0 < ci.end; s0 += 64) {
-            const uint32_t my = s0 + (uint32_t)lane;
+        for (uint32_t s0 = ci.beg; s0 < ci.end; s0 += kEmitLanes) {
+            const uint32_t my = s0 + lane;
             uint32_t g = 0;
             uint2 rc = make_uint2(0u, 0u);
             if (my < ci.end) {
                 g = order[my];
                 rc = rect[g];
             }
-            const uint32_t nb = min(64u, ci.end - s0);
-            for (uint32_t j = 0; j < nb; ++j) {
-                const uint32_t gj = __builtin_amdgcn_readlane(g, j);
-                const uint32_t ra = __builtin_amdgcn_readlane(rc.x, j);
-                const uint32_t rb = __builtin_amdgcn_readlane(rc.y, j);
-                const uint32_t x0 = ra & 0xFFFFu, y0 = ra >> 16, x1 = rb & 0xFFFFu, y1 = rb >> 16;
-                if (x1 <= x0 || y1 <= y0) continue;
-                const uint32_t first = y0 + ((wave - (y0 & 3u)) & 3u);   // first row == wave (mod 4)
-                if (first >= y1) continue;
-                const uint32_t rows = (y1 - first + 3u) >> 2;
-                const uint32_t width = x1 - x0;
-                const uint32_t n = rows * width;
-                const float inv_w = 1.0f / (float)width;
-                for (uint32_t k = (uint32_t)lane; k < n; k += 64u) {
-                    const uint32_t rr = (uint32_t)(((float)k + 0.5f) * inv_w);
-                    const uint32_t cc = k - rr * width;
-                    const uint32_t t = (first + 4u * rr) * (uint32_t)ci.tiles_x + x0 + cc;
-                    if (t >= band && t < bend) {
-                        const uint32_t p = atomicAdd(&s_pos[t - band], 1u);
-                        pairs[p] = gj;
+            const uint32_t nb = min((uint32_t)kEmitLanes, ci.end - s0);
+            uint32_t j = 0;
+            for (; j + 4 <= nb; j += 4) {
+                EmitItem it[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    it[q] = emit_item(__builtin_amdgcn_readlane(g, j + q), __builtin_amdgcn_readlane(rc.x, j + q),
+                                      __builtin_amdgcn_readlane(rc.y, j + q));
+                const uint32_t nmax = max(max(it[0].n, it[1].n), max(it[2].n, it[3].n));
+                if (nmax <= (uint32_t)kEmitLanes) {
+                    uint32_t t[4], p[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        t[q] = dummy;
+                        if (lane < it[q].n) {
+                            const uint32_t tt = rect_tile(lane, it[q].x0, it[q].y0, it[q].w, it[q].inv_w, tx);
+                            if (tt >= band && tt < bend) t[q] = tt - band;
+                        }
                     }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) p[q] = atomicAdd(&s_pos[t[q]], 1u);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (t[q] != dummy) pairs[p[q]] = it[q].g;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        for (uint32_t k = lane; k < it[q].n; k += kEmitLanes) {
+                            const uint32_t tt = rect_tile(k, it[q].x0, it[q].y0, it[q].w, it[q].inv_w, tx);
+                            if (tt >= band && tt < bend) pairs[atomicAdd(&s_pos[tt - band], 1u)] = it[q].g;
+                        }
+                    }
+                }
+            }
+            for (; j < nb; ++j) {
+                const EmitItem it = emit_item(__builtin_amdgcn_readlane(g, j), __builtin_amdgcn_readlane(rc.x, j),
+                                              __builtin_amdgcn_readlane(rc.y, j));
+                for (uint32_t k = lane; k < it.n; k += kEmitLanes) {
+                    const uint32_t tt = rect_tile(k, it.x0, it.y0, it.w, it.inv_w, tx);
+                    if (tt >= band && tt < bend) pairs[atomicAdd(&s_pos[tt - band], 1u)] = it.g;
                 }
             }
         }
@@ -120,18 +251,26 @@ __global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uin
     }
 }
 
+static uint32_t band_for(const Tables &tb) {
+    return tb.max_view_tiles < (uint32_t)kBandTiles ? tb.max_view_tiles : (uint32_t)kBandTiles;
+}
+
 hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *order,
                              const uint2 *rect, uint32_t *cnt, hipStream_t st) {
     if (chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_count, dim3(chunks), dim3(kCountThreads), 0, st, tb, order, rect, cnt);
+    const uint32_t band = band_for(tb);
+    hipLaunchKernelGGL(k_tile_count, dim3(chunks), dim3(kCountThreads), (size_t)band * 4, st, tb, order, rect, cnt,
+                       band);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                            const uint2 *rect, const uint32_t *range, uint32_t *pairs,
-                            hipStream_t st) {
+                            const uint2 *rect, const uint32_t *pre, const uint32_t *tile_base,
+                            uint32_t *pairs, hipStream_t st) {
     if (chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitThreads), 0, st, tb, order, rect, range, pairs);
+    const uint32_t band = band_for(tb);
+    hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitLanes), (size_t)(band + kEmitLanes) * 4, st, tb, order,
+                       rect, pre, tile_base, pairs, band);
     return hipGetLastError();
 }
 

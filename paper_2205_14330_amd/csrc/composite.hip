@@ -1,34 +1,36 @@
 // Per-tile front-to-back compositing (Sec. 3.2, Eq. 5-7) and its reverse-mode
 // derivative.
 //
-// One workgroup of 256 lanes (4 waves) per 16x16 tile, one pixel per lane.
-// The tile's depth-ordered list is consumed in chunks of 256 splat records
-// staged in LDS (each lane gathers one 32-byte record); every lane then walks
-// the chunk from LDS.  A lane stops after the first blended splat that leaves
-// T < t_min; the workgroup leaves the list as soon as no lane is active
-// (__syncthreads_count), which also ends idle waves early.
+// Forward: one workgroup of 4 waves per 16x16 tile; wave w owns the 8x8
+// quadrant w, one pixel per lane.  The tile's depth-ordered list is consumed
+// in chunks of 256 splat records gathered into LDS (the next chunk is
+// prefetched into registers while the current one is processed) and read
+// back as LDS broadcasts.  A pixel stops after the first blended splat that
+// leaves T < t_min; a wave skips the rest of a chunk once its 64 pixels have
+// stopped, and the workgroup leaves the list once all 256 have.
 //
-// The backward walks the same list in reverse from the furthest stop index,
-// recovering T_i = T_{i+1} / (1 - alpha_i) (alpha <= alpha_max < 1), keeps the
-// back-to-front colour sum, and turns each (pixel, splat) contribution into 8
-// partial sums.  Those are reduced across the 64 lanes of a wave, then across
-// the 4 waves in LDS, and leave the workgroup as one float atomic per quantity
-// per (tile, splat).
+// Backward: one wave per tile; each lane owns a 2x2 pixel quad so that the
+// per-splat reduction is shared by 256 pixels.  The list is walked in reverse
+// from the furthest stop index, recovering T_i = T_{i+1} / (1 - alpha_i)
+// (alpha <= alpha_max < 1), keeping the back-to-front colour sum, and folding
+// each (pixel, splat) contribution into 8 per-lane partial sums.  Records are
+// held one per lane and broadcast with readlane.  The sums are reduced across
+// the wave with DPP row operations into lane 63, which issues one float
+// atomic per quantity per (tile, splat).
 #include "dpr_internal.h"
 
 namespace dpr {
 
-constexpr int kCompThreads = kTilePix;   // 256
+constexpr int kCompLanes = 64;
+constexpr int kQuad = 4;          // pixels per lane
 
 struct TileCtx {
     uint32_t start, end;       // list range in pairs[]
-    int32_t px, py;            // this lane's pixel
-    bool inside;
-    uint64_t pix;              // index into per-pixel state arrays (global)
-    uint64_t lpix;             // pixel index within the view
     int v;                     // view
+    int x0, y0;                // top-left pixel of this lane's quad
 };
 
+// Backward layout: lane owns the 2x2 quad at (2 (lane & 7), 2 (lane >> 3)).
 __device__ __forceinline__ TileCtx tile_ctx(const CompositeArgs &a, uint32_t tile) {
     TileCtx c;
     c.v = find_segment(a.tile_start, a.n_views, tile);
@@ -36,14 +38,11 @@ __device__ __forceinline__ TileCtx tile_ctx(const CompositeArgs &a, uint32_t til
     const uint32_t lt = tile - vd.tile_off;
     const uint32_t ty = lt / (uint32_t)vd.tiles_x;
     const uint32_t tx = lt - ty * (uint32_t)vd.tiles_x;
-    c.px = (int)(tx * kTile + (threadIdx.x & (kTile - 1)));
-    c.py = (int)(ty * kTile + (threadIdx.x >> 4));
-    c.inside = c.px < vd.width && c.py < vd.height;
-    const uint64_t rb = vd.cnt_off + (uint64_t)lt * vd.nchunks;
-    c.start = a.range[rb];
-    c.end = a.range[rb + vd.nchunks];
-    c.lpix = (uint64_t)c.py * (uint64_t)vd.width + (uint64_t)c.px;
-    c.pix = vd.pix_off + c.lpix;
+    const int lane = threadIdx.x & 63;
+    c.x0 = (int)(tx * kTile) + 2 * (lane & 7);
+    c.y0 = (int)(ty * kTile) + 2 * (lane >> 3);
+    c.start = a.tile_base[tile];
+    c.end = a.tile_base[tile + 1];
     return c;
 }
 
@@ -53,219 +52,284 @@ __device__ __forceinline__ float splat_alpha(float e, float alpha_max, bool &cla
     return clamped ? alpha_max : g;
 }
 
-// next tile for persistent workgroups (thread 0 pops, broadcast through LDS)
-__device__ __forceinline__ uint32_t pop_tile(uint32_t *queue, uint32_t *s_next) {
-    __syncthreads();
-    if (threadIdx.x == 0) *s_next = atomicAdd(queue, 1u) + gridDim.x;
-    __syncthreads();
-    return *s_next;
+// Record k of the pair list, or an inert record past the end.
+__device__ __forceinline__ void load_rec(const CompositeArgs &a, uint32_t k, uint32_t end, float4 &r0, float4 &r1,
+                                         uint32_t &id) {
+    if (k < end) {
+        id = a.pairs[k];
+        const float4 *src = reinterpret_cast<const float4 *>(a.rec + id);
+        r0 = src[0];
+        r1 = src[1];
+    } else {
+        id = 0;
+        r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        r1 = make_float4(-INFINITY, 0.f, 0.f, 0.f);
+    }
+}
+
+__device__ __forceinline__ float bcast(float v, int j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
+__device__ __forceinline__ SplatRec bcast_rec(const float4 &r0, const float4 &r1, int j) {
+    SplatRec s;
+    s.px = bcast(r0.x, j); s.py = bcast(r0.y, j); s.a = bcast(r0.z, j); s.b = bcast(r0.w, j);
+    s.w = bcast(r1.x, j); s.cr = bcast(r1.y, j); s.cg = bcast(r1.z, j); s.cb = bcast(r1.w, j);
+    return s;
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8).
+// Give each XCD one contiguous range of tiles so that neighbouring tiles,
+// which share most of their splats, hit the same L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t total) {
+    const uint32_t q = total >> 3, r = total & 7u;
+    const uint32_t x = b & 7u, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
+// next tile for persistent waves
+__device__ __forceinline__ uint32_t pop_tile(uint32_t *queue) {
+    uint32_t t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(queue, 1u) + gridDim.x;
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
 }
 
 // ---------------------------------------------------------------------------
 // forward (COLOR = true) and recompute of the per-pixel state (COLOR = false)
 // ---------------------------------------------------------------------------
+constexpr int kFwdThreads = 256;
+
 template <bool COLOR, bool PERSISTENT>
-__global__ __launch_bounds__(kCompThreads) void k_composite(CompositeArgs a) {
-    __shared__ SplatRec s_rec[kCompThreads];
+__global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
+    __shared__ float4 s_r0[kFwdThreads], s_r1[kFwdThreads];
     __shared__ uint32_t s_next;
     const float neg_lambda = -a.th.lambda;
-    for (uint32_t tile = blockIdx.x; tile < a.total_tiles;) {
-        const TileCtx c = tile_ctx(a, tile);
-        const float ux = (float)c.px + 0.5f, uy = (float)c.py + 0.5f;
-        float T = 1.0f, I0 = 0.f, I1 = 0.f, I2 = 0.f;
-        uint32_t nlast = 0, nblend = 0;
-        bool done = !c.inside;
-        for (uint32_t base = c.start; base < c.end; base += kCompThreads) {
-            const uint32_t k = base + threadIdx.x;
-            if (k < c.end) {
-                const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[k]);
-                float4 *dst = reinterpret_cast<float4 *>(&s_rec[threadIdx.x]);
-                dst[0] = src[0];
-                dst[1] = src[1];
-            }
+    const float alpha_max = a.th.alpha_max, t_min = a.th.t_min;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_tile(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
+        const int v = find_segment(a.tile_start, a.n_views, tile);
+        const ViewDesc &vd = a.views[v];
+        const uint32_t lt = tile - vd.tile_off;
+        const uint32_t ty = lt / (uint32_t)vd.tiles_x;
+        const uint32_t tx = lt - ty * (uint32_t)vd.tiles_x;
+        const int px = (int)(tx * kTile) + 8 * (wave & 1) + (lane & 7);
+        const int py = (int)(ty * kTile) + 8 * (wave >> 1) + (lane >> 3);
+        const uint32_t start = a.tile_base[tile], end = a.tile_base[tile + 1];
+        const float ux = (float)px + 0.5f, uy = (float)py + 0.5f;
+        const bool inside = px < vd.width && py < vd.height;
+        bool live = inside;
+        float T = 1.f, I0 = 0.f, I1 = 0.f, I2 = 0.f;
+        uint32_t nlast = end - start, nblend = 0;
+        float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = make_float4(-INFINITY, 0.f, 0.f, 0.f);
+        if (start + tid < end) {
+            const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[start + tid]);
+            n0 = src[0];
+            n1 = src[1];
+        }
+        for (uint32_t base = start; base < end; base += kFwdThreads) {
+            s_r0[tid] = n0;
+            s_r1[tid] = n1;
             __syncthreads();
-            const uint32_t cnt = min((uint32_t)kCompThreads, c.end - base);
-            if (!done) {
-                for (uint32_t j = 0; j < cnt; ++j) {
-                    const SplatRec &s = s_rec[j];
+            if (base + kFwdThreads + tid < end) {
+                const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[base + kFwdThreads + tid]);
+                n0 = src[0];
+                n1 = src[1];
+            }
+            const int cnt = (int)min((uint32_t)kFwdThreads, end - base);
+            if (__ballot(live) != 0ull) {
+                for (int j = 0; j < cnt; ++j) {
+                    const float4 r0 = s_r0[j], r1 = s_r1[j];
+                    SplatRec s;
+                    s.px = r0.x; s.py = r0.y; s.a = r0.z; s.b = r0.w;
+                    s.w = r1.x; s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
                     float dx, dy;
                     const float e = splat_exponent(s, ux, uy, dx, dy);
-                    if (e < neg_lambda) continue;
-                    bool clamped;
-                    const float alpha = splat_alpha(e, a.th.alpha_max, clamped);
-                    if (COLOR) {
-                        const float Ta = T * alpha;
-                        I0 = fmaf(Ta, s.cr, I0);
-                        I1 = fmaf(Ta, s.cg, I1);
-                        I2 = fmaf(Ta, s.cb, I2);
+                    if (live && e >= neg_lambda) {
+                        bool clamped;
+                        const float alpha = splat_alpha(e, alpha_max, clamped);
+                        if (COLOR) {
+                            const float Ta = T * alpha;
+                            I0 = fmaf(Ta, s.cr, I0);
+                            I1 = fmaf(Ta, s.cg, I1);
+                            I2 = fmaf(Ta, s.cb, I2);
+                        }
+                        T = T * (1.0f - alpha);
+                        ++nblend;
+                        if (T < t_min) {
+                            live = false;
+                            nlast = base - start + (uint32_t)j + 1;
+                        }
                     }
-                    T = T * (1.0f - alpha);
-                    ++nblend;
-                    if (T < a.th.t_min) {
-                        done = true;
-                        nlast = base - c.start + j + 1;
-                        break;
-                    }
+                    if ((j & 15) == 15 && __ballot(live) == 0ull) break;
                 }
             }
-            if (__syncthreads_count(!done) == 0) break;
+            if (__syncthreads_count(live) == 0) break;
         }
-        if (c.inside) {
-            if (!done) nlast = c.end - c.start;
-            const ViewDesc &vd = a.views[c.v];
+        if (inside) {
+            const uint64_t lpix = (uint64_t)py * (uint64_t)vd.width + (uint64_t)px;
+            const uint64_t pix = vd.pix_off + lpix;
             if (COLOR) {
-                float *img = vd.image + 3 * c.lpix;
+                float *img = vd.image + 3 * lpix;
                 img[0] = I0; img[1] = I1; img[2] = I2;
-                if (vd.trans) vd.trans[c.lpix] = T;
-                if (a.stats) a.stats[c.pix] = nblend;
+                if (vd.trans) vd.trans[lpix] = T;
+                if (a.stats) a.stats[pix] = nblend;
             } else {
-                a.tfinal[c.pix] = T;
+                a.tfinal[pix] = T;
             }
-            if (a.nlast) a.nlast[c.pix] = nlast;
+            if (a.nlast) a.nlast[pix] = nlast;
         }
         if (!PERSISTENT) break;
-        tile = pop_tile(a.queue, &s_next);
+        __syncthreads();
+        if (tid == 0) s_next = atomicAdd(a.queue, 1u) + gridDim.x;
+        __syncthreads();
+        tile = s_next;
     }
 }
 
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_sum_f32(float v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Sum over the 64 lanes; the total is valid in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]   -> quad sums
+    v = dpp_add<0x141, 0xF>(v);   // row_half_mirror       -> 8-lane sums
+    v = dpp_add<0x140, 0xF>(v);   // row_mirror            -> 16-lane row sums
+    v = dpp_add<0x142, 0xA>(v);   // row_bcast:15 -> rows 1, 3 add rows 0, 2
+    v = dpp_add<0x143, 0xC>(v);   // row_bcast:31 -> rows 2, 3 add rows 0+1
     return v;
 }
 
 template <bool PERSISTENT>
-__global__ __launch_bounds__(kCompThreads) void k_composite_bwd(BackwardArgs b) {
-    __shared__ SplatRec s_rec[kCompThreads];
-    __shared__ uint32_t s_id[kCompThreads];
-    __shared__ float s_acc[8][kCompThreads];
-    __shared__ uint32_t s_max[kCompThreads / 64];
-    __shared__ uint32_t s_next;
+__global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     const CompositeArgs &a = b.c;
     const float neg_lambda = -a.th.lambda;
-    const int lane = __lane_id();
-    const int wave = threadIdx.x >> 6;
+    const float alpha_max = a.th.alpha_max;
+    const int lane = threadIdx.x;
 
-    for (uint32_t tile = blockIdx.x; tile < a.total_tiles;) {
+    for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_tile(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
         const TileCtx c = tile_ctx(a, tile);
         const ViewDesc &vd = a.views[c.v];
-        const float ux = (float)c.px + 0.5f, uy = (float)c.py + 0.5f;
-        uint32_t nl = 0;
-        float T = 1.0f, gI0 = 0.f, gI1 = 0.f, gI2 = 0.f, gT = 0.f;
-        if (c.inside) {
-            nl = b.nlast[c.pix];
-            T = b.tfinal_from_views ? vd.trans[c.lpix] : b.tfinal[c.pix];
-            const float *gi = b.dimage[c.v] + 3 * c.lpix;
-            gI0 = gi[0]; gI1 = gi[1]; gI2 = gi[2];
-            if (b.dtrans && b.dtrans[c.v]) gT = b.dtrans[c.v][c.lpix];
-        }
-        const float Tfin = T;
-        float B0 = 0.f, B1 = 0.f, B2 = 0.f;      // sum over blended splats behind of T_k alpha_k c_k
-
-        // furthest stop index of the tile
-        uint32_t m = nl;
+        float ux[kQuad], uy[kQuad], T[kQuad], gI0[kQuad], gI1[kQuad], gI2[kQuad], gTT[kQuad];
+        float B0[kQuad], B1[kQuad], B2[kQuad];
+        uint32_t nl[kQuad];
+        uint32_t mymax = 0;
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
-        if (lane == 0) s_max[wave] = m;
-        __syncthreads();
-        uint32_t maxn = 0;
-        for (int w = 0; w < kCompThreads / 64; ++w) maxn = max(maxn, s_max[w]);
-
-        for (uint32_t cend = c.start + maxn; cend > c.start;) {
-            const uint32_t cbeg = cend - c.start > (uint32_t)kCompThreads ? cend - kCompThreads : c.start;
-            const uint32_t cnt = cend - cbeg;
-            __syncthreads();
-            if (threadIdx.x < cnt) {
-                const uint32_t id = a.pairs[cbeg + threadIdx.x];
-                s_id[threadIdx.x] = id;
-                const float4 *src = reinterpret_cast<const float4 *>(a.rec + id);
-                float4 *dst = reinterpret_cast<float4 *>(&s_rec[threadIdx.x]);
-                dst[0] = src[0];
-                dst[1] = src[1];
+        for (int p = 0; p < kQuad; ++p) {
+            const int px = c.x0 + (p & 1), py = c.y0 + (p >> 1);
+            ux[p] = (float)px + 0.5f;
+            uy[p] = (float)py + 0.5f;
+            nl[p] = 0; T[p] = 1.f; gI0[p] = gI1[p] = gI2[p] = 0.f; gTT[p] = 0.f;
+            B0[p] = B1[p] = B2[p] = 0.f;
+            if (px < vd.width && py < vd.height) {
+                const uint64_t lpix = (uint64_t)py * (uint64_t)vd.width + (uint64_t)px;
+                const uint64_t pix = vd.pix_off + lpix;
+                nl[p] = b.nlast[pix];
+                T[p] = b.tfinal_from_views ? vd.trans[lpix] : b.tfinal[pix];
+                const float *gi = b.dimage[c.v] + 3 * lpix;
+                gI0[p] = gi[0]; gI1[p] = gi[1]; gI2[p] = gi[2];
+                if (b.dtrans && b.dtrans[c.v]) gTT[p] = b.dtrans[c.v][lpix] * T[p];   // dL/dT * T_final
+                mymax = max(mymax, nl[p]);
             }
+        }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) s_acc[q][threadIdx.x] = 0.f;
-            __syncthreads();
-            for (int j = (int)cnt - 1; j >= 0; --j) {
-                const uint32_t pos = cbeg - c.start + (uint32_t)j;
-                float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f;
-                bool hit = false;
-                if (pos < nl) {
-                    const SplatRec &s = s_rec[j];
-                    float dx, dy;
-                    const float e = splat_exponent(s, ux, uy, dx, dy);
-                    if (e >= neg_lambda) {
-                        hit = true;
-                        bool clamped;
-                        const float alpha = splat_alpha(e, a.th.alpha_max, clamped);
-                        const float om = 1.0f - alpha;
-                        const float iom = 1.0f / om;
-                        T = T * iom;                         // T in front of this splat
-                        const float Ta = T * alpha;
-                        const float dA = gI0 * (T * s.cr - B0 * iom) + gI1 * (T * s.cg - B1 * iom) +
-                                         gI2 * (T * s.cb - B2 * iom) - gT * Tfin * iom;
-                        v5 = Ta * gI0; v6 = Ta * gI1; v7 = Ta * gI2;
-                        B0 = fmaf(Ta, s.cr, B0);
-                        B1 = fmaf(Ta, s.cg, B1);
-                        B2 = fmaf(Ta, s.cb, B2);
-                        if (!clamped) {
-                            const float gw = dA * alpha * kLn2;    // dL/dw; dL/dq = -gw
-                            v4 = gw;
-                            v0 = gw * dx;
-                            v1 = gw * dy;
-                            v2 = v0 * dx;
-                            v3 = v1 * dy;
+        for (int d = 32; d >= 1; d >>= 1) mymax = max(mymax, (uint32_t)__shfl_xor((int)mymax, d, 64));
+        const uint32_t maxn = (uint32_t)__builtin_amdgcn_readfirstlane((int)mymax);
+
+        // chunks back to front: [cbeg, cbeg + 64) aligned to the list start
+        if (maxn > 0) {
+            uint32_t cbeg = c.start + ((maxn - 1) / kCompLanes) * kCompLanes;
+            const uint32_t lend = c.start + maxn;
+            float4 n0, n1;
+            uint32_t nid;
+            load_rec(a, cbeg + lane, lend, n0, n1, nid);
+            while (true) {
+                const float4 r0 = n0, r1 = n1;
+                const uint32_t id = nid;
+                const bool more = cbeg > c.start;
+                if (more) load_rec(a, cbeg - kCompLanes + lane, lend, n0, n1, nid);
+                const int cnt = (int)min((uint32_t)kCompLanes, lend - cbeg);
+                for (int j = cnt - 1; j >= 0; --j) {
+                    const SplatRec s = bcast_rec(r0, r1, j);
+                    const uint32_t pos = cbeg - c.start + (uint32_t)j;
+                    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f;
+                    bool any = false;
+#pragma unroll
+                    for (int p = 0; p < kQuad; ++p) {
+                        float dx, dy;
+                        const float e = splat_exponent(s, ux[p], uy[p], dx, dy);
+                        if (pos < nl[p] && e >= neg_lambda) {
+                            any = true;
+                            bool clamped;
+                            const float alpha = splat_alpha(e, alpha_max, clamped);
+                            const float iom = __builtin_amdgcn_rcpf(1.0f - alpha);
+                            T[p] = T[p] * iom;                       // T in front of this splat
+                            const float Ta = T[p] * alpha;
+                            const float dA = gI0[p] * fmaf(T[p], s.cr, -B0[p] * iom) +
+                                             gI1[p] * fmaf(T[p], s.cg, -B1[p] * iom) +
+                                             gI2[p] * fmaf(T[p], s.cb, -B2[p] * iom) - gTT[p] * iom;
+                            v5 = fmaf(Ta, gI0[p], v5);
+                            v6 = fmaf(Ta, gI1[p], v6);
+                            v7 = fmaf(Ta, gI2[p], v7);
+                            B0[p] = fmaf(Ta, s.cr, B0[p]);
+                            B1[p] = fmaf(Ta, s.cg, B1[p]);
+                            B2[p] = fmaf(Ta, s.cb, B2[p]);
+                            if (!clamped) {
+                                const float gw = dA * alpha * kLn2;    // dL/dw; dL/dq = -gw
+                                const float gx = gw * dx, gy = gw * dy;
+                                v4 += gw;
+                                v0 += gx;
+                                v1 += gy;
+                                v2 = fmaf(gx, dx, v2);
+                                v3 = fmaf(gy, dy, v3);
+                            }
+                        }
+                    }
+                    if (__ballot(any) != 0ull) {
+                        v0 = wave_sum_to_lane63(v0); v1 = wave_sum_to_lane63(v1);
+                        v2 = wave_sum_to_lane63(v2); v3 = wave_sum_to_lane63(v3);
+                        v4 = wave_sum_to_lane63(v4); v5 = wave_sum_to_lane63(v5);
+                        v6 = wave_sum_to_lane63(v6); v7 = wave_sum_to_lane63(v7);
+                        const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)id, j);
+                        if (lane == 63) {
+                            float *g = b.grad + 8 * (size_t)gid;
+                            atomicAdd(g + 0, v0); atomicAdd(g + 1, v1);
+                            atomicAdd(g + 2, v2); atomicAdd(g + 3, v3);
+                            atomicAdd(g + 4, v4); atomicAdd(g + 5, v5);
+                            atomicAdd(g + 6, v6); atomicAdd(g + 7, v7);
                         }
                     }
                 }
-                if (__ballot(hit) != 0ull) {
-                    v0 = wave_sum_f32(v0); v1 = wave_sum_f32(v1);
-                    v2 = wave_sum_f32(v2); v3 = wave_sum_f32(v3);
-                    v4 = wave_sum_f32(v4); v5 = wave_sum_f32(v5);
-                    v6 = wave_sum_f32(v6); v7 = wave_sum_f32(v7);
-                    if (lane == 0) {
-                        atomicAdd(&s_acc[0][j], v0); atomicAdd(&s_acc[1][j], v1);
-                        atomicAdd(&s_acc[2][j], v2); atomicAdd(&s_acc[3][j], v3);
-                        atomicAdd(&s_acc[4][j], v4); atomicAdd(&s_acc[5][j], v5);
-                        atomicAdd(&s_acc[6][j], v6); atomicAdd(&s_acc[7][j], v7);
-                    }
-                }
+                if (!more) break;
+                cbeg -= kCompLanes;
             }
-            __syncthreads();
-            if (threadIdx.x < cnt) {
-                float *gdst = b.grad + 8 * (size_t)s_id[threadIdx.x];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const float v = s_acc[q][threadIdx.x];
-                    if (v != 0.f) atomicAdd(gdst + q, v);
-                }
-            }
-            cend = cbeg;
         }
         if (!PERSISTENT) break;
-        tile = pop_tile(a.queue, &s_next);
+        tile = pop_tile(a.queue);
     }
 }
 
-static uint32_t persistent_grid(uint32_t tiles) {
+static uint32_t persistent_grid(uint32_t tiles, uint32_t per_cu) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
     }
-    const uint32_t g = (uint32_t)cus * 8u;
+    const uint32_t g = (uint32_t)cus * per_cu;
     return tiles < g ? tiles : g;
 }
 
 hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (a.total_tiles == 0) return hipSuccess;
     if (persistent) {
-        hipLaunchKernelGGL((k_composite<true, true>), dim3(persistent_grid(a.total_tiles)), dim3(kCompThreads), 0,
+        hipLaunchKernelGGL((k_composite<true, true>), dim3(persistent_grid(a.total_tiles, 4)), dim3(kFwdThreads), 0,
                            st, a);
     } else {
-        hipLaunchKernelGGL((k_composite<true, false>), dim3(a.total_tiles), dim3(kCompThreads), 0, st, a);
+        hipLaunchKernelGGL((k_composite<true, false>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -273,10 +337,10 @@ hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStre
 hipError_t launch_recompute(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (a.total_tiles == 0) return hipSuccess;
     if (persistent) {
-        hipLaunchKernelGGL((k_composite<false, true>), dim3(persistent_grid(a.total_tiles)), dim3(kCompThreads), 0,
+        hipLaunchKernelGGL((k_composite<false, true>), dim3(persistent_grid(a.total_tiles, 4)), dim3(kFwdThreads), 0,
                            st, a);
     } else {
-        hipLaunchKernelGGL((k_composite<false, false>), dim3(a.total_tiles), dim3(kCompThreads), 0, st, a);
+        hipLaunchKernelGGL((k_composite<false, false>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -284,10 +348,10 @@ hipError_t launch_recompute(const CompositeArgs &a, bool persistent, hipStream_t
 hipError_t launch_composite_bwd(const BackwardArgs &b, bool persistent, hipStream_t st) {
     if (b.c.total_tiles == 0) return hipSuccess;
     if (persistent) {
-        hipLaunchKernelGGL((k_composite_bwd<true>), dim3(persistent_grid(b.c.total_tiles)), dim3(kCompThreads), 0,
+        hipLaunchKernelGGL((k_composite_bwd<true>), dim3(persistent_grid(b.c.total_tiles, 16)), dim3(kCompLanes), 0,
                            st, b);
     } else {
-        hipLaunchKernelGGL((k_composite_bwd<false>), dim3(b.c.total_tiles), dim3(kCompThreads), 0, st, b);
+        hipLaunchKernelGGL((k_composite_bwd<false>), dim3(b.c.total_tiles), dim3(kCompLanes), 0, st, b);
     }
     return hipGetLastError();
 }

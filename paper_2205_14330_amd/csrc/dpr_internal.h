@@ -10,8 +10,9 @@ namespace dpr {
 
 constexpr int kTile = 16;                 // screen tile edge in pixels
 constexpr int kTilePix = kTile * kTile;   // 256 pixels per tile
-constexpr int kChunkItems = 2048;         // depth-sorted items per binning chunk
+constexpr int kChunkItems = 512;          // depth-sorted items per binning chunk
 constexpr int kBandTiles = 8192;          // tiles of one view handled per LDS band
+constexpr int kSegChunks = 16;            // chunks per column-scan segment
 constexpr int kSortThreads = 256;
 constexpr int kSortItemsPerThread = 8;
 constexpr int kSortTile = kSortThreads * kSortItemsPerThread;   // 2048 keys per sort block
@@ -40,7 +41,8 @@ struct ViewDesc {
     uint32_t nsort_blocks;
     uint32_t pad0;
     uint64_t hist_off;          // first radix-histogram entry of this view
-    uint64_t cnt_off;           // first (tile, chunk) count entry of this view
+    uint64_t cnt_off;           // first (chunk, tile) count entry of this view (chunk-major)
+    uint64_t seg_off;           // first (segment, tile) partial-sum entry of this view
     uint64_t pix_off;           // first pixel of this view in per-pixel state arrays
     const float *xyz;
     const float *sh;
@@ -124,6 +126,9 @@ struct Tables {                  // device pointers inside the plan workspace
     const uint32_t *chunk_start;        // [n_views]
     const uint32_t *tile_start;         // [n_views]
     int32_t n_views, n_scenes;
+    uint32_t max_view_tiles;            // largest tile count of any view
+    uint32_t max_view_segs;             // largest column-scan segment count of any view
+    uint32_t total_tiles;
 };
 
 hipError_t launch_project(const Tables &tb, const Thresholds &th, int sh_degree, uint32_t point_blocks,
@@ -142,11 +147,17 @@ hipError_t launch_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint64_t *
                        uint64_t *total64, hipStream_t st);
 uint64_t scan_partials(uint64_t n);
 
+// Binning.  cnt is chunk-major per view: cnt[cnt_off + c * tiles + t].
 hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *order,
                              const uint2 *rect, uint32_t *cnt, hipStream_t st);
+// In place: cnt[c][t] -> sum of cnt[c'][t] over c' < c; tile_total[tile] = column sum.
+// segs: scratch of sum over views of tiles * segments u32.
+hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, uint32_t *tile_total,
+                               hipStream_t st);
+// tile_base = exclusive scan of tile_total (tiles + 1 entries).
 hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                            const uint2 *rect, const uint32_t *range, uint32_t *pairs,
-                            hipStream_t st);
+                            const uint2 *rect, const uint32_t *pre, const uint32_t *tile_base,
+                            uint32_t *pairs, hipStream_t st);
 
 struct CompositeArgs {
     const ViewDesc *views;
@@ -155,7 +166,7 @@ struct CompositeArgs {
     uint32_t total_tiles;
     const SplatRec *rec;
     const uint32_t *pairs;
-    const uint32_t *range;      // scanned (tile, chunk) counts
+    const uint32_t *tile_base;  // [tiles + 1] first pair of each tile
     uint32_t *nlast;            // per-pixel stop index (or null)
     float *tfinal;              // per-pixel final T for recompute (or null)
     uint32_t *stats;            // per-pixel blended count (or null)

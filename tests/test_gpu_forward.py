@@ -129,9 +129,7 @@ def test_tile_lists_are_exact(dpr):
     keys[order] = skeys
     rect = to_np(ws[inf.rect_off: inf.rect_off + 8 * M].view(torch.int32)).view(np.uint32).reshape(M, 2)
     tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
-    nch = (M + inf.chunk_items - 1) // inf.chunk_items
-    cnt = tx * ty * nch
-    rng_ = to_np(ws[inf.range_off: inf.range_off + 4 * (cnt + 1)].view(torch.int32)).view(np.uint32)
+    rng_ = to_np(ws[inf.range_off: inf.range_off + 4 * (tx * ty + 1)].view(torch.int32)).view(np.uint32)
     pairs = to_np(plan.ws[inf.pairs_off: inf.pairs_off + 4 * inf.pairs].view(torch.int32)).view(np.uint32)
     assert rng_[-1] == inf.pairs
     expect = {t: [] for t in range(tx * ty)}
@@ -142,7 +140,7 @@ def test_tile_lists_are_exact(dpr):
             for xx in range(x0, x1):
                 expect[yy * tx + xx].append((keys[g], g))
     for t in range(tx * ty):
-        s, e = rng_[t * nch], rng_[(t + 1) * nch]
+        s, e = rng_[t], rng_[t + 1]
         want = [g for _, g in sorted(expect[t])]
         assert pairs[s:e].tolist() == want, t
 
