@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--views", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this renderer runs on one GPU; --gpus above 1 is not supported "
@@ -186,6 +188,15 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                 "frac": None, "traffic": load_traffic(dom, "config3")}
+
+    if args.copy_calibration_mib > 0:
+        src = torch.empty(args.copy_calibration_mib * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -466,7 +466,7 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
     }
     {
         StageScope sc_(p, DPR_STAGE_TILE_COUNT, st);
-        STAGE_TRY(launch_tile_count(tb, (uint32_t)s.chunks, vals, rect, cnt, st));
+        STAGE_TRY(launch_tile_count(tb, (uint32_t)s.chunks, vals, rect, rec, p->th.lambda, cnt, st));
     }
     {
         StageScope sc_(p, DPR_STAGE_TILE_SCAN, st);
@@ -510,6 +510,7 @@ int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
         StageScope sc_(p, DPR_STAGE_EMIT, st);
         HIP_TRY(launch_tile_emit(tb, (uint32_t)p->sz.chunks, reinterpret_cast<const uint32_t *>(p->pws + lay.vals.off),
                                  reinterpret_cast<const uint2 *>(p->pws + lay.rect.off),
+                                 reinterpret_cast<const SplatRec *>(p->pws + lay.rec.off), p->th.lambda,
                                  reinterpret_cast<const uint32_t *>(p->pws + lay.cnt.off),
                                  reinterpret_cast<const uint32_t *>(p->pws + lay.tile_base.off),
                                  reinterpret_cast<uint32_t *>(w + f.pairs.off), st));

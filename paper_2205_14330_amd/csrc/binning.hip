@@ -47,7 +47,8 @@ __device__ __forceinline__ ChunkInfo chunk_info(const Tables &tb) {
 }
 
 __global__ __launch_bounds__(kCountThreads) void k_tile_count(Tables tb, const uint32_t *order, const uint2 *rect,
-                                                               uint32_t *cnt, uint32_t band_tiles) {
+                                                               const SplatRec *rec, float lambda, uint32_t *cnt,
+                                                               uint32_t band_tiles) {
     extern __shared__ uint32_t s_h[];
     const ChunkInfo ci = chunk_info(tb);
     for (uint32_t band = 0; band < ci.ntiles; band += band_tiles) {
@@ -55,14 +56,19 @@ __global__ __launch_bounds__(kCountThreads) void k_tile_count(Tables tb, const u
         for (uint32_t t = threadIdx.x; t < bend - band; t += kCountThreads) s_h[t] = 0;
         __syncthreads();
         for (uint32_t s = ci.beg + threadIdx.x; s < ci.end; s += kCountThreads) {
-            const uint2 rc = rect[order[s]];
+            const uint32_t g = order[s];
+            const uint2 rc = rect[g];
             const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
+            if (x1 <= x0 || y1 <= y0) continue;
+            const float4 r0 = reinterpret_cast<const float4 *>(rec + g)[0];
+            const float thr = reinterpret_cast<const float4 *>(rec + g)[1].x + lambda;
             for (uint32_t ty = y0; ty < y1; ++ty) {
                 const uint32_t rowb = ty * (uint32_t)ci.tiles_x;
                 if (rowb + x1 <= band || rowb + x0 >= bend) continue;
                 for (uint32_t tx = x0; tx < x1; ++tx) {
                     const uint32_t t = rowb + tx;
-                    if (t >= band && t < bend) atomicAdd(&s_h[t - band], 1u);
+                    if (t >= band && t < bend && splat_touches_tile(r0.x, r0.y, r0.z, r0.w, thr, tx, ty))
+                        atomicAdd(&s_h[t - band], 1u);
                 }
             }
         }
@@ -151,20 +157,24 @@ hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, 
 // ---------------------------------------------------------------------------
 // emit
 // ---------------------------------------------------------------------------
-// Tile of the k-th cell of rectangle (x0, y0, w) in row-major order.
-__device__ __forceinline__ uint32_t rect_tile(uint32_t k, uint32_t x0, uint32_t y0, uint32_t w, float inv_w,
-                                              uint32_t tiles_x) {
-    const uint32_t r = (uint32_t)(((float)k + 0.5f) * inv_w);   // exact for k < 2^20, w <= 1024
-    return (y0 + r) * tiles_x + x0 + (k - r * w);
-}
-
 struct EmitItem {
     uint32_t g, x0, y0, w, n;
     float inv_w;
+    float px, py, a, b, thr;
 };
 
-__device__ __forceinline__ EmitItem emit_item(uint32_t g, uint32_t ra, uint32_t rb) {
+__device__ __forceinline__ float rl(float v, uint32_t j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
+__device__ __forceinline__ EmitItem emit_item(uint32_t g, uint32_t ra, uint32_t rb, const float4 &shape, float thr,
+                                              uint32_t j) {
     EmitItem it;
+    it.px = rl(shape.x, j);
+    it.py = rl(shape.y, j);
+    it.a = rl(shape.z, j);
+    it.b = rl(shape.w, j);
+    it.thr = rl(thr, j);
     it.g = g;
     it.x0 = ra & 0xFFFFu;
     it.y0 = ra >> 16;
@@ -176,33 +186,48 @@ __device__ __forceinline__ EmitItem emit_item(uint32_t g, uint32_t ra, uint32_t 
     return it;
 }
 
+// Appends one item to all its tiles (any rectangle size); cell k of the
+// rectangle is row floor((k + 0.5) / w), exact for k < 2^20 and w <= 1024.
+__device__ __forceinline__ void emit_one(const EmitItem &it, uint32_t lane, uint32_t tiles_x, uint32_t band,
+                                         uint32_t bend, uint32_t *s_pos, uint32_t *pairs) {
+    for (uint32_t k = lane; k < it.n; k += kEmitLanes) {
+        const uint32_t r = (uint32_t)(((float)k + 0.5f) * it.inv_w);
+        const uint32_t cx = it.x0 + k - r * it.w, cy = it.y0 + r;
+        const uint32_t tt = cy * tiles_x + cx;
+        if (tt >= band && tt < bend && splat_touches_tile(it.px, it.py, it.a, it.b, it.thr, cx, cy))
+            pairs[atomicAdd(&s_pos[tt - band], 1u)] = it.g;
+    }
+}
+
 // One wave per chunk.  Items are appended strictly in depth order; four items
 // are interleaved so that their LDS cursor updates are in flight together
 // (LDS operations of one wave complete in program order, so a tile touched by
-// two of them still receives them in order).  Lanes without a tile update a
-// private dummy cursor so the atomics need no branches.
+// two of them still receives them in order).
 __global__ __launch_bounds__(kEmitLanes) void k_tile_emit(Tables tb, const uint32_t *order, const uint2 *rect,
-                                                           const uint32_t *pre, const uint32_t *tile_base,
-                                                           uint32_t *pairs, uint32_t band_tiles) {
-    extern __shared__ uint32_t s_pos[];    // [band_tiles + 64]
+                                                           const SplatRec *rec, float lambda, const uint32_t *pre,
+                                                           const uint32_t *tile_base, uint32_t *pairs,
+                                                           uint32_t band_tiles) {
+    extern __shared__ uint32_t s_pos[];    // [band_tiles]
     const ChunkInfo ci = chunk_info(tb);
     const uint32_t lane = threadIdx.x;
     const uint32_t tx = (uint32_t)ci.tiles_x;
     for (uint32_t band = 0; band < ci.ntiles; band += band_tiles) {
         const uint32_t bend = min(band + band_tiles, ci.ntiles);
         const uint32_t nb_t = bend - band;
-        const uint32_t dummy = nb_t + lane;
         for (uint32_t t = lane; t < nb_t; t += kEmitLanes)
             s_pos[t] = tile_base[ci.tile_off + band + t] + pre[ci.row + band + t];
-        s_pos[dummy] = 0;
         __syncthreads();
         for (uint32_t s0 = ci.beg; s0 < ci.end; s0 += kEmitLanes) {
             const uint32_t my = s0 + lane;
             uint32_t g = 0;
             uint2 rc = make_uint2(0u, 0u);
+            float4 shape = make_float4(0.f, 0.f, 0.f, 0.f);
+            float thr = -1.f;
             if (my < ci.end) {
                 g = order[my];
                 rc = rect[g];
+                shape = reinterpret_cast<const float4 *>(rec + g)[0];
+                thr = reinterpret_cast<const float4 *>(rec + g)[1].x + lambda;
             }
             const uint32_t nb = min((uint32_t)kEmitLanes, ci.end - s0);
             uint32_t j = 0;
@@ -211,40 +236,39 @@ __global__ __launch_bounds__(kEmitLanes) void k_tile_emit(Tables tb, const uint3
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     it[q] = emit_item(__builtin_amdgcn_readlane(g, j + q), __builtin_amdgcn_readlane(rc.x, j + q),
-                                      __builtin_amdgcn_readlane(rc.y, j + q));
+                                      __builtin_amdgcn_readlane(rc.y, j + q), shape, thr, j + q);
                 const uint32_t nmax = max(max(it[0].n, it[1].n), max(it[2].n, it[3].n));
                 if (nmax <= (uint32_t)kEmitLanes) {
                     uint32_t t[4], p[4];
+                    bool on[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        t[q] = dummy;
+                        on[q] = false;
+                        t[q] = 0;
                         if (lane < it[q].n) {
-                            const uint32_t tt = rect_tile(lane, it[q].x0, it[q].y0, it[q].w, it[q].inv_w, tx);
-                            if (tt >= band && tt < bend) t[q] = tt - band;
+                            const uint32_t r = (uint32_t)(((float)lane + 0.5f) * it[q].inv_w);
+                            const uint32_t cx = it[q].x0 + lane - r * it[q].w, cy = it[q].y0 + r;
+                            const uint32_t tt = cy * tx + cx;
+                            on[q] = tt >= band && tt < bend &&
+                                    splat_touches_tile(it[q].px, it[q].py, it[q].a, it[q].b, it[q].thr, cx, cy);
+                            t[q] = tt - band;
                         }
                     }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) p[q] = atomicAdd(&s_pos[t[q]], 1u);
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        if (t[q] != dummy) pairs[p[q]] = it[q].g;
+                        if (on[q]) p[q] = atomicAdd(&s_pos[t[q]], 1u);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (on[q]) pairs[p[q]] = it[q].g;
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        for (uint32_t k = lane; k < it[q].n; k += kEmitLanes) {
-                            const uint32_t tt = rect_tile(k, it[q].x0, it[q].y0, it[q].w, it[q].inv_w, tx);
-                            if (tt >= band && tt < bend) pairs[atomicAdd(&s_pos[tt - band], 1u)] = it[q].g;
-                        }
-                    }
+                    for (int q = 0; q < 4; ++q) emit_one(it[q], lane, tx, band, bend, s_pos, pairs);
                 }
             }
             for (; j < nb; ++j) {
                 const EmitItem it = emit_item(__builtin_amdgcn_readlane(g, j), __builtin_amdgcn_readlane(rc.x, j),
-                                              __builtin_amdgcn_readlane(rc.y, j));
-                for (uint32_t k = lane; k < it.n; k += kEmitLanes) {
-                    const uint32_t tt = rect_tile(k, it.x0, it.y0, it.w, it.inv_w, tx);
-                    if (tt >= band && tt < bend) pairs[atomicAdd(&s_pos[tt - band], 1u)] = it.g;
-                }
+                                              __builtin_amdgcn_readlane(rc.y, j), shape, thr, j);
+                emit_one(it, lane, tx, band, bend, s_pos, pairs);
             }
         }
         __syncthreads();
@@ -256,21 +280,21 @@ static uint32_t band_for(const Tables &tb) {
 }
 
 hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                             const uint2 *rect, uint32_t *cnt, hipStream_t st) {
+                             const uint2 *rect, const SplatRec *rec, float lambda, uint32_t *cnt, hipStream_t st) {
     if (chunks == 0) return hipSuccess;
     const uint32_t band = band_for(tb);
-    hipLaunchKernelGGL(k_tile_count, dim3(chunks), dim3(kCountThreads), (size_t)band * 4, st, tb, order, rect, cnt,
-                       band);
+    hipLaunchKernelGGL(k_tile_count, dim3(chunks), dim3(kCountThreads), (size_t)band * 4, st, tb, order, rect, rec,
+                       lambda, cnt, band);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                            const uint2 *rect, const uint32_t *pre, const uint32_t *tile_base,
-                            uint32_t *pairs, hipStream_t st) {
+                            const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
+                            const uint32_t *tile_base, uint32_t *pairs, hipStream_t st) {
     if (chunks == 0) return hipSuccess;
     const uint32_t band = band_for(tb);
-    hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitLanes), (size_t)(band + kEmitLanes) * 4, st, tb, order,
-                       rect, pre, tile_base, pairs, band);
+    hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitLanes), (size_t)band * 4, st, tb, order, rect, rec,
+                       lambda, pre, tile_base, pairs, band);
     return hipGetLastError();
 }
 

@@ -15,8 +15,9 @@
 // (alpha <= alpha_max < 1), keeping the back-to-front colour sum, and folding
 // each (pixel, splat) contribution into 8 per-lane partial sums.  Records are
 // held one per lane and broadcast with readlane.  The sums are reduced across
-// the wave with DPP row operations into lane 63, which issues one float
-// atomic per quantity per (tile, splat).
+// each group of 8 lanes with DPP, the 8 group sums of up to 16 splats are
+// staged in LDS, and each flush completes 128 sums and adds them to the
+// per-item gradient records with two 64-lane float atomics.
 #include "dpr_internal.h"
 
 namespace dpr {
@@ -46,10 +47,9 @@ __device__ __forceinline__ TileCtx tile_ctx(const CompositeArgs &a, uint32_t til
     return c;
 }
 
-__device__ __forceinline__ float splat_alpha(float e, float alpha_max, bool &clamped) {
-    const float g = __builtin_amdgcn_exp2f(e);
-    clamped = g > alpha_max;
-    return clamped ? alpha_max : g;
+// alpha = min(alpha_max, 2^e); the clamp (and only it) blocks the gradient to e.
+__device__ __forceinline__ float splat_alpha(float e, float alpha_max) {
+    return fminf(__builtin_amdgcn_exp2f(e), alpha_max);
 }
 
 // Record k of the pair list, or an inert record past the end.
@@ -78,15 +78,6 @@ __device__ __forceinline__ SplatRec bcast_rec(const float4 &r0, const float4 &r1
     return s;
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8).
-// Give each XCD one contiguous range of tiles so that neighbouring tiles,
-// which share most of their splats, hit the same L2.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t total) {
-    const uint32_t q = total >> 3, r = total & 7u;
-    const uint32_t x = b & 7u, i = b >> 3;
-    return x * q + min(x, r) + i;
-}
-
 // next tile for persistent waves
 __device__ __forceinline__ uint32_t pop_tile(uint32_t *queue) {
     uint32_t t = 0;
@@ -106,7 +97,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     const float neg_lambda = -a.th.lambda;
     const float alpha_max = a.th.alpha_max, t_min = a.th.t_min;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_tile(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
+    for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_remap(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
         const int v = find_segment(a.tile_start, a.n_views, tile);
         const ViewDesc &vd = a.views[v];
         const uint32_t lt = tile - vd.tile_off;
@@ -145,8 +136,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                     float dx, dy;
                     const float e = splat_exponent(s, ux, uy, dx, dy);
                     if (live && e >= neg_lambda) {
-                        bool clamped;
-                        const float alpha = splat_alpha(e, alpha_max, clamped);
+                        const float alpha = splat_alpha(e, alpha_max);
                         if (COLOR) {
                             const float Ta = T * alpha;
                             I0 = fmaf(Ta, s.cr, I0);
@@ -189,30 +179,56 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-template <int CTRL, int ROW_MASK>
+template <int CTRL>
 __device__ __forceinline__ float dpp_add(float v) {
-    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-// Sum over the 64 lanes; the total is valid in lane 63.
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
-    v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
-    v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]   -> quad sums
-    v = dpp_add<0x141, 0xF>(v);   // row_half_mirror       -> 8-lane sums
-    v = dpp_add<0x140, 0xF>(v);   // row_mirror            -> 16-lane row sums
-    v = dpp_add<0x142, 0xA>(v);   // row_bcast:15 -> rows 1, 3 add rows 0, 2
-    v = dpp_add<0x143, 0xC>(v);   // row_bcast:31 -> rows 2, 3 add rows 0+1
+// Sum over each group of 8 consecutive lanes (valid in all 8 lanes).
+__device__ __forceinline__ float octet_sum(float v) {
+    v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]  -> sums of 4
+    v = dpp_add<0x141>(v);   // row_half_mirror      -> sums of 8
     return v;
+}
+
+// Staging of per-splat partial sums: slot k holds, for one splat, the 8 octet
+// sums of each of the 8 quantities at [k][octet][quantity] with a padded
+// octet stride of 9 words, so both the octet writes and the flush reads hit
+// distinct LDS banks.
+constexpr int kSlots = 16;
+constexpr int kOctStride = 9;
+constexpr int kSlotStride = 8 * kOctStride;
+
+// Completes the sums of the first nslots slots (lane L handles slot L/8 and
+// slot 8 + L/8, quantity L%8) and adds them to the gradient records.
+__device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t *s_gid, int nslots, float *grad,
+                                            int lane) {
+    const int q = lane & 7;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int k = (lane >> 3) + 8 * half;
+        if (k < nslots) {
+            const float *src = s_part + k * kSlotStride + q;
+            float sum = 0.f;
+#pragma unroll
+            for (int o = 0; o < 8; ++o) sum += src[o * kOctStride];
+            atomicAdd(grad + 8 * (size_t)s_gid[k] + q, sum);
+        }
+    }
 }
 
 template <bool PERSISTENT>
 __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
+    __shared__ float s_part[kSlots * kSlotStride];
+    __shared__ uint32_t s_gid[kSlots];
     const CompositeArgs &a = b.c;
     const float neg_lambda = -a.th.lambda;
     const float alpha_max = a.th.alpha_max;
     const int lane = threadIdx.x;
+    const int octet = lane >> 3;
 
-    for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_tile(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
+    for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_remap(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
         const TileCtx c = tile_ctx(a, tile);
         const ViewDesc &vd = a.views[c.v];
         float ux[kQuad], uy[kQuad], T[kQuad], gI0[kQuad], gI1[kQuad], gI2[kQuad], gTT[kQuad];
@@ -242,6 +258,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
         const uint32_t maxn = (uint32_t)__builtin_amdgcn_readfirstlane((int)mymax);
 
         // chunks back to front: [cbeg, cbeg + 64) aligned to the list start
+        int nslots = 0;
         if (maxn > 0) {
             uint32_t cbeg = c.start + ((maxn - 1) / kCompLanes) * kCompLanes;
             const uint32_t lend = c.start + maxn;
@@ -259,49 +276,50 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                     const uint32_t pos = cbeg - c.start + (uint32_t)j;
                     float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f;
                     bool any = false;
+                    // branch-free over the 4 pixels: a pixel that did not blend this
+                    // splat gets alpha = 0, so 1/(1 - alpha) = 1 and every update
+                    // below is an exact no-op for it
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
                         float dx, dy;
                         const float e = splat_exponent(s, ux[p], uy[p], dx, dy);
-                        if (pos < nl[p] && e >= neg_lambda) {
-                            any = true;
-                            bool clamped;
-                            const float alpha = splat_alpha(e, alpha_max, clamped);
-                            const float iom = __builtin_amdgcn_rcpf(1.0f - alpha);
-                            T[p] = T[p] * iom;                       // T in front of this splat
-                            const float Ta = T[p] * alpha;
-                            const float dA = gI0[p] * fmaf(T[p], s.cr, -B0[p] * iom) +
-                                             gI1[p] * fmaf(T[p], s.cg, -B1[p] * iom) +
-                                             gI2[p] * fmaf(T[p], s.cb, -B2[p] * iom) - gTT[p] * iom;
-                            v5 = fmaf(Ta, gI0[p], v5);
-                            v6 = fmaf(Ta, gI1[p], v6);
-                            v7 = fmaf(Ta, gI2[p], v7);
-                            B0[p] = fmaf(Ta, s.cr, B0[p]);
-                            B1[p] = fmaf(Ta, s.cg, B1[p]);
-                            B2[p] = fmaf(Ta, s.cb, B2[p]);
-                            if (!clamped) {
-                                const float gw = dA * alpha * kLn2;    // dL/dw; dL/dq = -gw
-                                const float gx = gw * dx, gy = gw * dy;
-                                v4 += gw;
-                                v0 += gx;
-                                v1 += gy;
-                                v2 = fmaf(gx, dx, v2);
-                                v3 = fmaf(gy, dy, v3);
-                            }
-                        }
+                        const bool hit = pos < nl[p] && e >= neg_lambda;
+                        any = any || hit;
+                        const float g = __builtin_amdgcn_exp2f(e);
+                        const bool clamped = g > alpha_max;
+                        const float alpha = hit ? fminf(g, alpha_max) : 0.f;
+                        const float iom = __builtin_amdgcn_rcpf(1.0f - alpha);
+                        T[p] = T[p] * iom;                       // T in front of this splat
+                        const float Ta = T[p] * alpha;
+                        const float dA = gI0[p] * fmaf(T[p], s.cr, -B0[p] * iom) +
+                                         gI1[p] * fmaf(T[p], s.cg, -B1[p] * iom) +
+                                         gI2[p] * fmaf(T[p], s.cb, -B2[p] * iom) - gTT[p] * iom;
+                        v5 = fmaf(Ta, gI0[p], v5);
+                        v6 = fmaf(Ta, gI1[p], v6);
+                        v7 = fmaf(Ta, gI2[p], v7);
+                        B0[p] = fmaf(Ta, s.cr, B0[p]);
+                        B1[p] = fmaf(Ta, s.cg, B1[p]);
+                        B2[p] = fmaf(Ta, s.cb, B2[p]);
+                        const float gw = clamped ? 0.f : dA * alpha * kLn2;    // dL/dw; dL/dq = -gw
+                        const float gx = gw * dx, gy = gw * dy;
+                        v4 += gw;
+                        v0 += gx;
+                        v1 += gy;
+                        v2 = fmaf(gx, dx, v2);
+                        v3 = fmaf(gy, dy, v3);
                     }
                     if (__ballot(any) != 0ull) {
-                        v0 = wave_sum_to_lane63(v0); v1 = wave_sum_to_lane63(v1);
-                        v2 = wave_sum_to_lane63(v2); v3 = wave_sum_to_lane63(v3);
-                        v4 = wave_sum_to_lane63(v4); v5 = wave_sum_to_lane63(v5);
-                        v6 = wave_sum_to_lane63(v6); v7 = wave_sum_to_lane63(v7);
-                        const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)id, j);
-                        if (lane == 63) {
-                            float *g = b.grad + 8 * (size_t)gid;
-                            atomicAdd(g + 0, v0); atomicAdd(g + 1, v1);
-                            atomicAdd(g + 2, v2); atomicAdd(g + 3, v3);
-                            atomicAdd(g + 4, v4); atomicAdd(g + 5, v5);
-                            atomicAdd(g + 6, v6); atomicAdd(g + 7, v7);
+                        v0 = octet_sum(v0); v1 = octet_sum(v1); v2 = octet_sum(v2); v3 = octet_sum(v3);
+                        v4 = octet_sum(v4); v5 = octet_sum(v5); v6 = octet_sum(v6); v7 = octet_sum(v7);
+                        if ((lane & 7) == 7) {
+                            float *dst = s_part + nslots * kSlotStride + octet * kOctStride;
+                            dst[0] = v0; dst[1] = v1; dst[2] = v2; dst[3] = v3;
+                            dst[4] = v4; dst[5] = v5; dst[6] = v6; dst[7] = v7;
+                        }
+                        if (lane == 0) s_gid[nslots] = (uint32_t)__builtin_amdgcn_readlane((int)id, j);
+                        if (++nslots == kSlots) {
+                            flush_slots(s_part, s_gid, kSlots, b.grad, lane);
+                            nslots = 0;
                         }
                     }
                 }
@@ -309,6 +327,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 cbeg -= kCompLanes;
             }
         }
+        if (nslots > 0) flush_slots(s_part, s_gid, nslots, b.grad, lane);
         if (!PERSISTENT) break;
         tile = pop_tile(a.queue);
     }

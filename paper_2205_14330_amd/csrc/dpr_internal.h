@@ -93,6 +93,16 @@ __device__ __forceinline__ int find_segment(const uint32_t *starts, int n, uint3
     return lo;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8).
+// This maps block b to a work index so that each XCD gets one contiguous range
+// of work items (neighbouring items share data, which then stays in one L2).
+// It is a bijection of [0, total).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t total) {
+    const uint32_t q = total >> 3, r = total & 7u;
+    const uint32_t x = b & 7u, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
 // Camera-space depth key, shared by the cull, the sort and the chain rule:
 // Z32 = fmaf(R20, x, fmaf(R21, y, fmaf(R22, z, t2))).
 __device__ __forceinline__ float depth_z(const float *R, const float *t, float x, float y, float z) {
@@ -110,6 +120,20 @@ __device__ __forceinline__ float splat_exponent(const SplatRec &s, float ux, flo
     dy = __fsub_rn(s.py, uy);
     float q = __fmaf_rn(s.a, __fmul_rn(dx, dx), __fmul_rn(s.b, __fmul_rn(dy, dy)));
     return __fsub_rn(s.w, q);
+}
+
+// Conservative test of whether any pixel centre of tile (tx, ty) can pass the
+// candidate predicate a dx^2 + b dy^2 <= thr of a splat centred at (px, py):
+// the quadratic form at the point of the tile's pixel-centre box closest to
+// the centre is a lower bound for every pixel of the tile.  Used identically
+// by the count and emit kernels, so both see the same (tile, splat) pairs.
+__device__ __forceinline__ bool splat_touches_tile(float px, float py, float a, float b, float thr, uint32_t tx,
+                                                   uint32_t ty) {
+    const float x0 = (float)(tx * kTile) + 0.5f, y0 = (float)(ty * kTile) + 0.5f;
+    const float cx = fminf(fmaxf(px, x0), x0 + (float)(kTile - 1));
+    const float cy = fminf(fmaxf(py, y0), y0 + (float)(kTile - 1));
+    const float dx = cx - px, dy = cy - py;
+    return a * dx * dx + b * dy * dy <= thr * (1.0f + 1.0f / 1024.0f) + 1.0e-6f;
 }
 
 }  // namespace dpr
@@ -149,15 +173,15 @@ uint64_t scan_partials(uint64_t n);
 
 // Binning.  cnt is chunk-major per view: cnt[cnt_off + c * tiles + t].
 hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                             const uint2 *rect, uint32_t *cnt, hipStream_t st);
+                             const uint2 *rect, const SplatRec *rec, float lambda, uint32_t *cnt, hipStream_t st);
 // In place: cnt[c][t] -> sum of cnt[c'][t] over c' < c; tile_total[tile] = column sum.
 // segs: scratch of sum over views of tiles * segments u32.
 hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, uint32_t *tile_total,
                                hipStream_t st);
 // tile_base = exclusive scan of tile_total (tiles + 1 entries).
 hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                            const uint2 *rect, const uint32_t *pre, const uint32_t *tile_base,
-                            uint32_t *pairs, hipStream_t st);
+                            const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
+                            const uint32_t *tile_base, uint32_t *pairs, hipStream_t st);
 
 struct CompositeArgs {
     const ViewDesc *views;

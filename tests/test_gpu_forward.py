@@ -116,10 +116,13 @@ def test_records_depth_keys_and_order(dpr):
 
 
 def test_tile_lists_are_exact(dpr):
-    """Each tile's list = the items whose tile rectangle covers it, ascending (key, item)."""
+    """Each tile's list holds, in ascending (key, item) order, exactly the items
+    whose tile rectangle covers the tile and whose ellipse can reach one of the
+    tile's pixel centres (checked with a small margin on either side)."""
     torch = __import__("torch")
     sc, cam = _scene_cam(51, n=3000, size=(100, 70))
-    plan = gpu_plan([sc], [(0, cam)], dpr.RenderParams())
+    params = dpr.RenderParams()
+    plan = gpu_plan([sc], [(0, cam)], params)
     inf = plan.info()
     ws = plan.plan_ws
     M = inf.items
@@ -128,21 +131,42 @@ def test_tile_lists_are_exact(dpr):
     keys = np.empty_like(skeys)
     keys[order] = skeys
     rect = to_np(ws[inf.rect_off: inf.rect_off + 8 * M].view(torch.int32)).view(np.uint32).reshape(M, 2)
+    rec = to_np(ws[inf.rec_off: inf.rec_off + 32 * M].view(torch.float32)).reshape(M, 8).astype(np.float64)
+    lam = -np.log2(params.alpha_min)
     tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
     rng_ = to_np(ws[inf.range_off: inf.range_off + 4 * (tx * ty + 1)].view(torch.int32)).view(np.uint32)
     pairs = to_np(plan.ws[inf.pairs_off: inf.pairs_off + 4 * inf.pairs].view(torch.int32)).view(np.uint32)
     assert rng_[-1] == inf.pairs
-    expect = {t: [] for t in range(tx * ty)}
+    cover = {t: [] for t in range(tx * ty)}
     for g in range(M):
         x0, y0 = rect[g, 0] & 0xFFFF, rect[g, 0] >> 16
         x1, y1 = rect[g, 1] & 0xFFFF, rect[g, 1] >> 16
         for yy in range(y0, y1):
             for xx in range(x0, x1):
-                expect[yy * tx + xx].append((keys[g], g))
+                cover[yy * tx + xx].append((keys[g], g))
+
+    def qmin(g, t):
+        px, py, a, b, w = rec[g, :5]
+        X0, Y0 = (t % tx) * 16 + 0.5, (t // tx) * 16 + 0.5
+        cx, cy = min(max(px, X0), X0 + 15), min(max(py, Y0), Y0 + 15)
+        return a * (cx - px) ** 2 + b * (cy - py) ** 2, w + lam
+
+    dropped = 0
     for t in range(tx * ty):
-        s, e = rng_[t], rng_[t + 1]
-        want = [g for _, g in sorted(expect[t])]
-        assert pairs[s:e].tolist() == want, t
+        got = pairs[rng_[t]: rng_[t + 1]].tolist()
+        full = [g for _, g in sorted(cover[t])]
+        # order: a subsequence of the rect-covering list
+        it = iter(full)
+        assert all(g in it for g in got), t
+        keep = set(got)
+        for g in full:
+            q, thr = qmin(g, t)
+            if g in keep:
+                assert q <= thr * (1 + 2e-3) + 1e-5, (t, g, q, thr)
+            else:
+                dropped += 1
+                assert q > thr * (1 - 2e-3) - 1e-5, (t, g, q, thr)
+    assert dropped > 0
 
 
 def test_empty_and_culled_scenes(dpr):
