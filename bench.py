@@ -14,7 +14,6 @@ blended-splat counts) and the FP64 CPU oracle timed on one step's views.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -37,27 +36,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2205_14330_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel sources; else None."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
+    profiles/traffic_<workload>.json, if it was taken on the current kernel
+    sources; else None."""
+    from paper_2205_14330_amd.profiling import kernel_source_hash
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
-    except Exception:
+    except (OSError, ValueError):
         return None
-    e = d.get(workload, {}).get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    e = d.get("kernels", {}).get(kernel)
+    if not e or d.get("source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
 
@@ -92,6 +84,10 @@ def main():
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (reference for HBM counters)")
+    ap.add_argument("--workload", choices=["train", "dynamic", "serve"], default="train")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the serving trace (train: short leg in the same JSON line; 0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this renderer runs on one GPU; --gpus above 1 is not supported "
@@ -107,8 +103,16 @@ def main():
         sys.exit(1)
     dpr.load()
     dev = torch.device("cuda:0")
+    if args.workload == "dynamic":
+        return bench_dynamic(args)
+    if args.workload == "serve":
+        out = {"metric": "served p50/p99 latency and Mpix/s (16 resident scenes, Poisson requests)",
+               "n_gpus": 1, "dtype": "f32", "data": "synthetic"}
+        out.update(bench_serving(args.serve_seconds if args.serve_seconds > 0 else 60.0, args.serve_rate))
+        print(json.dumps(out), flush=True)
+        return
     V, S = args.views, args.size
-    scene_np, cams, gt_np = workloads.config3(n=args.points, size=S, views_per_step=V, steps=100)
+    scene_np, cams, gt_np = workloads.surface300k_4x800(n=args.points, size=S, views_per_step=V, steps=100)
     scene = dpr.SceneTensors.from_numpy(scene_np, dev)
     gt = dpr.SceneTensors.from_numpy(gt_np, dev)
     nsteps = args.warmup + args.steps
@@ -133,43 +137,61 @@ def main():
             plan.backward(g, None)
         return plan
 
-    def timed(params, backward, steps, warmup):
-        for k in range(warmup):
-            step(k, params, backward)
+    def timed(params, backward, steps, warmup, collect=None):
+        """Times `steps` steps after `warmup`.  At most two plans are alive (the
+        caching allocator reuses their memory); a plan is inspected and freed
+        once the next plan's host sync has passed its work."""
+        prev = None
+        for k in range(warmup):              # same two-live-plans pattern as the timed loop
+            plan = step(k, params, backward)
+            if prev is not None:
+                prev.free()
+            prev = plan
+        if prev is not None:
+            prev.free()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plans = [step(warmup + k, params, backward) for k in range(steps)]
+        prev = None
+        for k in range(steps):
+            plan = step(warmup + k, params, backward)
+            if prev is not None:
+                if collect:
+                    collect(prev)
+                prev.free()
+            prev = plan
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, plans
+        dt = time.perf_counter() - t0
+        if collect:
+            collect(prev)
+        prev.free()
+        return dt
 
     pix_step = V * S * S
     base = dict(persistent=args.persistent)
     # main metric: forward + backward (stored T), with stage timing and blend counts
-    t_fb, plans = timed(dpr.RenderParams(timing=True, stats=True, **base), True, args.steps, args.warmup)
     stage_ms = {s: 0.0 for s in dpr.STAGES}
-    blends = 0
-    pairs = 0
-    for p in plans:
-        for s, v in p.stage_times().items():
+    blend_acc = torch.zeros((), dtype=torch.int64, device=dev)
+    pair_acc = [0]
+
+    def collect(p):
+        for s_, v in p.stage_times().items():
             if v > 0:
-                stage_ms[s] += v
+                stage_ms[s_] += v
         inf = p.info()
-        blends += int(p.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32).sum().item())
-        pairs += inf.pairs
-        p.free()
-    del plans
+        blend_acc.add_(p.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32).sum())
+        pair_acc[0] += inf.pairs
+
+    t_fb = timed(dpr.RenderParams(timing=True, stats=True, **base), True, args.steps, args.warmup, collect)
+    blends = int(blend_acc.item())
+    pairs = pair_acc[0]
     K = args.steps
     mpix_fb = pix_step * K / t_fb / 1e6
     log(f"fwd+bwd: {t_fb / K * 1e3:.3f} ms/step, {mpix_fb:.1f} Mpix/s")
     log("stage ms/step: " + ", ".join(f"{s}={v / K:.3f}" for s, v in stage_ms.items()))
 
-    t_f, plans = timed(dpr.RenderParams(**base), False, K, args.warmup)
-    for p in plans:
-        p.free()
+    t_f = timed(dpr.RenderParams(**base), False, K, args.warmup)
     mpix_f = pix_step * K / t_f / 1e6
-    t_r, plans = timed(dpr.RenderParams(bwd_mode="recompute", **base), True, K, args.warmup)
-    for p in plans:
-        p.free()
+    t_r = timed(dpr.RenderParams(bwd_mode="recompute", **base), True, K, args.warmup)
     mpix_r = pix_step * K / t_r / 1e6
     log(f"fwd: {mpix_f:.1f} Mpix/s; fwd+bwd recompute: {mpix_r:.1f} Mpix/s")
 
@@ -182,12 +204,12 @@ def main():
         achieved = ops / t_launch / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
                 "unit": "Tlane-op/s", "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4),
-                "traffic": load_traffic(dom, "config3"),
+                "traffic": load_traffic(dom, "surface300k_4x800"),
                 "per_unit": f"{comp[dom]} lane-ops per blended (pixel, splat)",
                 "units_per_launch": blends / K, "launch_ms": round(t_launch * 1e3, 4)}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": None, "traffic": load_traffic(dom, "config3")}
+                "frac": None, "traffic": load_traffic(dom, "surface300k_4x800")}
 
     if args.copy_calibration_mib > 0:
         src = torch.empty(args.copy_calibration_mib * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -204,6 +226,12 @@ def main():
         cpu = cpu_baseline(scene_np, step_views[0], lambda v: t_np[v])
         log(f"cpu baseline: {cpu}")
 
+    serving = None
+    if args.serve_seconds > 0:
+        del targets
+        torch.cuda.empty_cache()
+        serving = bench_serving(args.serve_seconds, args.serve_rate)
+
     out = {
         "metric": METRIC, "value": round(mpix_fb, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(t_fb / K * 1e3, 4), "higher_is_better": True,
@@ -216,9 +244,90 @@ def main():
         "fwd_bwd_recompute_mpix_s": round(mpix_r, 2),
         "stage_ms_per_step": {s: round(v / K, 4) for s, v in stage_ms.items()},
         "pairs_per_step": pairs / K, "blended_per_step": blends / K,
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_dynamic(args):
+    """30 frames x 200k points, one 1024x768 view per frame, all frames in one
+    plan: forward + backward per step."""
+    import torch
+    import workloads
+    import paper_2205_14330_amd as dpr
+    scenes_np, cams, trng = workloads.dynamic30x200k_1024x768()
+    scenes = [dpr.SceneTensors.from_numpy(s) for s in scenes_np]
+    F = len(cams)
+    views = [(t, cams[t]) for t in range(F)]
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    targets = [torch.rand((c.height, c.width, 3), device="cuda", generator=gen) for c in cams]
+    out = {}
+    for persistent in (False, True):
+        def step(params):
+            plan = dpr.Plan(scenes, views, params)
+            plan.forward()
+            plan.backward([(2.0 * (plan.images[t] - targets[t])).contiguous() for t in range(F)], None)
+            return plan
+        params = dpr.RenderParams(timing=True, persistent=persistent)
+        for _ in range(args.warmup):
+            step(params).free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plans = [step(params) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        st = {k: 0.0 for k in dpr.STAGES}
+        for p in plans:
+            for k, v in p.stage_times().items():
+                st[k] += max(v, 0.0) / args.steps
+            p.free()
+        px = sum(c.pixels for c in cams)
+        out["persistent" if persistent else "grid"] = {
+            "ms_per_step": round(dt * 1e3, 3), "mpix_s": round(px / dt / 1e6, 1),
+            "stage_ms": {k: round(v, 3) for k, v in st.items() if v > 0}}
+        log(f"dynamic persistent={persistent}: {dt * 1e3:.2f} ms/step")
+    best = min(out.values(), key=lambda d: d["ms_per_step"])
+    print(json.dumps({"metric": "Mpix/s fwd+bwd, 30 frames x 200k points, 1024x768, one launch per stage",
+                      "value": best["mpix_s"], "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": best["ms_per_step"], "higher_is_better": True,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "30 frames x 200k points (sinusoidal motion), SH degree 2, "
+                                             "one 1024x768 orbit view per frame, forward + backward"},
+                      "modes": out}), flush=True)
+
+
+def bench_serving(seconds: float, rate: float) -> dict:
+    """16 resident scenes, Poisson requests of mixed resolution: continuous
+    batching on 2 streams vs one view per launch on one stream, same trace."""
+    import torch
+    import workloads
+    import paper_2205_14330_amd as dpr
+    from paper_2205_14330_amd.serving import Request, RendererExecutor, Server, latency_stats
+    scenes = [dpr.SceneTensors.from_numpy(s) for s in workloads.serving_scenes()]
+    trace = workloads.serving_trace(n_scenes=len(scenes), rate=rate, duration=seconds)
+    budget = 16 << 30
+    res = {"trace": {"seconds": seconds, "rate_per_s": rate, "requests": len(trace),
+                     "offered_mpix_s": round(sum(r.camera.pixels for r in trace) / seconds / 1e6, 1),
+                     "points": [s.n for s in scenes]}, "hbm_budget_bytes": budget}
+    # warm up both paths
+    for slots, mv in ((2, 32), (1, 1)):
+        srv = Server(RendererExecutor(scenes, n_slots=slots), hbm_budget=budget, max_views=mv)
+        srv.run_trace(trace[:20], lambda i, tr: Request(i, tr.scene, tr.camera, 0.0))
+    torch.cuda.synchronize()
+    for name, slots, mv in (("continuous_batching", 2, 32), ("one_view_per_launch", 1, 1)):
+        srv = Server(RendererExecutor(scenes, n_slots=slots), hbm_budget=budget, max_views=mv)
+        t0 = time.perf_counter()
+        done = srv.run_trace(trace, lambda i, tr: Request(i, tr.scene, tr.camera, 0.0))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = latency_stats(done, wall)
+        st["mean_batch"] = round(float(np.mean(srv.batches)), 2)
+        st["max_batch"] = int(max(srv.batches))
+        st["peak_hbm_bytes"] = int(srv.peak_in_use)
+        res[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+        log(f"serving {name}: p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
+            f"{st['served_mpix_s']:.1f} Mpix/s, mean batch {st['mean_batch']}")
+    return res
 
 
 if __name__ == "__main__":

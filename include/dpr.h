@@ -106,7 +106,8 @@ enum { DPR_BWD_STORED = 0, DPR_BWD_RECOMPUTE = 1 };
 enum {
     DPR_FLAG_TIMING = 1,      /* record HIP events around every stage (dpr_stage_times)    */
     DPR_FLAG_STATS = 2,       /* count blended splats per pixel (dpr_plan_info.stats_off)  */
-    DPR_FLAG_PERSISTENT = 4   /* compositing kernels pop tiles from a work queue           */
+    DPR_FLAG_PERSISTENT = 4   /* forward compositing pops tiles from a work queue (the
+                                 backward always does)                                      */
 };
 
 typedef struct dpr_params {

@@ -451,9 +451,9 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
 
     {
         StageScope sc_(p, DPR_STAGE_UPLOAD, st);
-        STAGE_TRY(hipMemcpyAsync(w + lay.views.off, p->vdesc.data(), sizeof(ViewDesc) * V, hipMemcpyHostToDevice, st));
-        STAGE_TRY(hipMemcpyAsync(w + lay.scenes.off, p->sdesc.data(), sizeof(SceneDesc) * S, hipMemcpyHostToDevice, st));
-        STAGE_TRY(hipMemcpyAsync(w + lay.u32tab.off, p->u32tab.data(), 4 * p->u32tab.size(), hipMemcpyHostToDevice, st));
+        STAGE_TRY(upload_async(w + lay.views.off, p->vdesc.data(), sizeof(ViewDesc) * V, st));
+        STAGE_TRY(upload_async(w + lay.scenes.off, p->sdesc.data(), sizeof(SceneDesc) * S, st));
+        STAGE_TRY(upload_async(w + lay.u32tab.off, p->u32tab.data(), 4 * p->u32tab.size(), st));
     }
     {
         StageScope sc_(p, DPR_STAGE_PROJECT, st);
@@ -521,8 +521,8 @@ int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
     a.queue = reinterpret_cast<uint32_t *>(w + f.queue.off);
     const bool persistent = (p->params.flags & DPR_FLAG_PERSISTENT) != 0;
     {
-        StageScope sc_(p, DPR_STAGE_COMPOSITE_FWD, st);
         if (persistent) HIP_TRY(launch_fill_u32(a.queue, 0u, 4, st));
+        StageScope sc_(p, DPR_STAGE_COMPOSITE_FWD, st);
         HIP_TRY(launch_composite_fwd(a, persistent, st));
     }
     p->forward_done = 1;
@@ -569,8 +569,8 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
         p->sdesc_bwd[s].dsh = dL_dsh ? dL_dsh[s] : nullptr;
         p->sdesc_bwd[s].dopacity = dL_dopacity ? dL_dopacity[s] : nullptr;
     }
-    HIP_TRY(hipMemcpyAsync(bw + bl.tabs.off, p->bwd_tab.data(), 8 * p->bwd_tab.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(bw + bl.sgrad.off, p->sdesc_bwd.data(), sizeof(SceneDesc) * S, hipMemcpyHostToDevice, st));
+    HIP_TRY(upload_async(bw + bl.tabs.off, p->bwd_tab.data(), 8 * p->bwd_tab.size(), st));
+    HIP_TRY(upload_async(bw + bl.sgrad.off, p->sdesc_bwd.data(), sizeof(SceneDesc) * S, st));
 
     CompositeArgs a = composite_args(p, ws);
     const bool persistent = (p->params.flags & DPR_FLAG_PERSISTENT) != 0;
@@ -583,8 +583,8 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
         a.nlast = reinterpret_cast<uint32_t *>(bw + bl.nlast.off);
         a.tfinal = reinterpret_cast<float *>(bw + bl.tfin.off);
         a.queue = queue;
-        StageScope sc_(p, DPR_STAGE_RECOMPUTE, st);
         if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 4, st));
+        StageScope sc_(p, DPR_STAGE_RECOMPUTE, st);
         HIP_TRY(launch_recompute(a, persistent, st));
         b.nlast = a.nlast;
         b.tfinal = a.tfinal;
@@ -600,10 +600,12 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
     a.queue = queue;
     b.c = a;
     {
-        StageScope sc_(p, DPR_STAGE_COMPOSITE_BWD, st);
+        // the backward always runs as a persistent work queue: its tiles are
+        // long and uneven, and dynamic assignment balances them best
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(b.grad), 0u, 8ull * p->sz.items, st));
-        if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 4, st));
-        HIP_TRY(launch_composite_bwd(b, persistent, st));
+        HIP_TRY(launch_fill_u32(queue, 0u, 4, st));
+        StageScope sc_(p, DPR_STAGE_COMPOSITE_BWD, st);
+        HIP_TRY(launch_composite_bwd(b, true, st));
     }
     {
         Tables tb = make_tables(p);

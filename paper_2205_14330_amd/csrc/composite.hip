@@ -375,6 +375,38 @@ hipError_t launch_composite_bwd(const BackwardArgs &b, bool persistent, hipStrea
     return hipGetLastError();
 }
 
+// Small host tables travel inside the kernel-argument buffer of this kernel,
+// so their upload is ordered on the stream and never blocks the host (unlike
+// a copy from pageable host memory).
+constexpr int kUploadWords = 960;
+struct UploadChunk {
+    uint32_t nwords;
+    uint32_t words[kUploadWords];
+};
+
+__global__ void k_upload(uint32_t *dst, UploadChunk c) {
+    for (uint32_t i = threadIdx.x; i < c.nwords; i += blockDim.x) dst[i] = c.words[i];
+}
+
+hipError_t upload_async(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    if (bytes % 4 != 0) return hipErrorInvalidValue;
+    const uint32_t *s = static_cast<const uint32_t *>(src);
+    uint32_t *d = static_cast<uint32_t *>(dst);
+    size_t n = bytes / 4;
+    while (n > 0) {
+        UploadChunk c;
+        c.nwords = (uint32_t)(n < (size_t)kUploadWords ? n : (size_t)kUploadWords);
+        for (uint32_t i = 0; i < c.nwords; ++i) c.words[i] = s[i];
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, st, d, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        s += c.nwords;
+        d += c.nwords;
+        n -= c.nwords;
+    }
+    return hipSuccess;
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, uint64_t n) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;

@@ -215,5 +215,7 @@ hipError_t launch_point_bwd(const Tables &tb, const Thresholds &th, int sh_degre
                             const float *grad, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st);
+// Stream-ordered copy of a small host table (bytes % 4 == 0) through kernel arguments.
+hipError_t upload_async(void *dst, const void *src, size_t bytes, hipStream_t st);
 
 }  // namespace dpr

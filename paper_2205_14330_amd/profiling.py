@@ -1,0 +1,137 @@
+"""Summaries of rocprofv3 output for the renderer's kernels.
+
+kernel_stats():  per-kernel call count and average/min/max duration from a
+                 ``--kernel-trace --stats`` run (``*_kernel_stats.csv``).
+pmc_traffic():   HBM bytes per launch from two ``--pmc FETCH_SIZE`` and
+                 ``--pmc WRITE_SIZE`` runs (``*_counter_collection.csv``, KiB
+                 per dispatch).  Each counter is scaled by what it reads for a
+                 plain device copy of known size made in the same run (the
+                 largest ``copyBuffer`` dispatch), so the result is in bytes
+                 actually moved.
+
+Usage:
+  python -m paper_2205_14330_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>"
+  python -m paper_2205_14330_amd.profiling traffic <fetch.csv> <write.csv> <copy MiB> <out.json> "<command>"
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# short names of the library's kernels (demangled prefix -> name)
+KERNELS = {
+    "dpr::k_project": "project",
+    "dpr::k_radix_hist": "radix_hist",
+    "dpr::k_radix_scatter": "radix_scatter",
+    "dpr::k_scan_reduce": "scan_reduce",
+    "dpr::k_scan_partials": "scan_partials",
+    "dpr::k_scan_down": "scan_down",
+    "dpr::k_tile_count": "tile_count",
+    "dpr::k_col_segsum": "col_segsum",
+    "dpr::k_col_segscan": "col_segscan",
+    "dpr::k_col_down": "col_down",
+    "dpr::k_tile_emit": "tile_emit",
+    "dpr::k_composite<true": "composite_fwd",
+    "dpr::k_composite<false": "recompute",
+    "dpr::k_composite_bwd": "composite_bwd",
+    "dpr::k_point_bwd": "point_bwd",
+    "dpr::k_fill_u32": "fill",
+}
+
+
+def short_name(full: str) -> str:
+    name = full.replace("void ", "")
+    for k, v in KERNELS.items():
+        if name.startswith(k):
+            return v
+    return name.split("(")[0][:48]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def kernel_stats(stats_csv: str):
+    agg = collections.OrderedDict()
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows:
+        n = short_name(r["Name"])
+        e = agg.setdefault(n, {"calls": 0, "total_ns": 0.0, "min_ns": float("inf"), "max_ns": 0.0})
+        e["calls"] += int(r["Calls"])
+        e["total_ns"] += float(r["TotalDurationNs"])
+        e["min_ns"] = min(e["min_ns"], float(r["MinNs"]))
+        e["max_ns"] = max(e["max_ns"], float(r["MaxNs"]))
+    for e in agg.values():
+        e["avg_ns"] = e["total_ns"] / max(e["calls"], 1)
+    return agg
+
+
+def write_stats_txt(stats_csv: str, out_txt: str, command: str):
+    agg = kernel_stats(stats_csv)
+    tot = sum(e["total_ns"] for e in agg.values())
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", f"# kernel sources: {kernel_source_hash()}",
+             "", f"{'kernel':48s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
+    for n, e in agg.items():
+        lines.append(f"{n:48s} {e['calls']:6d} {e['avg_ns'] / 1e3:10.2f} {e['min_ns'] / 1e3:10.2f} "
+                     f"{e['max_ns'] / 1e3:10.2f} {100 * e['total_ns'] / tot:6.1f}")
+    open(out_txt, "w").write("\n".join(lines) + "\n")
+    return agg
+
+
+def _per_dispatch(counter_csv: str):
+    out = collections.defaultdict(list)
+    copies = []
+    for r in csv.DictReader(open(counter_csv)):
+        v = float(r["Counter_Value"]) * 1024.0
+        if "copyBuffer" in r["Kernel_Name"]:
+            copies.append(v)
+        out[short_name(r["Kernel_Name"])].append(v)
+    return out, copies
+
+
+def pmc_traffic(fetch_csv: str, write_csv: str, copy_mib: float):
+    f, fc = _per_dispatch(fetch_csv)
+    w, wc = _per_dispatch(write_csv)
+    known = copy_mib * (1 << 20)
+    f_scale = known / max(fc) if fc else 1.0
+    w_scale = known / max(wc) if wc else 1.0
+    res = {}
+    for k in sorted(set(f) | set(w)):
+        fb = sum(f.get(k, [0])) / max(len(f.get(k, [])), 1) * f_scale
+        wb = sum(w.get(k, [0])) / max(len(w.get(k, [])), 1) * w_scale
+        res[k] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                  "dispatches": max(len(f.get(k, [])), len(w.get(k, [])))}
+    return res, f_scale, w_scale
+
+
+def main(argv):
+    if len(argv) >= 4 and argv[0] == "stats":
+        agg = write_stats_txt(argv[1], argv[2], argv[3])
+        print(json.dumps({k: round(v["avg_ns"] / 1e3, 2) for k, v in agg.items()}))
+    elif len(argv) >= 6 and argv[0] == "traffic":
+        res, fs, ws = pmc_traffic(argv[1], argv[2], float(argv[3]))
+        doc = {"command": argv[5], "source_hash": kernel_source_hash(), "fetch_scale": fs, "write_scale": ws,
+               "kernels": {k: {kk: round(vv, 1) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                           for k, v in res.items()}}
+        json.dump(doc, open(argv[4], "w"), indent=1)
+        print(f"fetch scale {fs:.3f}, write scale {ws:.3f}")
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

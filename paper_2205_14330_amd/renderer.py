@@ -11,6 +11,7 @@ import ctypes
 import dataclasses
 from typing import List, Optional, Sequence, Tuple
 
+import numpy as np
 import torch
 
 from . import _abi
@@ -71,8 +72,8 @@ class SceneTensors:
 def camera_struct(cam) -> _abi.Camera:
     """``cam``: any object with R (3x3), t (3), fx, fy, cx, cy, width, height."""
     c = _abi.Camera()
-    R = [float(v) for v in torch.as_tensor(cam.R, dtype=torch.float32).reshape(9).tolist()]
-    t = [float(v) for v in torch.as_tensor(cam.t, dtype=torch.float32).reshape(3).tolist()]
+    R = np.asarray(cam.R, dtype=np.float32).reshape(9).tolist()
+    t = np.asarray(cam.t, dtype=np.float32).reshape(3).tolist()
     c.R[:] = R
     c.t[:] = t
     c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)

@@ -145,12 +145,12 @@ def test_autograd_function_matches_oracle(dpr):
         compare_grads(to_np(op.grad), ref.opacity, f"{mode} autograd dopacity")
 
 
-def test_config2_gradients_restricted_pixels(dpr):
+def test_ball100k_gradients_restricted_pixels(dpr):
     """100k points, 8 views of 400x400, L2 loss against the seeded targets,
     restricted to 4096 random pixels per view (the oracle computes exactly the
     same loss); all gradients and the 256-point subset are checked."""
     import torch
-    sc, cams, targets, subset = workloads.config2()
+    sc, cams, targets, subset = workloads.ball100k_8x400()
     views = [(0, c) for c in cams]
     params = dpr.RenderParams()
     plan = gpu_plan([sc], views, params)
@@ -167,9 +167,9 @@ def test_config2_gradients_restricted_pixels(dpr):
     got = [to_np(t) for t in out[0]]
     ref = oracle.backward(sc, cams, [g.reshape(-1, 3)[p] for g, p in zip(gI, pix)], None, params=oparams(params),
                           pixels=pix)
-    compare_grads(got[0], ref.xyz, "c2 dxyz")
-    compare_grads(got[1], ref.sh, "c2 dsh")
-    compare_grads(got[2], ref.opacity, "c2 dopacity")
-    compare_grads(got[0][subset], ref.xyz[subset], "c2 subset dxyz")
-    compare_grads(got[1][subset], ref.sh[subset], "c2 subset dsh")
-    compare_grads(got[2][subset], ref.opacity[subset], "c2 subset dopacity")
+    compare_grads(got[0], ref.xyz, "ball100k dxyz")
+    compare_grads(got[1], ref.sh, "ball100k dsh")
+    compare_grads(got[2], ref.opacity, "ball100k dopacity")
+    compare_grads(got[0][subset], ref.xyz[subset], "ball100k subset dxyz")
+    compare_grads(got[1][subset], ref.sh[subset], "ball100k subset dsh")
+    compare_grads(got[2][subset], ref.opacity[subset], "ball100k subset dopacity")

@@ -46,10 +46,10 @@ def _render_check(dpr, scenes, views, params, label="", pixels_per_view=None):
     return plan
 
 
-def test_config1_forward_parity(dpr):
+def test_cube4k_forward_parity(dpr):
     """4096 points, one 128x128 view at distance 3: full frame vs the oracle."""
-    sc, cams = workloads.config1()
-    _render_check(dpr, [sc], [(0, cams[0])], dpr.RenderParams(), "c1")
+    sc, cams = workloads.cube4k_128px()
+    _render_check(dpr, [sc], [(0, cams[0])], dpr.RenderParams(), "cube4k")
 
 
 @pytest.mark.parametrize("deg,frame", [(0, 0), (1, 1), (2, 0), (2, 1), (3, 0)])
@@ -268,15 +268,15 @@ def test_stats_count_blended_splats(dpr):
     assert abs(int(st.sum()) - int(ref.ncontrib.sum())) <= 0.001 * ref.ncontrib.sum() + 5
 
 
-def test_config2_forward_parity_sampled(dpr):
+def test_ball100k_forward_parity_sampled(dpr):
     """100k points, 8 views of 400x400: 2 full frames + 4096 pixels of every view."""
-    sc, cams, _, _ = workloads.config2()
+    sc, cams, _, _ = workloads.ball100k_8x400()
     views = [(0, c) for c in cams]
     plan = gpu_plan([sc], views, dpr.RenderParams())
     for v, (_, cam) in enumerate(views):
         pix = None if v < 2 else random_pixels(200 + v, cam, 4096)
         ref = oracle.render(sc, cam, pixels=pix)
-        compare_images(to_np(plan.images[v]), to_np(plan.trans[v]), ref, pixels=pix, label=f"c2 view {v}")
+        compare_images(to_np(plan.images[v]), to_np(plan.trans[v]), ref, pixels=pix, label=f"ball100k view {v}")
 
 
 def test_render_forward_1_convenience(dpr):

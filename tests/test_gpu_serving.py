@@ -1,0 +1,89 @@
+"""GPU tests of the serving form: each served request equals the same request
+rendered alone (bitwise), a served result matches the oracle, and admission
+under a small HBM budget keeps batches small."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import Camera
+
+from _gpu_util import compare_images, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_14330_amd as dpr
+    dpr.load()
+    scenes_np = [workloads.small_scene(200 + s, n, extent=0.8) for s, n in enumerate([3000, 7000, 500])]
+    scenes = [dpr.SceneTensors.from_numpy(s) for s in scenes_np]
+    return dpr, scenes_np, scenes
+
+
+def _trace(n, rate, seed):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    sizes = [(40, 40), (64, 48), (17, 33), (96, 80), (128, 72)]
+    out = []
+    for i in range(n):
+        w, h = sizes[int(rng.integers(len(sizes)))]
+        out.append(workloads.Request(float(t[i]), int(rng.integers(3)),
+                                                                  workloads.random_sphere_camera(rng, w, h)))
+    return out
+
+
+def _serve(dpr, scenes, trace, budget, max_views=16, slots=2):
+    from paper_2205_14330_amd.serving import Request, RendererExecutor, Server
+    ex = RendererExecutor(scenes, n_slots=slots)
+    srv = Server(ex, hbm_budget=budget, max_views=max_views)
+    done = srv.run_trace(trace, lambda i, tr: Request(i, tr.scene, tr.camera, 0.0))
+    return srv, sorted(done, key=lambda r: r.rid)
+
+
+def test_served_requests_equal_their_solo_render_bitwise(env):
+    import torch
+    dpr, scenes_np, scenes = env
+    trace = _trace(40, 2000.0, 1)
+    srv, done = _serve(dpr, scenes, trace, budget=8 << 30)
+    torch.cuda.synchronize()
+    assert len(done) == 40 and all(r.error is None for r in done)
+    assert max(srv.batches) > 1                      # some batching happened
+    for r in done:
+        alone = dpr.Plan([scenes[r.scene]], [(0, r.camera)], dpr.RenderParams(bwd_mode="recompute"),
+                         trans=[None])
+        alone.forward()
+        torch.cuda.synchronize()
+        assert torch.equal(alone.images[0], r.image), r.rid
+        assert r.latency > 0
+
+
+def test_served_result_matches_oracle(env):
+    import torch
+    dpr, scenes_np, scenes = env
+    trace = _trace(6, 500.0, 2)
+    srv, done = _serve(dpr, scenes, trace, budget=8 << 30)
+    torch.cuda.synchronize()
+    for r in done[:3]:
+        ref = oracle.render(scenes_np[r.scene], r.camera)
+        img = to_np(r.image)
+        assert np.abs(img - ref.image).max() <= 1e-4
+
+
+def test_small_budget_limits_batches(env):
+    import torch
+    dpr, scenes_np, scenes = env
+    from paper_2205_14330_amd.serving import RendererExecutor
+    trace = _trace(24, 5000.0, 3)
+    ex = RendererExecutor(scenes)
+    from paper_2205_14330_amd.serving import Request
+    one = max(ex.request_bytes(Request(0, t.scene, t.camera, 0.0)) for t in trace)
+    srv, done = _serve(dpr, scenes, trace, budget=2 * one)
+    torch.cuda.synchronize()
+    assert len(done) == 24 and all(r.error is None for r in done)
+    assert srv.peak_in_use <= 2 * one                # the budget holds (exact bytes after planning)
+    assert max(srv.batches) <= 3                     # and keeps batches small

@@ -25,8 +25,8 @@ import numpy as np
 __all__ = [
     "Camera", "Scene", "seed_rng", "fov_focal", "look_at_camera",
     "random_sphere_camera", "orbit_camera", "random_scene_uniform_cube",
-    "config1", "config2", "config3", "config4", "config5_scenes",
-    "config5_trace", "small_scene", "SH_COEFFS",
+    "cube4k_128px", "ball100k_8x400", "surface300k_4x800", "dynamic30x200k_1024x768", "serving_scenes",
+    "serving_trace", "small_scene", "SH_COEFFS", "Request",
 ]
 
 SH_COEFFS = {0: 1, 1: 4, 2: 9, 3: 16}
@@ -80,9 +80,9 @@ class Scene:
         return {v: d for d, v in SH_COEFFS.items()}[k]
 
 
-def seed_rng(config_index: int) -> np.random.Generator:
-    """Generator for configuration c (1-based): child c-1 of SeedSequence(0)."""
-    return np.random.default_rng(np.random.SeedSequence(0, spawn_key=(config_index - 1,)))
+def seed_rng(stream: int) -> np.random.Generator:
+    """Generator of workload stream s (1-based): child s-1 of SeedSequence(0)."""
+    return np.random.default_rng(np.random.SeedSequence(0, spawn_key=(stream - 1,)))
 
 
 def fov_focal(width: int, fov_deg: float = 50.0) -> float:
@@ -157,10 +157,11 @@ def small_scene(seed: int, n: int, sh_degree: int = 2, radius: float = 0.02,
 
 
 # ----------------------------------------------------------------------------
-# The five workload shapes.
+# Workload shapes (sizes follow the paper's scenes: tens to hundreds of
+# thousands of points, 128^2 to 1080p views, 1 to 30 frames).
 # ----------------------------------------------------------------------------
 
-def config1():
+def cube4k_128px():
     """4096 points uniform in [-1,1]^3, SH degree 2 ~ N(0, 0.3), opacity
     sigmoid(N(0,1)), radius 0.02; one camera at distance 3 looking at the
     origin (R = I, t = (0,0,3)), fov 50 deg, 128x128."""
@@ -171,7 +172,7 @@ def config1():
     return scene, [cam]
 
 
-def config2(n: int = 100_000, views: int = 8, size: int = 400):
+def ball100k_8x400(n: int = 100_000, views: int = 8, size: int = 400):
     """100k points uniform in the unit ball; 8 random views on the radius-3
     sphere at 400x400; uniform random targets; a 256-point gradient subset."""
     rng = seed_rng(2)
@@ -213,7 +214,7 @@ def _surface_scene(rng, n, frac_on_surface, bumps=None, jitter=0.01):
     return Scene(xyz.astype(np.float32), sh, op, np.full(n, 0.02, np.float32)), bumps
 
 
-def config3(n: int = 300_000, size: int = 800, views_per_step: int = 4, steps: int = 100):
+def surface300k_4x800(n: int = 300_000, size: int = 800, views_per_step: int = 4, steps: int = 100):
     """300k points uniform in [-1,1]^3, the first 30% moved onto a random
     surface z = sum of 20 Gaussian bumps (+ N(0, 0.01^2)); SH degree 2;
     4 views per step at 800x800 for 100 steps."""
@@ -226,7 +227,7 @@ def config3(n: int = 300_000, size: int = 800, views_per_step: int = 4, steps: i
     return scene, cams, gt
 
 
-def config4(frames: int = 30, n: int = 200_000, width: int = 1024, height: int = 768):
+def dynamic30x200k_1024x768(frames: int = 30, n: int = 200_000, width: int = 1024, height: int = 768):
     """30 frames of 200k points moved by a smooth sinusoidal displacement
     field; SH shared across frames; one orbit view per frame at 1024x768."""
     rng = seed_rng(4)
@@ -249,7 +250,7 @@ def config4(frames: int = 30, n: int = 200_000, width: int = 1024, height: int =
 RESOLUTIONS = [(256, 256), (512, 512), (800, 800), (1280, 720), (1920, 1080)]
 
 
-def config5_scenes(count: int = 16, scale: float = 1.0):
+def serving_scenes(count: int = 16, scale: float = 1.0):
     """16 resident scenes with log-uniform point counts in [5e4, 5e5], each
     drawn with the surface generator under its own seed."""
     rng = seed_rng(5)
@@ -269,7 +270,7 @@ class Request:
     camera: Camera
 
 
-def config5_trace(n_scenes: int = 16, rate: float = 200.0, duration: float = 60.0,
+def serving_trace(n_scenes: int = 16, rate: float = 200.0, duration: float = 60.0,
                   seed_key: int = 0, resolutions: Optional[List] = None) -> List[Request]:
     """Poisson arrivals with random scene, random pose on the radius-3 sphere
     and a resolution drawn uniformly from the five serving sizes."""
