@@ -133,17 +133,17 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                     SplatRec s;
                     s.px = r0.x; s.py = r0.y; s.a = r0.z; s.b = r0.w;
                     s.w = r1.x; s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
-                    float dx, dy;
-                    const float e = splat_exponent(s, ux, uy, dx, dy);
+                    float dx, dy, q;
+                    const float e = splat_exponent(s, ux, uy, dx, dy, q);
                     if (live && e >= neg_lambda) {
                         const float alpha = splat_alpha(e, alpha_max);
+                        const float Ta = T * alpha;
                         if (COLOR) {
-                            const float Ta = T * alpha;
                             I0 = fmaf(Ta, s.cr, I0);
                             I1 = fmaf(Ta, s.cg, I1);
                             I2 = fmaf(Ta, s.cb, I2);
                         }
-                        T = T * (1.0f - alpha);
+                        T = T - Ta;                    // T (1 - alpha)
                         ++nblend;
                         if (T < t_min) {
                             live = false;
@@ -208,7 +208,7 @@ __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t 
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         const int k = (lane >> 3) + 8 * half;
-        if (k < nslots) {
+        if (k < nslots && q != 3) {     // quantity 3 is unused
             const float *src = s_part + k * kSlotStride + q;
             float sum = 0.f;
 #pragma unroll
@@ -231,8 +231,10 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_remap(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
         const TileCtx c = tile_ctx(a, tile);
         const ViewDesc &vd = a.views[c.v];
-        float ux[kQuad], uy[kQuad], T[kQuad], gI0[kQuad], gI1[kQuad], gI2[kQuad], gTT[kQuad];
-        float B0[kQuad], B1[kQuad], B2[kQuad];
+        // per pixel: T (recovered front-to-back transmittance), dL/dI, and
+        // D = dL/dI . B + dL/dT * T_final with B = sum over the blended splats
+        // behind of T_k alpha_k c_k, so that dL/dalpha_i = T_i (dL/dI . c_i) - D / (1 - alpha_i)
+        float ux[kQuad], uy[kQuad], T[kQuad], gI0[kQuad], gI1[kQuad], gI2[kQuad], D[kQuad];
         uint32_t nl[kQuad];
         uint32_t mymax = 0;
 #pragma unroll
@@ -240,8 +242,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
             const int px = c.x0 + (p & 1), py = c.y0 + (p >> 1);
             ux[p] = (float)px + 0.5f;
             uy[p] = (float)py + 0.5f;
-            nl[p] = 0; T[p] = 1.f; gI0[p] = gI1[p] = gI2[p] = 0.f; gTT[p] = 0.f;
-            B0[p] = B1[p] = B2[p] = 0.f;
+            nl[p] = 0; T[p] = 1.f; gI0[p] = gI1[p] = gI2[p] = 0.f; D[p] = 0.f;
             if (px < vd.width && py < vd.height) {
                 const uint64_t lpix = (uint64_t)py * (uint64_t)vd.width + (uint64_t)px;
                 const uint64_t pix = vd.pix_off + lpix;
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 T[p] = b.tfinal_from_views ? vd.trans[lpix] : b.tfinal[pix];
                 const float *gi = b.dimage[c.v] + 3 * lpix;
                 gI0[p] = gi[0]; gI1[p] = gi[1]; gI2[p] = gi[2];
-                if (b.dtrans && b.dtrans[c.v]) gTT[p] = b.dtrans[c.v][lpix] * T[p];   // dL/dT * T_final
+                if (b.dtrans && b.dtrans[c.v]) D[p] = b.dtrans[c.v][lpix] * T[p];   // dL/dT * T_final
                 mymax = max(mymax, nl[p]);
             }
         }
@@ -274,15 +275,15 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 for (int j = cnt - 1; j >= 0; --j) {
                     const SplatRec s = bcast_rec(r0, r1, j);
                     const uint32_t pos = cbeg - c.start + (uint32_t)j;
-                    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f;
+                    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f;
                     bool any = false;
                     // branch-free over the 4 pixels: a pixel that did not blend this
                     // splat gets alpha = 0, so 1/(1 - alpha) = 1 and every update
                     // below is an exact no-op for it
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
-                        float dx, dy;
-                        const float e = splat_exponent(s, ux[p], uy[p], dx, dy);
+                        float dx, dy, q;
+                        const float e = splat_exponent(s, ux[p], uy[p], dx, dy, q);
                         const bool hit = pos < nl[p] && e >= neg_lambda;
                         any = any || hit;
                         const float g = __builtin_amdgcn_exp2f(e);
@@ -291,29 +292,24 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         const float iom = __builtin_amdgcn_rcpf(1.0f - alpha);
                         T[p] = T[p] * iom;                       // T in front of this splat
                         const float Ta = T[p] * alpha;
-                        const float dA = gI0[p] * fmaf(T[p], s.cr, -B0[p] * iom) +
-                                         gI1[p] * fmaf(T[p], s.cg, -B1[p] * iom) +
-                                         gI2[p] * fmaf(T[p], s.cb, -B2[p] * iom) - gTT[p] * iom;
+                        const float gc = fmaf(gI0[p], s.cr, fmaf(gI1[p], s.cg, gI2[p] * s.cb));
+                        const float dA = fmaf(T[p], gc, -D[p] * iom);   // dL/dalpha
+                        D[p] = fmaf(Ta, gc, D[p]);
                         v5 = fmaf(Ta, gI0[p], v5);
                         v6 = fmaf(Ta, gI1[p], v6);
                         v7 = fmaf(Ta, gI2[p], v7);
-                        B0[p] = fmaf(Ta, s.cr, B0[p]);
-                        B1[p] = fmaf(Ta, s.cg, B1[p]);
-                        B2[p] = fmaf(Ta, s.cb, B2[p]);
-                        const float gw = clamped ? 0.f : dA * alpha * kLn2;    // dL/dw; dL/dq = -gw
-                        const float gx = gw * dx, gy = gw * dy;
+                        const float gw = clamped ? 0.f : dA * alpha;   // dL/de / ln 2
                         v4 += gw;
-                        v0 += gx;
-                        v1 += gy;
-                        v2 = fmaf(gx, dx, v2);
-                        v3 = fmaf(gy, dy, v3);
+                        v0 = fmaf(gw, dx, v0);
+                        v1 = fmaf(gw, dy, v1);
+                        v2 = fmaf(gw, q, v2);
                     }
                     if (__ballot(any) != 0ull) {
-                        v0 = octet_sum(v0); v1 = octet_sum(v1); v2 = octet_sum(v2); v3 = octet_sum(v3);
-                        v4 = octet_sum(v4); v5 = octet_sum(v5); v6 = octet_sum(v6); v7 = octet_sum(v7);
+                        v0 = octet_sum(v0); v1 = octet_sum(v1); v2 = octet_sum(v2); v4 = octet_sum(v4);
+                        v5 = octet_sum(v5); v6 = octet_sum(v6); v7 = octet_sum(v7);
                         if ((lane & 7) == 7) {
                             float *dst = s_part + nslots * kSlotStride + octet * kOctStride;
-                            dst[0] = v0; dst[1] = v1; dst[2] = v2; dst[3] = v3;
+                            dst[0] = v0; dst[1] = v1; dst[2] = v2; dst[3] = 0.f;
                             dst[4] = v4; dst[5] = v5; dst[6] = v6; dst[7] = v7;
                         }
                         if (lane == 0) s_gid[nslots] = (uint32_t)__builtin_amdgcn_readlane((int)id, j);

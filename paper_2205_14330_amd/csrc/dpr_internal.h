@@ -114,11 +114,11 @@ __device__ __forceinline__ float depth_z(const float *R, const float *t, float x
 // Exponent of the splat opacity: e = w - (a dx^2 + b dy^2); alpha = 2^e.
 // Written with explicit rounding so every kernel that re-evaluates a splat
 // (forward, recompute, backward) takes bit-identical decisions.
-__device__ __forceinline__ float splat_exponent(const SplatRec &s, float ux, float uy,
-                                                float &dx, float &dy) {
+__device__ __forceinline__ float splat_exponent(const SplatRec &s, float ux, float uy, float &dx, float &dy,
+                                                float &q) {
     dx = __fsub_rn(s.px, ux);
     dy = __fsub_rn(s.py, uy);
-    float q = __fmaf_rn(s.a, __fmul_rn(dx, dx), __fmul_rn(s.b, __fmul_rn(dy, dy)));
+    q = __fmaf_rn(s.a, __fmul_rn(dx, dx), __fmul_rn(s.b, __fmul_rn(dy, dy)));
     return __fsub_rn(s.w, q);
 }
 

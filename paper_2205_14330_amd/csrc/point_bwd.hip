@@ -6,11 +6,12 @@
 // One thread per scene point loops over the scene's views in a fixed order,
 // so the sum over views is deterministic and each output is written once.
 //
-// Gradient record of an item (accumulated by the compositing backward):
-//   A0 = sum gw dx, A1 = sum gw dy, A2 = sum gw dx^2, A3 = sum gw dy^2,
-//   A4 = sum gw, A5..A7 = dL/dc, with gw = dL/dw and dx = px - ux.
-// Since e = w - a dx^2 - b dy^2:
-//   dL/dpx = -2a A0, dL/dpy = -2b A1, dL/da = -A2, dL/db = -A3, dL/dw = A4.
+// Gradient record of an item (accumulated by the compositing backward), with
+// gw = (dL/de) / ln 2 per (pixel, splat), e = w - q, q = a dx^2 + b dy^2,
+// dx = px - ux:
+//   A0 = sum gw dx, A1 = sum gw dy, A2 = sum gw q, A3 = 0, A4 = sum gw, A5..A7 = dL/dc.
+// Hence dL/dw = ln2 A4, dL/dpx = -2a ln2 A0, dL/dpy = -2b ln2 A1, and since a and
+// b scale as Z^2, the part of dL/dZ through the splat shape is -(2 ln2 / Z) A2.
 #include "dpr_internal.h"
 #include "sh.h"
 
@@ -55,17 +56,15 @@ __global__ __launch_bounds__(kPointThreads) void k_point_bwd(Tables tb, Threshol
         const float a = (0.5f * kLog2e) / (sx * sx);
         const float bb = (0.5f * kLog2e) / (sy * sy);
 
-        const float g_px = -2.f * a * ga.x;
-        const float g_py = -2.f * bb * ga.y;
-        const float g_a = -ga.z;
-        const float g_b = -ga.w;
-        const float g_w = gb.x;
+        const float g_px = -2.f * kLn2 * a * ga.x;
+        const float g_py = -2.f * kLn2 * bb * ga.y;
+        const float g_w = kLn2 * gb.x;
         const float gc0 = gb.y, gc1 = gb.z, gc2 = gb.w;
 
         // projection px = fx X/Z + cx, py = fy Y/Z + cy; a, b ~ Z^2
         float dX = g_px * vd.fx * iz;
         float dY = g_py * vd.fy * iz;
-        float dZ = -(g_px * vd.fx * X + g_py * vd.fy * Yc) * iz * iz + 2.f * (g_a * a + g_b * bb) * iz;
+        float dZ = -(g_px * vd.fx * X + g_py * vd.fy * Yc) * iz * iz - 2.f * kLn2 * ga.z * iz;
         // opacity: w = log2(o)
         gO += g_w / (o * kLn2);
 
