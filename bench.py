@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--views", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time only the forward + backward metric (skip the forward-only and recompute legs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (reference for HBM counters)")
     ap.add_argument("--workload", choices=["train", "dynamic", "serve"], default="train")
@@ -189,11 +191,13 @@ def main():
     log(f"fwd+bwd: {t_fb / K * 1e3:.3f} ms/step, {mpix_fb:.1f} Mpix/s")
     log("stage ms/step: " + ", ".join(f"{s}={v / K:.3f}" for s, v in stage_ms.items()))
 
-    t_f = timed(dpr.RenderParams(**base), False, K, args.warmup)
-    mpix_f = pix_step * K / t_f / 1e6
-    t_r = timed(dpr.RenderParams(bwd_mode="recompute", **base), True, K, args.warmup)
-    mpix_r = pix_step * K / t_r / 1e6
-    log(f"fwd: {mpix_f:.1f} Mpix/s; fwd+bwd recompute: {mpix_r:.1f} Mpix/s")
+    mpix_f = mpix_r = None
+    if not args.main_only:
+        t_f = timed(dpr.RenderParams(**base), False, K, args.warmup)
+        mpix_f = round(pix_step * K / t_f / 1e6, 2)
+        t_r = timed(dpr.RenderParams(bwd_mode="recompute", **base), True, K, args.warmup)
+        mpix_r = round(pix_step * K / t_r / 1e6, 2)
+        log(f"fwd: {mpix_f} Mpix/s; fwd+bwd recompute: {mpix_r} Mpix/s")
 
     # roofline of the dominant kernel (per launch = per step)
     comp = {"composite_fwd": FWD_OPS_PER_BLEND, "composite_bwd": BWD_OPS_PER_BLEND}
@@ -240,8 +244,8 @@ def main():
                                "per step, forward + backward (stored T), L2 loss",
                    "points": args.points, "views_per_step": V, "width": S, "height": S,
                    "persistent": bool(args.persistent)},
-        "fwd_mpix_s": round(mpix_f, 2), "fwd_bwd_mpix_s": round(mpix_fb, 2),
-        "fwd_bwd_recompute_mpix_s": round(mpix_r, 2),
+        "fwd_mpix_s": mpix_f, "fwd_bwd_mpix_s": round(mpix_fb, 2),
+        "fwd_bwd_recompute_mpix_s": mpix_r,
         "stage_ms_per_step": {s: round(v / K, 4) for s, v in stage_ms.items()},
         "pairs_per_step": pairs / K, "blended_per_step": blends / K,
         "roofline": roof, "cpu_baseline": cpu, "serving": serving,
