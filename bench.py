@@ -130,8 +130,12 @@ def main():
     torch.cuda.synchronize()
     log(f"setup done: {args.points} points, {V} x {S}x{S}, {nsteps} steps")
 
+    # two live plans at a time (one being inspected while the next runs), so two
+    # workspaces, each reused every other step
+    wss = [dpr.Workspace(dev), dpr.Workspace(dev)]
+
     def step(k, params, backward=True):
-        plan = dpr.Plan([scene], [(0, c) for c in step_views[k]], params)
+        plan = dpr.Plan([scene], [(0, c) for c in step_views[k]], params, workspace=wss[k % 2])
         plan.forward()
         if backward:
             tgt = targets[k % len(targets)]
@@ -139,30 +143,45 @@ def main():
             plan.backward(g, None)
         return plan
 
-    def timed(params, backward, steps, warmup, collect=None):
-        """Times `steps` steps after `warmup`.  At most two plans are alive (the
-        caching allocator reuses their memory); a plan is inspected and freed
-        once the next plan's host sync has passed its work."""
+    def timed(params, backward, steps, warmup, collect=None, reset=None):
+        """Times `steps` steps after `warmup`.  At most two plans are alive, on
+        the two workspaces; a plan is inspected and freed once the next plan's
+        host sync has passed its work.  The warmup runs the same loop, inspection
+        included (its first calls load torch's kernels), then `reset` clears
+        what the inspection accumulated."""
         prev = None
-        for k in range(warmup):              # same two-live-plans pattern as the timed loop
+        for k in range(warmup):
             plan = step(k, params, backward)
             if prev is not None:
+                if collect:
+                    collect(prev)
                 prev.free()
             prev = plan
         if prev is not None:
+            if collect:
+                collect(prev)
             prev.free()
         torch.cuda.synchronize()
+        if reset:
+            reset()
+        n_alloc = torch.cuda.memory_stats().get("num_device_alloc", 0)
+        host = []
         t0 = time.perf_counter()
         prev = None
         for k in range(steps):
+            ts = time.perf_counter()
             plan = step(warmup + k, params, backward)
             if prev is not None:
                 if collect:
                     collect(prev)
                 prev.free()
             prev = plan
+            host.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        n_alloc = torch.cuda.memory_stats().get("num_device_alloc", 0) - n_alloc
+        log(f"  timed loop: {steps} steps, host ms/step median {1e3 * float(np.median(host)):.2f} "
+            f"max {1e3 * max(host):.2f} (step {int(np.argmax(host))}), device allocations {n_alloc}")
         if collect:
             collect(prev)
         prev.free()
@@ -183,7 +202,13 @@ def main():
         blend_acc.add_(p.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32).sum())
         pair_acc[0] += inf.pairs
 
-    t_fb = timed(dpr.RenderParams(timing=True, stats=True, **base), True, args.steps, args.warmup, collect)
+    def reset():
+        for s_ in stage_ms:
+            stage_ms[s_] = 0.0
+        blend_acc.zero_()
+        pair_acc[0] = 0
+
+    t_fb = timed(dpr.RenderParams(timing=True, stats=True, **base), True, args.steps, args.warmup, collect, reset)
     blends = int(blend_acc.item())
     pairs = pair_acc[0]
     K = args.steps
@@ -266,25 +291,40 @@ def bench_dynamic(args):
     gen = torch.Generator(device="cuda").manual_seed(4)
     targets = [torch.rand((c.height, c.width, 3), device="cuda", generator=gen) for c in cams]
     out = {}
+    wss = [dpr.Workspace(), dpr.Workspace()]
     for persistent in (False, True):
-        def step(params):
-            plan = dpr.Plan(scenes, views, params)
+        def step(k, params):
+            plan = dpr.Plan(scenes, views, params, workspace=wss[k % 2])
             plan.forward()
             plan.backward([(2.0 * (plan.images[t] - targets[t])).contiguous() for t in range(F)], None)
             return plan
         params = dpr.RenderParams(timing=True, persistent=persistent)
-        for _ in range(args.warmup):
-            step(params).free()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plans = [step(params) for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
         st = {k: 0.0 for k in dpr.STAGES}
-        for p in plans:
+
+        def collect(p):
             for k, v in p.stage_times().items():
                 st[k] += max(v, 0.0) / args.steps
             p.free()
+
+        prev = None
+        for k in range(args.warmup):
+            plan = step(k, params)
+            if prev is not None:
+                prev.free()
+            prev = plan
+        torch.cuda.synchronize()
+        if prev is not None:
+            prev.free()
+        t0 = time.perf_counter()
+        prev = None
+        for k in range(args.steps):
+            plan = step(k, params)
+            if prev is not None:
+                collect(prev)       # the new plan's host sync has passed the previous plan's work
+            prev = plan
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        collect(prev)
         px = sum(c.pixels for c in cams)
         out["persistent" if persistent else "grid"] = {
             "ms_per_step": round(dt * 1e3, 3), "mpix_s": round(px / dt / 1e6, 1),

@@ -86,18 +86,54 @@ def _stream_handle(stream: Optional[torch.cuda.Stream]) -> int:
     return int(s.cuda_stream)
 
 
+class Workspace:
+    """Device buffers for the plan, forward and backward workspaces, reused by
+    successive plans and grown geometrically (never shrunk), so a loop whose
+    pair count varies from step to step stops allocating device memory after
+    its first steps.
+
+    A Workspace serves ONE plan at a time: making a new plan with it hands the
+    buffers to that plan, and the earlier plan's forward/backward then raise.
+    Work of successive plans on one stream is ordered by the stream, so a plan
+    may be made while the previous one's kernels are still queued; plans on
+    different streams, or two plans alive at once (e.g. one's statistics read
+    while the next runs), need a Workspace each.
+    """
+
+    def __init__(self, device="cuda", headroom: float = 1.25):
+        self.device = torch.device(device)
+        self.headroom = float(headroom)
+        self.bufs = {}
+        self.owner = None
+
+    def get(self, name: str, nbytes: int) -> torch.Tensor:
+        nbytes = max(int(nbytes), 1)
+        b = self.bufs.get(name)
+        if b is None or b.numel() < nbytes:
+            size = (int(nbytes * self.headroom) + (1 << 21) - 1) & ~((1 << 21) - 1)
+            self.bufs.pop(name, None)
+            b = torch.empty(size, dtype=torch.uint8, device=self.device)
+            self.bufs[name] = b
+        return b
+
+    def reserved_bytes(self) -> int:
+        return sum(b.numel() for b in self.bufs.values())
+
+
 class Plan:
     """One batch of views over one or more resident scenes.
 
     The plan workspace, the forward workspace and the output images are
-    allocated with torch on the scenes' device; the library does no device
-    allocation of its own.
+    allocated with torch on the scenes' device (or taken from `workspace`);
+    the library does no device allocation of its own.
     """
 
     def __init__(self, scenes: Sequence[SceneTensors], views: Sequence[Tuple[int, object]],
                  params: RenderParams = RenderParams(), stream: Optional[torch.cuda.Stream] = None,
-                 images: Optional[Sequence[torch.Tensor]] = None, trans: Optional[Sequence[torch.Tensor]] = None):
+                 images: Optional[Sequence[torch.Tensor]] = None, trans: Optional[Sequence[torch.Tensor]] = None,
+                 workspace: Optional[Workspace] = None):
         self.lib = load()
+        self.workspace = workspace
         self.scenes = list(scenes)
         self.views = list(views)
         self.params = params
@@ -120,7 +156,11 @@ class Plan:
         nbytes = self.lib.dpr_plan_ws_bytes(self._c_scenes, len(self.scenes), self._c_views, len(cv))
         if nbytes == 0:
             check(_abi.DPR_ERR_INVALID_ARG)
-        self.plan_ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        if workspace is not None:
+            workspace.owner = self
+            self.plan_ws = workspace.get("plan", nbytes)
+        else:
+            self.plan_ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
         self._plan = ctypes.c_void_p()
         rc = self.lib.dpr_plan_forward(self._c_scenes, len(self.scenes), self._c_views, len(cv),
                                        ctypes.byref(self._c_params), self.plan_ws.data_ptr(), int(nbytes),
@@ -128,11 +168,19 @@ class Plan:
         check(rc)
         self.ws = None
 
+    def _check_owner(self):
+        if self.workspace is not None and self.workspace.owner is not self:
+            raise RuntimeError("this plan's Workspace has been handed to a newer plan")
+
     # -- forward ------------------------------------------------------------------
     def forward(self):
+        self._check_owner()
         n = int(self.lib.dpr_workspace_bytes(self._plan))
         if self.ws is None or self.ws.numel() < n:
-            self.ws = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+            if self.workspace is not None:
+                self.ws = self.workspace.get("fwd", n)
+            else:
+                self.ws = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
         check(self.lib.dpr_render_forward(self._plan, self.ws.data_ptr(), int(self.ws.numel()),
                                           _stream_handle(self.stream)))
         return self.images, self.trans
@@ -143,6 +191,7 @@ class Plan:
         """Returns per-scene lists of (dxyz, dsh, dopacity) tensors (None where not wanted)."""
         if self.ws is None:
             raise RuntimeError("backward before forward")
+        self._check_owner()
         gi = []
         for g, c in zip(dL_dimage, self._cams):
             if g.dtype != torch.float32 or not g.is_contiguous() or tuple(g.shape) != (c.height, c.width, 3):
@@ -163,7 +212,10 @@ class Plan:
                             torch.empty_like(s.sh) if "sh" in want else None,
                             torch.empty_like(s.opacity) if "opacity" in want else None))
         nb = int(self.lib.dpr_backward_ws_bytes(self._plan))
-        bws = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
+        if self.workspace is not None:
+            bws = self.workspace.get("bwd", nb)
+        else:
+            bws = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
         P = _abi.ptr_array
         di = P([g.data_ptr() for g in gi])
         dt = None if gt is None else P([0 if g is None else g.data_ptr() for g in gt])
@@ -171,7 +223,7 @@ class Plan:
         ds = P([0 if o[1] is None else o[1].data_ptr() for o in out])
         do = P([0 if o[2] is None else o[2].data_ptr() for o in out])
         check(self.lib.dpr_render_backward(self._plan, self.ws.data_ptr(), int(self.ws.numel()), di, dt, dx, ds, do,
-                                           bws.data_ptr(), nb, _stream_handle(self.stream)))
+                                           bws.data_ptr(), int(bws.numel()), _stream_handle(self.stream)))
         self._bws = bws   # keep alive until the stream has consumed it
         return out
 

@@ -9,7 +9,7 @@ import oracle
 import workloads
 from workloads import Camera, Scene
 
-from _gpu_util import compare_grads, compare_images, gpu_plan, oparams, random_pixels, to_np
+from _gpu_util import compare_grads, compare_images, gpu_plan, oparams, random_pixels, scene_tensors, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -173,3 +173,43 @@ def test_ball100k_gradients_restricted_pixels(dpr):
     compare_grads(got[0][subset], ref.xyz[subset], "ball100k subset dxyz")
     compare_grads(got[1][subset], ref.sh[subset], "ball100k subset dsh")
     compare_grads(got[2][subset], ref.opacity[subset], "ball100k subset dopacity")
+
+
+def test_workspace_reuse_matches_fresh_allocations(dpr):
+    """Plans sharing one grown Workspace give the same images (bitwise) and
+    gradients as plans with their own allocations, and the oracle's images;
+    a plan whose Workspace went to a newer plan refuses to run."""
+    import torch
+    sc = workloads.small_scene(95, 3000, extent=0.7)
+    st = scene_tensors(sc)
+    rng = np.random.default_rng(95)
+    sets = [[workloads.random_sphere_camera(rng, 24, 20)],
+            [workloads.random_sphere_camera(rng, 70, 45), workloads.random_sphere_camera(rng, 33, 33)],
+            [workloads.random_sphere_camera(rng, 16, 16)]]
+    ws = dpr.Workspace("cuda", headroom=1.0)       # no headroom: the second set must grow it
+    params = dpr.RenderParams()
+    prev = None
+    for k, cams in enumerate(sets):
+        views = [(0, c) for c in cams]
+        gI, gT = _weights(950 + k, cams)
+        gi = [torch.from_numpy(g).cuda() for g in gI]
+        gt = [torch.from_numpy(g).cuda() for g in gT]
+        a = dpr.Plan([st], views, params, workspace=ws)
+        if prev is not None:
+            with pytest.raises(RuntimeError):
+                prev.forward()
+        a.forward()
+        ga = [to_np(t) for t in a.backward(gi, gt)[0]]
+        b = dpr.Plan([st], views, params)
+        b.forward()
+        gb = [to_np(t) for t in b.backward(gi, gt)[0]]
+        for v, cam in enumerate(cams):
+            assert np.array_equal(to_np(a.images[v]), to_np(b.images[v]))
+            assert np.array_equal(to_np(a.trans[v]), to_np(b.trans[v]))
+            ref = oracle.render(sc, cam, oparams(params))
+            compare_images(to_np(a.images[v]), to_np(a.trans[v]), ref, label=f"set {k} view {v}")
+        for x, y in zip(ga, gb):
+            assert np.abs(x - y).max() <= 1e-5 * max(np.abs(x).max(), 1e-30)
+        b.free()
+        prev = a
+    assert ws.reserved_bytes() > 0
