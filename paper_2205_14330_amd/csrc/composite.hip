@@ -13,11 +13,12 @@
 // per-splat reduction is shared by 256 pixels.  The list is walked in reverse
 // from the furthest stop index, recovering T_i = T_{i+1} / (1 - alpha_i)
 // (alpha <= alpha_max < 1), keeping the back-to-front colour sum, and folding
-// each (pixel, splat) contribution into 8 per-lane partial sums.  Records are
-// held one per lane and broadcast with readlane.  The sums are reduced across
-// each group of 8 lanes with DPP, the 8 group sums of up to 16 splats are
-// staged in LDS, and each flush completes 128 sums and adds them to the
-// per-item gradient records with two 64-lane float atomics.
+// each (pixel, splat) contribution into 7 per-lane partial sums.  A chunk of 64
+// records is gathered one per lane, written to LDS and read back as
+// broadcasts.  The sums are reduced across each group of 4 lanes with DPP, the
+// 16 group sums of up to 8 splats are staged in LDS, and each flush completes
+// 56 sums and adds them to the per-item gradient records with one 64-lane
+// float atomic.
 #include "dpr_internal.h"
 
 namespace dpr {
@@ -65,17 +66,6 @@ __device__ __forceinline__ void load_rec(const CompositeArgs &a, uint32_t k, uin
         r0 = make_float4(0.f, 0.f, 0.f, 0.f);
         r1 = make_float4(-INFINITY, 0.f, 0.f, 0.f);
     }
-}
-
-__device__ __forceinline__ float bcast(float v, int j) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
-}
-
-__device__ __forceinline__ SplatRec bcast_rec(const float4 &r0, const float4 &r1, int j) {
-    SplatRec s;
-    s.px = bcast(r0.x, j); s.py = bcast(r0.y, j); s.a = bcast(r0.z, j); s.b = bcast(r0.w, j);
-    s.w = bcast(r1.x, j); s.cr = bcast(r1.y, j); s.cg = bcast(r1.z, j); s.cb = bcast(r1.w, j);
-    return s;
 }
 
 // next tile for persistent waves
@@ -181,40 +171,37 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ float dpp_add(float v) {
-    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// Sum over each group of 8 consecutive lanes (valid in all 8 lanes).
-__device__ __forceinline__ float octet_sum(float v) {
+// Sum over each group of 4 consecutive lanes (valid in all 4 lanes).
+__device__ __forceinline__ float quad_sum(float v) {
     v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
-    v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]  -> sums of 4
-    v = dpp_add<0x141>(v);   // row_half_mirror      -> sums of 8
+    v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
     return v;
 }
 
-// Staging of per-splat partial sums: slot k holds, for one splat, the 8 octet
-// sums of each of the 8 quantities at [k][octet][quantity] with a padded
-// octet stride of 9 words, so both the octet writes and the flush reads hit
-// distinct LDS banks.
-constexpr int kSlots = 16;
-constexpr int kOctStride = 9;
-constexpr int kSlotStride = 8 * kOctStride;
+// Staging of per-splat partial sums: slot k holds, for one splat, the 16
+// lane-quad sums of each of the 8 quantities at [k][quad][quantity].  The quad
+// stride of 9 words keeps the 16 writers of one quantity on distinct banks; the
+// slot stride of 152 words (24 mod 32, 24 mod 64) keeps the 64 flush readers
+// (8 slots x 8 quantities) on distinct banks.
+constexpr int kSlots = 8;
+constexpr int kQuadStride = 9;
+constexpr int kSlotStride = 16 * kQuadStride + 8;
 
-// Completes the sums of the first nslots slots (lane L handles slot L/8 and
-// slot 8 + L/8, quantity L%8) and adds them to the gradient records.
+// Completes the sums of the first nslots slots (lane L handles slot L/8,
+// quantity L%8) and adds them to the gradient records.
 __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t *s_gid, int nslots, float *grad,
                                             int lane) {
     const int q = lane & 7;
+    const int k = lane >> 3;
+    if (k < nslots && q != 3) {     // quantity 3 is unused
+        const float *src = s_part + k * kSlotStride + q;
+        float sum = src[0];
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const int k = (lane >> 3) + 8 * half;
-        if (k < nslots && q != 3) {     // quantity 3 is unused
-            const float *src = s_part + k * kSlotStride + q;
-            float sum = 0.f;
-#pragma unroll
-            for (int o = 0; o < 8; ++o) sum += src[o * kOctStride];
-            atomicAdd(grad + 8 * (size_t)s_gid[k] + q, sum);
-        }
+        for (int o = 1; o < 16; ++o) sum += src[o * kQuadStride];
+        atomicAdd(grad + 8 * (size_t)s_gid[k] + q, sum);
     }
 }
 
@@ -222,11 +209,12 @@ template <bool PERSISTENT>
 __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     __shared__ float s_part[kSlots * kSlotStride];
     __shared__ uint32_t s_gid[kSlots];
+    __shared__ float4 s_rec[2 * kCompLanes];       // the current chunk: record j at [2j], [2j + 1]
     const CompositeArgs &a = b.c;
     const float neg_lambda = -a.th.lambda;
     const float alpha_max = a.th.alpha_max;
     const int lane = threadIdx.x;
-    const int octet = lane >> 3;
+    float *const my_part = s_part + (lane >> 2) * kQuadStride;
 
     for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_remap(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
         const TileCtx c = tile_ctx(a, tile);
@@ -267,54 +255,68 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
             uint32_t nid;
             load_rec(a, cbeg + lane, lend, n0, n1, nid);
             while (true) {
-                const float4 r0 = n0, r1 = n1;
                 const uint32_t id = nid;
+                __syncthreads();                 // the previous chunk's broadcasts are done
+                s_rec[2 * lane] = n0;
+                s_rec[2 * lane + 1] = n1;
+                __syncthreads();
                 const bool more = cbeg > c.start;
                 if (more) load_rec(a, cbeg - kCompLanes + lane, lend, n0, n1, nid);
                 const int cnt = (int)min((uint32_t)kCompLanes, lend - cbeg);
                 for (int j = cnt - 1; j >= 0; --j) {
-                    const SplatRec s = bcast_rec(r0, r1, j);
+                    const float4 f0 = s_rec[2 * j], f1 = s_rec[2 * j + 1];
+                    SplatRec s;
+                    s.px = f0.x; s.py = f0.y; s.a = f0.z; s.b = f0.w;
+                    s.w = f1.x; s.cr = f1.y; s.cg = f1.z; s.cb = f1.w;
                     const uint32_t pos = cbeg - c.start + (uint32_t)j;
-                    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f, v7 = 0.f;
+                    float gw[kQuad], Ta[kQuad], dxs[kQuad], dys[kQuad], qs[kQuad];
                     bool any = false;
                     // branch-free over the 4 pixels: a pixel that did not blend this
                     // splat gets alpha = 0, so 1/(1 - alpha) = 1 and every update
                     // below is an exact no-op for it
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
-                        float dx, dy, q;
-                        const float e = splat_exponent(s, ux[p], uy[p], dx, dy, q);
+                        const float e = splat_exponent(s, ux[p], uy[p], dxs[p], dys[p], qs[p]);
                         const bool hit = pos < nl[p] && e >= neg_lambda;
                         any = any || hit;
                         const float g = __builtin_amdgcn_exp2f(e);
                         const bool clamped = g > alpha_max;
-                        const float alpha = hit ? fminf(g, alpha_max) : 0.f;
+                        const float alpha = hit ? (clamped ? alpha_max : g) : 0.f;
+                        const float m = (hit && !clamped) ? g : 0.f;     // alpha where e passes a gradient
                         const float iom = __builtin_amdgcn_rcpf(1.0f - alpha);
                         T[p] = T[p] * iom;                       // T in front of this splat
-                        const float Ta = T[p] * alpha;
+                        Ta[p] = T[p] * alpha;
                         const float gc = fmaf(gI0[p], s.cr, fmaf(gI1[p], s.cg, gI2[p] * s.cb));
                         const float dA = fmaf(T[p], gc, -D[p] * iom);   // dL/dalpha
-                        D[p] = fmaf(Ta, gc, D[p]);
-                        v5 = fmaf(Ta, gI0[p], v5);
-                        v6 = fmaf(Ta, gI1[p], v6);
-                        v7 = fmaf(Ta, gI2[p], v7);
-                        const float gw = clamped ? 0.f : dA * alpha;   // dL/de / ln 2
-                        v4 += gw;
-                        v0 = fmaf(gw, dx, v0);
-                        v1 = fmaf(gw, dy, v1);
-                        v2 = fmaf(gw, q, v2);
+                        D[p] = fmaf(Ta[p], gc, D[p]);
+                        gw[p] = dA * m;                                  // dL/de / ln 2
                     }
                     if (__ballot(any) != 0ull) {
-                        v0 = octet_sum(v0); v1 = octet_sum(v1); v2 = octet_sum(v2); v4 = octet_sum(v4);
-                        v5 = octet_sum(v5); v6 = octet_sum(v6); v7 = octet_sum(v7);
-                        if ((lane & 7) == 7) {
-                            float *dst = s_part + nslots * kSlotStride + octet * kOctStride;
-                            dst[0] = v0; dst[1] = v1; dst[2] = v2; dst[3] = 0.f;
+                        float v0 = gw[0] * dxs[0], v1 = gw[0] * dys[0], v2 = gw[0] * qs[0], v4 = gw[0];
+                        float v5 = Ta[0] * gI0[0], v6 = Ta[0] * gI1[0], v7 = Ta[0] * gI2[0];
+#pragma unroll
+                        for (int p = 1; p < kQuad; ++p) {
+                            v0 = fmaf(gw[p], dxs[p], v0);
+                            v1 = fmaf(gw[p], dys[p], v1);
+                            v2 = fmaf(gw[p], qs[p], v2);
+                            v4 += gw[p];
+                            v5 = fmaf(Ta[p], gI0[p], v5);
+                            v6 = fmaf(Ta[p], gI1[p], v6);
+                            v7 = fmaf(Ta[p], gI2[p], v7);
+                        }
+                        v0 = quad_sum(v0); v1 = quad_sum(v1); v2 = quad_sum(v2); v4 = quad_sum(v4);
+                        v5 = quad_sum(v5); v6 = quad_sum(v6); v7 = quad_sum(v7);
+                        {   // the 4 lanes of a group hold bitwise-equal sums and store them
+                            // to the same words, which keeps the DPP adds unconditional
+                            float *dst = my_part + nslots * kSlotStride;
+                            dst[0] = v0; dst[1] = v1; dst[2] = v2;
                             dst[4] = v4; dst[5] = v5; dst[6] = v6; dst[7] = v7;
                         }
-                        if (lane == 0) s_gid[nslots] = (uint32_t)__builtin_amdgcn_readlane((int)id, j);
+                        if (lane == j) s_gid[nslots] = id;
                         if (++nslots == kSlots) {
+                            __syncthreads();     // staged sums are written before other lanes read them
                             flush_slots(s_part, s_gid, kSlots, b.grad, lane);
+                            __syncthreads();     // and read before the slots are written again
                             nslots = 0;
                         }
                     }
@@ -323,7 +325,11 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 cbeg -= kCompLanes;
             }
         }
-        if (nslots > 0) flush_slots(s_part, s_gid, nslots, b.grad, lane);
+        if (nslots > 0) {
+            __syncthreads();
+            flush_slots(s_part, s_gid, nslots, b.grad, lane);
+            __syncthreads();
+        }
         if (!PERSISTENT) break;
         tile = pop_tile(a.queue);
     }
