@@ -1,13 +1,15 @@
 // Per-tile front-to-back compositing (Sec. 3.2, Eq. 5-7) and its reverse-mode
 // derivative.
 //
-// Forward: one workgroup of 4 waves per 16x16 tile; wave w owns the 8x8
-// quadrant w, one pixel per lane.  The tile's depth-ordered list is consumed
-// in chunks of 256 splat records gathered into LDS (the next chunk is
-// prefetched into registers while the current one is processed) and read
-// back as LDS broadcasts.  A pixel stops after the first blended splat that
-// leaves T < t_min; a wave skips the rest of a chunk once its 64 pixels have
-// stopped, and the workgroup leaves the list once all 256 have.
+// Forward: one workgroup of 2 waves per 16x16 tile; wave w owns the 16x8
+// half w, two horizontally adjacent pixels per lane.  The tile's
+// depth-ordered list is consumed in chunks of 256 splat records gathered into
+// LDS (the next chunk is prefetched into registers while the current one is
+// processed) and read back as LDS broadcasts: the 20 bytes of the exponent
+// first, the colour only if some pixel of the wave blends.  The blend is
+// branch-free per pixel.  A pixel stops after the first blended splat that
+// leaves T < t_min; a wave leaves the chunk once its 128 pixels have stopped,
+// and the workgroup leaves the list once all 256 have.
 //
 // Backward: one wave per tile; each lane owns a 2x2 pixel quad so that the
 // per-splat reduction is shared by 256 pixels.  The list is walked in reverse
@@ -78,11 +80,19 @@ __device__ __forceinline__ uint32_t pop_tile(uint32_t *queue) {
 // ---------------------------------------------------------------------------
 // forward (COLOR = true) and recompute of the per-pixel state (COLOR = false)
 // ---------------------------------------------------------------------------
-constexpr int kFwdThreads = 256;
+// Two waves per tile: wave w owns rows [8w, 8w + 8), each lane a horizontal
+// pixel pair.  Each chunk stages 2 records per thread.
+constexpr int kFwdPx = 2;                 // pixels per lane
+constexpr int kFwdThreads = 128;
+constexpr int kFwdChunk = 2 * kFwdThreads;
 
+// A pixel is live while T >= t_min: T only decreases, by T alpha <= T, and
+// the pixel stops right after the blend that takes it below t_min, so the
+// test is exactly the stop rule.  Pixels outside the image start at T = -1.
 template <bool COLOR, bool PERSISTENT>
 __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
-    __shared__ float4 s_r0[kFwdThreads], s_r1[kFwdThreads];
+    constexpr int PX = kFwdPx, kThreads = kFwdThreads, kChunk = kFwdChunk;
+    __shared__ float4 s_r0[kChunk], s_r1[kChunk];
     __shared__ uint32_t s_next;
     const float neg_lambda = -a.th.lambda;
     const float alpha_max = a.th.alpha_max, t_min = a.th.t_min;
@@ -93,70 +103,111 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
         const uint32_t lt = tile - vd.tile_off;
         const uint32_t ty = lt / (uint32_t)vd.tiles_x;
         const uint32_t tx = lt - ty * (uint32_t)vd.tiles_x;
-        const int px = (int)(tx * kTile) + 8 * (wave & 1) + (lane & 7);
-        const int py = (int)(ty * kTile) + 8 * (wave >> 1) + (lane >> 3);
         const uint32_t start = a.tile_base[tile], end = a.tile_base[tile + 1];
-        const float ux = (float)px + 0.5f, uy = (float)py + 0.5f;
-        const bool inside = px < vd.width && py < vd.height;
-        bool live = inside;
-        float T = 1.f, I0 = 0.f, I1 = 0.f, I2 = 0.f;
-        uint32_t nlast = end - start, nblend = 0;
-        float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = make_float4(-INFINITY, 0.f, 0.f, 0.f);
-        if (start + tid < end) {
-            const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[start + tid]);
-            n0 = src[0];
-            n1 = src[1];
+        const int x0 = (int)(tx * kTile) + 2 * (lane & 7);
+        const int y0 = (int)(ty * kTile) + 8 * wave + (lane >> 3);
+        float ux[PX], uy[PX], T[PX], I0[PX], I1[PX], I2[PX];
+        uint32_t nlast[PX], nblend[PX];
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            const int px = x0 + p, py = y0;
+            ux[p] = (float)px + 0.5f;
+            uy[p] = (float)py + 0.5f;
+            T[p] = (px < vd.width && py < vd.height) ? 1.f : -1.f;
+            I0[p] = I1[p] = I2[p] = 0.f;
+            nlast[p] = end - start; nblend[p] = 0;
         }
-        for (uint32_t base = start; base < end; base += kFwdThreads) {
-            s_r0[tid] = n0;
-            s_r1[tid] = n1;
-            __syncthreads();
-            if (base + kFwdThreads + tid < end) {
-                const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[base + kFwdThreads + tid]);
-                n0 = src[0];
-                n1 = src[1];
+        float4 n0[2], n1[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            n0[h] = make_float4(0.f, 0.f, 0.f, 0.f);
+            n1[h] = make_float4(-INFINITY, 0.f, 0.f, 0.f);
+            if (start + h * kThreads + tid < end) {
+                const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[start + h * kThreads + tid]);
+                n0[h] = src[0];
+                n1[h] = src[1];
             }
-            const int cnt = (int)min((uint32_t)kFwdThreads, end - base);
-            if (__ballot(live) != 0ull) {
-                for (int j = 0; j < cnt; ++j) {
-                    const float4 r0 = s_r0[j], r1 = s_r1[j];
-                    SplatRec s;
-                    s.px = r0.x; s.py = r0.y; s.a = r0.z; s.b = r0.w;
-                    s.w = r1.x; s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
-                    float dx, dy, q;
-                    const float e = splat_exponent(s, ux, uy, dx, dy, q);
-                    if (live && e >= neg_lambda) {
-                        const float alpha = splat_alpha(e, alpha_max);
-                        const float Ta = T * alpha;
-                        if (COLOR) {
-                            I0 = fmaf(Ta, s.cr, I0);
-                            I1 = fmaf(Ta, s.cg, I1);
-                            I2 = fmaf(Ta, s.cb, I2);
-                        }
-                        T = T - Ta;                    // T (1 - alpha)
-                        ++nblend;
-                        if (T < t_min) {
-                            live = false;
-                            nlast = base - start + (uint32_t)j + 1;
-                        }
-                    }
-                    if ((j & 15) == 15 && __ballot(live) == 0ull) break;
+        }
+        for (uint32_t base = start; base < end; base += kChunk) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                s_r0[h * kThreads + tid] = n0[h];
+                s_r1[h * kThreads + tid] = n1[h];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t k = base + kChunk + h * kThreads + tid;
+                if (k < end) {
+                    const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[k]);
+                    n0[h] = src[0];
+                    n1[h] = src[1];
                 }
             }
-            if (__syncthreads_count(live) == 0) break;
+            const int cnt = (int)min((uint32_t)kChunk, end - base);
+            for (int j0 = 0; j0 < cnt; j0 += 16) {
+                bool any_live = false;
+#pragma unroll
+                for (int p = 0; p < PX; ++p) any_live = any_live || T[p] >= t_min;
+                if (__ballot(any_live) == 0ull) break;
+                const int jn = min(j0 + 16, cnt);
+                for (int j = j0; j < jn; ++j) {
+                    const float4 r0 = s_r0[j];
+                    SplatRec s;
+                    s.px = r0.x; s.py = r0.y; s.a = r0.z; s.b = r0.w;
+                    s.w = s_r1[j].x;
+                    float e[PX];
+                    bool hit[PX];
+                    bool any = false;
+#pragma unroll
+                    for (int p = 0; p < PX; ++p) {
+                        float dx, dy, q;
+                        e[p] = splat_exponent(s, ux[p], uy[p], dx, dy, q);
+                        hit[p] = T[p] >= t_min && e[p] >= neg_lambda;
+                        any = any || hit[p];
+                    }
+                    if (__ballot(any) != 0ull) {
+                        const float4 r1 = s_r1[j];
+                        s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
+                        // branch-free over the lane's pixels: alpha = 0 leaves a
+                        // pixel that does not blend this splat exactly unchanged
+                        const uint32_t pos1 = base - start + (uint32_t)j + 1;
+#pragma unroll
+                        for (int p = 0; p < PX; ++p) {
+                            const float alpha = hit[p] ? splat_alpha(e[p], alpha_max) : 0.f;
+                            const float Ta = T[p] * alpha;
+                            if (COLOR) {
+                                I0[p] = fmaf(Ta, s.cr, I0[p]);
+                                I1[p] = fmaf(Ta, s.cg, I1[p]);
+                                I2[p] = fmaf(Ta, s.cb, I2[p]);
+                                nblend[p] += hit[p] ? 1u : 0u;
+                            }
+                            T[p] = T[p] - Ta;                       // T (1 - alpha)
+                            if (hit[p] && T[p] < t_min) nlast[p] = pos1;
+                        }
+                    }
+                }
+            }
+            bool any_live = false;
+#pragma unroll
+            for (int p = 0; p < PX; ++p) any_live = any_live || T[p] >= t_min;
+            if (__syncthreads_count(any_live) == 0) break;
         }
-        if (inside) {
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            const int px = x0 + p, py = y0;
+            if (px >= vd.width || py >= vd.height) continue;
             const uint64_t lpix = (uint64_t)py * (uint64_t)vd.width + (uint64_t)px;
             const uint64_t pix = vd.pix_off + lpix;
             if (COLOR) {
                 float *img = vd.image + 3 * lpix;
-                img[0] = I0; img[1] = I1; img[2] = I2;
-                if (vd.trans) vd.trans[lpix] = T;
-                if (a.stats) a.stats[pix] = nblend;
+                img[0] = I0[p]; img[1] = I1[p]; img[2] = I2[p];
+                if (vd.trans) vd.trans[lpix] = T[p];
+                if (a.stats) a.stats[pix] = nblend[p];
             } else {
-                a.tfinal[pix] = T;
+                a.tfinal[pix] = T[p];
             }
-            if (a.nlast) a.nlast[pix] = nlast;
+            if (a.nlast) a.nlast[pix] = nlast[p];
         }
         if (!PERSISTENT) break;
         __syncthreads();
@@ -347,7 +398,7 @@ static uint32_t persistent_grid(uint32_t tiles, uint32_t per_cu) {
 hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (a.total_tiles == 0) return hipSuccess;
     if (persistent) {
-        hipLaunchKernelGGL((k_composite<true, true>), dim3(persistent_grid(a.total_tiles, 4)), dim3(kFwdThreads), 0,
+        hipLaunchKernelGGL((k_composite<true, true>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0,
                            st, a);
     } else {
         hipLaunchKernelGGL((k_composite<true, false>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
@@ -358,7 +409,7 @@ hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStre
 hipError_t launch_recompute(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (a.total_tiles == 0) return hipSuccess;
     if (persistent) {
-        hipLaunchKernelGGL((k_composite<false, true>), dim3(persistent_grid(a.total_tiles, 4)), dim3(kFwdThreads), 0,
+        hipLaunchKernelGGL((k_composite<false, true>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0,
                            st, a);
     } else {
         hipLaunchKernelGGL((k_composite<false, false>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
