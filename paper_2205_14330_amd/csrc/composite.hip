@@ -320,48 +320,69 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                     s.px = f0.x; s.py = f0.y; s.a = f0.z; s.b = f0.w;
                     s.w = f1.x; s.cr = f1.y; s.cg = f1.z; s.cb = f1.w;
                     const uint32_t pos = cbeg - c.start + (uint32_t)j;
-                    float gw[kQuad], Ta[kQuad], dxs[kQuad], dys[kQuad], qs[kQuad];
-                    bool any = false;
-                    // branch-free over the 4 pixels: a pixel that did not blend this
-                    // splat gets alpha = 0, so 1/(1 - alpha) = 1 and every update
-                    // below is an exact no-op for it
+                    float gw[kQuad], Ta[kQuad], e[kQuad], g[kQuad], alpha[kQuad], qs[kQuad];
+                    float dx0 = 0.f, dy0 = 0.f;
+                    bool hit[kQuad];
+                    bool any = false, any_clamped = false;
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
-                        const float e = splat_exponent(s, ux[p], uy[p], dxs[p], dys[p], qs[p]);
-                        const bool hit = pos < nl[p] && e >= neg_lambda;
-                        any = any || hit;
-                        const float g = __builtin_amdgcn_exp2f(e);
-                        const bool clamped = g > alpha_max;
-                        const float alpha = hit ? (clamped ? alpha_max : g) : 0.f;
-                        const float m = (hit && !clamped) ? g : 0.f;     // alpha where e passes a gradient
-                        const float iom = __builtin_amdgcn_rcpf(1.0f - alpha);
+                        float dx, dy;
+                        e[p] = splat_exponent(s, ux[p], uy[p], dx, dy, qs[p]);
+                        if (p == 0) { dx0 = dx; dy0 = dy; }
+                        hit[p] = pos < nl[p] && e[p] >= neg_lambda;
+                        g[p] = __builtin_amdgcn_exp2f(e[p]);
+                        // a pixel that did not blend this splat gets alpha = 0, so
+                        // 1/(1 - alpha) = 1 and every update below is an exact no-op for it
+                        alpha[p] = hit[p] ? g[p] : 0.f;
+                        any = any || hit[p];
+                        any_clamped = any_clamped || (hit[p] && g[p] > alpha_max);
+                    }
+                    const bool wave_any = __ballot(any) != 0ull;
+                    // the alpha_max clamp, which also blocks the gradient to e, is rare:
+                    // it is applied on a path of its own, before and after the update
+                    const bool wave_clamped = __builtin_expect(__ballot(any_clamped) != 0ull, 0);
+                    if (wave_clamped) {
+#pragma unroll
+                        for (int p = 0; p < kQuad; ++p)
+                            if (hit[p] && g[p] > alpha_max) alpha[p] = alpha_max;
+                    }
+#pragma unroll
+                    for (int p = 0; p < kQuad; ++p) {
+                        const float iom = __builtin_amdgcn_rcpf(1.0f - alpha[p]);
                         T[p] = T[p] * iom;                       // T in front of this splat
-                        Ta[p] = T[p] * alpha;
+                        Ta[p] = T[p] * alpha[p];
                         const float gc = fmaf(gI0[p], s.cr, fmaf(gI1[p], s.cg, gI2[p] * s.cb));
                         const float dA = fmaf(T[p], gc, -D[p] * iom);   // dL/dalpha
                         D[p] = fmaf(Ta[p], gc, D[p]);
-                        gw[p] = dA * m;                                  // dL/de / ln 2
+                        gw[p] = dA * alpha[p];                           // dL/de / ln 2
                     }
-                    if (__ballot(any) != 0ull) {
-                        float v0 = gw[0] * dxs[0], v1 = gw[0] * dys[0], v2 = gw[0] * qs[0], v4 = gw[0];
+                    if (wave_clamped) {
+#pragma unroll
+                        for (int p = 0; p < kQuad; ++p)
+                            if (hit[p] && g[p] > alpha_max) gw[p] = 0.f;
+                    }
+                    if (wave_any) {
+                        // quad pixel p sits at (+(p & 1), +(p >> 1)) from pixel 0, so its
+                        // dx is dx0 - (p & 1) and its dy is dy0 - (p >> 1)
+                        const float gx = gw[1] + gw[3], gz = gw[0] + gw[2];
+                        const float v4 = gx + gz;
+                        const float v0 = fmaf(dx0, v4, -gx);
+                        const float v1 = fmaf(dy0, v4, -(gw[2] + gw[3]));
+                        float v2 = gw[0] * qs[0];
                         float v5 = Ta[0] * gI0[0], v6 = Ta[0] * gI1[0], v7 = Ta[0] * gI2[0];
 #pragma unroll
                         for (int p = 1; p < kQuad; ++p) {
-                            v0 = fmaf(gw[p], dxs[p], v0);
-                            v1 = fmaf(gw[p], dys[p], v1);
                             v2 = fmaf(gw[p], qs[p], v2);
-                            v4 += gw[p];
                             v5 = fmaf(Ta[p], gI0[p], v5);
                             v6 = fmaf(Ta[p], gI1[p], v6);
                             v7 = fmaf(Ta[p], gI2[p], v7);
                         }
-                        v0 = quad_sum(v0); v1 = quad_sum(v1); v2 = quad_sum(v2); v4 = quad_sum(v4);
-                        v5 = quad_sum(v5); v6 = quad_sum(v6); v7 = quad_sum(v7);
                         {   // the 4 lanes of a group hold bitwise-equal sums and store them
                             // to the same words, which keeps the DPP adds unconditional
                             float *dst = my_part + nslots * kSlotStride;
-                            dst[0] = v0; dst[1] = v1; dst[2] = v2;
-                            dst[4] = v4; dst[5] = v5; dst[6] = v6; dst[7] = v7;
+                            dst[0] = quad_sum(v0); dst[1] = quad_sum(v1); dst[2] = quad_sum(v2);
+                            dst[4] = quad_sum(v4); dst[5] = quad_sum(v5); dst[6] = quad_sum(v6);
+                            dst[7] = quad_sum(v7);
                         }
                         if (lane == j) s_gid[nslots] = id;
                         if (++nslots == kSlots) {

@@ -213,3 +213,30 @@ def test_workspace_reuse_matches_fresh_allocations(dpr):
         b.free()
         prev = a
     assert ws.reserved_bytes() > 0
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_clamped_alpha_gradients(dpr, mode):
+    """Splats of opacity 0.999 centred on pixel centres: alpha is clamped to
+    alpha_max there (the clamp passes no gradient to opacity or position),
+    mixed with ordinary splats around them."""
+    import torch
+    base = workloads.small_scene(97, 1200, extent=0.5, radius=0.05)
+    rng = np.random.default_rng(97)
+    cam = workloads.random_sphere_camera(rng, 48, 40)
+    m = 200
+    u = rng.integers(0, cam.width, m) + 0.5
+    v = rng.integers(0, cam.height, m) + 0.5
+    Z = rng.uniform(2.6, 3.4, m)
+    xc = np.stack([(u - cam.cx) * Z / cam.fx, (v - cam.cy) * Z / cam.fy, Z], 1)
+    xw = (xc - np.asarray(cam.t, np.float64)) @ np.asarray(cam.R, np.float64)     # R^T (x_cam - t)
+    sc = Scene(np.concatenate([base.xyz, xw.astype(np.float32)]),
+               np.concatenate([base.sh, (0.3 * rng.standard_normal((m,) + base.sh.shape[1:])).astype(np.float32)]),
+               np.concatenate([base.opacity, np.full(m, 0.999, np.float32)]),
+               np.concatenate([base.radius, np.full(m, 0.05, np.float32)]))
+    params = dpr.RenderParams(bwd_mode=mode)
+    gI, gT = _weights(97, [cam])
+    plan, got = _gpu_grads(dpr, [sc], [(0, cam)], params, gI, gT)
+    ref = oracle.render(sc, cam, oparams(params))
+    compare_images(to_np(plan.images[0]), to_np(plan.trans[0]), ref, label=f"clamped {mode}")
+    _check_scene(dpr, sc, [cam], params, gI, gT, got[0], f"clamped {mode}")
