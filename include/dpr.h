@@ -96,9 +96,8 @@ typedef struct dpr_view {
     int32_t reserved;        /* must be 0                                            */
     dpr_camera cam;
     float *image;            /* [height][width][3] output (pre-background colour)    */
-    float *trans;            /* [height][width] output: final transmittance T.
-                                Required when bwd_mode = DPR_BWD_STORED; may be NULL
-                                otherwise (then T is not written).                   */
+    float *trans;            /* [height][width] output: final transmittance T, or
+                                NULL (then T is not written).                        */
 } dpr_view;
 
 enum { DPR_SH_FRAME_CAMERA = 0, DPR_SH_FRAME_WORLD = 1 };
@@ -107,7 +106,7 @@ enum {
     DPR_FLAG_TIMING = 1,      /* record HIP events around every stage (dpr_stage_times)    */
     DPR_FLAG_STATS = 2,       /* count blended splats per pixel (dpr_plan_info.stats_off)  */
     DPR_FLAG_PERSISTENT = 4   /* forward compositing pops tiles from a work queue (the
-                                 backward always does)                                      */
+                                 backward always pops (tile, segment) work items)           */
 };
 
 typedef struct dpr_params {
@@ -116,8 +115,9 @@ typedef struct dpr_params {
     float alpha_max;         /* alpha clamp, (0, 0.999]; default 0.99                           */
     float z_near;            /* near plane, > 0; default 0.01                                   */
     int32_t sh_frame;        /* DPR_SH_FRAME_*                                                  */
-    int32_t bwd_mode;        /* DPR_BWD_*: keep the per-pixel stop index (4 B/px) in the
-                                forward workspace, or recompute it in backward                 */
+    int32_t bwd_mode;        /* DPR_BWD_*: the forward keeps the backward state in its
+                                workspace (stored), or the backward composites again to
+                                rebuild it (recompute: smaller forward workspace)             */
     int32_t flags;           /* DPR_FLAG_* bitmask                                              */
     int32_t reserved;        /* must be 0                                                       */
 } dpr_params;
@@ -179,8 +179,11 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes,
                      const dpr_view *views, int32_t n_views, const dpr_params *params,
                      void *plan_ws, size_t plan_ws_bytes, void *stream, dpr_plan **out);
 
-/* Bytes of the forward workspace (pair lists + per-pixel state), known after
- * dpr_plan_forward. */
+/* Bytes of the forward workspace, known after dpr_plan_forward: the per-tile
+ * pair lists and, in stored mode, the state the backward reads (per pixel the
+ * stop index and final (T, I); per tile a (T, I) checkpoint of every pixel each
+ * 512 list positions; the backward's work items), about 16 B per pair + 20 B
+ * per pixel on top of the 4 B per pair of the lists. */
 size_t dpr_workspace_bytes(const dpr_plan *plan);
 
 /* Emits the per-tile depth-ordered splat lists and composites every view front
@@ -189,7 +192,8 @@ size_t dpr_workspace_bytes(const dpr_plan *plan);
 int dpr_render_forward(dpr_plan *plan, void *ws, size_t ws_bytes, void *stream);
 
 /* Bytes of the backward scratch workspace (per-view-point gradient records,
- * plus the per-pixel state in recompute mode).  Needed only during the call. */
+ * plus, in recompute mode, the backward state that stored mode keeps in the
+ * forward workspace).  Needed only during the call. */
 size_t dpr_backward_ws_bytes(const dpr_plan *plan);
 
 /* Reverse-mode gradients of a loss L through the forward of this plan.

@@ -233,8 +233,26 @@ struct StageScope {
     }
 };
 
+// Per-pixel and per-tile state a backward reads: stop index, final (T, I),
+// (T, I) checkpoints every kBwdSeg list positions, and (tile, segment) work
+// items.  Held in the forward workspace in stored mode and in the backward
+// workspace in recompute mode.
+struct BwdState {
+    Region nlast, fin, ckpt, work;
+};
+
+BwdState add_bwd_state(Layout &L, const dpr_plan *p, bool on) {
+    BwdState s;
+    s.nlast = L.add(on ? 4 * p->sz.pixels : 0);
+    s.fin = L.add(on ? 16 * p->sz.pixels : 0);
+    s.ckpt = L.add(on ? 16ull * kTilePix * ckpt_slots(p->pairs, p->sz.tiles) : 0);
+    s.work = L.add(on ? 8 * work_capacity(p->pairs, p->sz.tiles) : 0);
+    return s;
+}
+
 struct FwdLayout {
-    Region pairs, nlast, stats, queue;
+    Region pairs, stats, counters;
+    BwdState st;
     uint64_t total = 0;
 };
 
@@ -242,15 +260,16 @@ FwdLayout fwd_layout(const dpr_plan *p) {
     Layout L;
     FwdLayout f;
     f.pairs = L.add(4 * p->pairs);
-    f.nlast = L.add(p->params.bwd_mode == DPR_BWD_STORED ? 4 * p->sz.pixels : 0);
+    f.st = add_bwd_state(L, p, p->params.bwd_mode == DPR_BWD_STORED);
     f.stats = L.add((p->params.flags & DPR_FLAG_STATS) ? 4 * p->sz.pixels : 0);
-    f.queue = L.add(16);
+    f.counters = L.add(16);
     f.total = L.total;
     return f;
 }
 
 struct BwdLayout {
-    Region tabs, sgrad, grad, nlast, tfin, queue;
+    Region tabs, sgrad, grad, counters;
+    BwdState st;
     uint64_t total = 0;
 };
 
@@ -260,12 +279,18 @@ BwdLayout bwd_layout(const dpr_plan *p) {
     b.tabs = L.add(8ull * 2 * p->sz.n_views);
     b.sgrad = L.add(sizeof(SceneDesc) * (uint64_t)p->sz.n_scenes);
     b.grad = L.add(32ull * p->sz.items);
-    const bool rec = p->params.bwd_mode == DPR_BWD_RECOMPUTE;
-    b.nlast = L.add(rec ? 4 * p->sz.pixels : 0);
-    b.tfin = L.add(rec ? 4 * p->sz.pixels : 0);
-    b.queue = L.add(16);
+    b.st = add_bwd_state(L, p, p->params.bwd_mode == DPR_BWD_RECOMPUTE);
+    b.counters = L.add(16);
     b.total = L.total;
     return b;
+}
+
+// Points the composite arguments at a backward state region.
+void set_bwd_state(CompositeArgs &a, uint8_t *base, const BwdState &s) {
+    a.nlast = reinterpret_cast<uint32_t *>(base + s.nlast.off);
+    a.fin = reinterpret_cast<float4 *>(base + s.fin.off);
+    a.ckpt = reinterpret_cast<float4 *>(base + s.ckpt.off);
+    a.work = reinterpret_cast<uint2 *>(base + s.work.off);
 }
 
 CompositeArgs composite_args(const dpr_plan *p, const void *ws) {
@@ -280,10 +305,13 @@ CompositeArgs composite_args(const dpr_plan *p, const void *ws) {
     a.rec = reinterpret_cast<const SplatRec *>(p->pws + p->lay.rec.off);
     a.pairs = reinterpret_cast<const uint32_t *>(w + f.pairs.off);
     a.tile_base = reinterpret_cast<const uint32_t *>(p->pws + p->lay.tile_base.off);
-    a.nlast = nullptr;
-    a.tfinal = nullptr;
+    a.write_views = 0;
     a.stats = nullptr;
-    a.queue = nullptr;
+    a.nlast = nullptr;
+    a.fin = nullptr;
+    a.ckpt = nullptr;
+    a.work = nullptr;
+    a.counters = nullptr;
     a.th = p->th;
     return a;
 }
@@ -516,12 +544,13 @@ int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
                                  reinterpret_cast<uint32_t *>(w + f.pairs.off), st));
     }
     CompositeArgs a = composite_args(p, ws);
-    a.nlast = f.nlast.bytes ? reinterpret_cast<uint32_t *>(w + f.nlast.off) : nullptr;
+    a.write_views = 1;
     a.stats = f.stats.bytes ? reinterpret_cast<uint32_t *>(w + f.stats.off) : nullptr;
-    a.queue = reinterpret_cast<uint32_t *>(w + f.queue.off);
+    if (p->params.bwd_mode == DPR_BWD_STORED) set_bwd_state(a, w, f.st);
+    a.counters = reinterpret_cast<uint32_t *>(w + f.counters.off);
     const bool persistent = (p->params.flags & DPR_FLAG_PERSISTENT) != 0;
     {
-        if (persistent) HIP_TRY(launch_fill_u32(a.queue, 0u, 4, st));
+        HIP_TRY(launch_fill_u32(a.counters, 0u, 4, st));
         StageScope sc_(p, DPR_STAGE_COMPOSITE_FWD, st);
         HIP_TRY(launch_composite_fwd(a, persistent, st));
     }
@@ -547,11 +576,8 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
     if (!dL_dimage) return fail(DPR_ERR_INVALID_ARG, "dL_dimage is NULL");
     const int V = p->sz.n_views, S = p->sz.n_scenes;
     const bool recompute = p->params.bwd_mode == DPR_BWD_RECOMPUTE;
-    for (int v = 0; v < V; ++v) {
+    for (int v = 0; v < V; ++v)
         if (!dL_dimage[v]) return fail(DPR_ERR_INVALID_ARG, "dL_dimage[%d] is NULL", v);
-        if (!recompute && !p->views[v].trans)
-            return fail(DPR_ERR_INVALID_ARG, "view %d: stored backward needs the trans output", v);
-    }
     if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t *bw = static_cast<uint8_t *>(bwd_ws);
@@ -574,38 +600,38 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
 
     CompositeArgs a = composite_args(p, ws);
     const bool persistent = (p->params.flags & DPR_FLAG_PERSISTENT) != 0;
-    uint32_t *queue = reinterpret_cast<uint32_t *>(bw + bl.queue.off);
-    BackwardArgs b;
+    uint32_t *counters = reinterpret_cast<uint32_t *>(bw + bl.counters.off);   // [0] recompute queue, [1] work
+    BackwardArgs b;                                                                // items, [2] backward queue
     b.dimage = reinterpret_cast<const float *const *>(bw + bl.tabs.off);
     b.dtrans = dL_dtrans ? reinterpret_cast<const float *const *>(bw + bl.tabs.off + 8ull * V) : nullptr;
     b.grad = reinterpret_cast<float *>(bw + bl.grad.off);
+    HIP_TRY(launch_fill_u32(counters, 0u, 4, st));
     if (recompute) {
-        a.nlast = reinterpret_cast<uint32_t *>(bw + bl.nlast.off);
-        a.tfinal = reinterpret_cast<float *>(bw + bl.tfin.off);
-        a.queue = queue;
-        if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 4, st));
+        // the forward again, writing only the backward state (to the backward workspace)
+        set_bwd_state(a, bw, bl.st);
+        a.counters = counters;
         StageScope sc_(p, DPR_STAGE_RECOMPUTE, st);
-        HIP_TRY(launch_recompute(a, persistent, st));
-        b.nlast = a.nlast;
-        b.tfinal = a.tfinal;
-        b.tfinal_from_views = 0;
+        HIP_TRY(launch_composite_fwd(a, persistent, st));
+        b.work_count = counters + 1;
     } else {
-        b.nlast = reinterpret_cast<const uint32_t *>(w + f.nlast.off);
-        b.tfinal = nullptr;
-        b.tfinal_from_views = 1;
+        set_bwd_state(a, const_cast<uint8_t *>(w), f.st);
+        b.work_count = reinterpret_cast<const uint32_t *>(w + f.counters.off) + 1;
     }
+    b.nlast = a.nlast;
+    b.fin = a.fin;
+    b.ckpt = a.ckpt;
+    b.work = a.work;
+    b.queue = counters + 2;
     a.nlast = nullptr;
-    a.tfinal = nullptr;
-    a.stats = nullptr;
-    a.queue = queue;
+    a.fin = nullptr;
+    a.ckpt = nullptr;
+    a.work = nullptr;
+    a.counters = nullptr;
     b.c = a;
     {
-        // the backward always runs as a persistent work queue: its tiles are
-        // long and uneven, and dynamic assignment balances them best
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(b.grad), 0u, 8ull * p->sz.items, st));
-        HIP_TRY(launch_fill_u32(queue, 0u, 4, st));
         StageScope sc_(p, DPR_STAGE_COMPOSITE_BWD, st);
-        HIP_TRY(launch_composite_bwd(b, true, st));
+        HIP_TRY(launch_composite_bwd(b, st));
     }
     {
         Tables tb = make_tables(p);
@@ -643,7 +669,7 @@ int dpr_plan_get_info(const dpr_plan *p, dpr_plan_info *out) {
     out->rect_off = (int64_t)p->lay.rect.off;
     out->range_off = (int64_t)p->lay.tile_base.off;
     out->pairs_off = (int64_t)f.pairs.off;
-    out->nlast_off = f.nlast.bytes ? (int64_t)f.nlast.off : -1;
+    out->nlast_off = f.st.nlast.bytes ? (int64_t)f.st.nlast.off : -1;
     out->stats_off = f.stats.bytes ? (int64_t)f.stats.off : -1;
     out->tile_size = kTile;
     out->chunk_items = kChunkItems;

@@ -11,16 +11,21 @@
 // leaves T < t_min; a wave leaves the chunk once its 128 pixels have stopped,
 // and the workgroup leaves the list once all 256 have.
 //
-// Backward: one wave per tile; each lane owns a 2x2 pixel quad so that the
-// per-splat reduction is shared by 256 pixels.  The list is walked in reverse
-// from the furthest stop index, recovering T_i = T_{i+1} / (1 - alpha_i)
-// (alpha <= alpha_max < 1), keeping the back-to-front colour sum, and folding
-// each (pixel, splat) contribution into 7 per-lane partial sums.  A chunk of 64
-// records is gathered one per lane, written to LDS and read back as
-// broadcasts.  The sums are reduced across each group of 4 lanes with DPP, the
-// 16 group sums of up to 8 splats are staged in LDS, and each flush completes
-// 56 sums and adds them to the per-item gradient records with one 64-lane
-// float atomic.
+// Backward: one wave per (tile, segment) work item; each lane owns a 2x2
+// pixel quad so that the per-splat reduction is shared by 256 pixels.  A
+// segment is 512 list positions; the forward left at each segment boundary a
+// checkpoint of every pixel's (T, I), so the segments of one long list are
+// processed independently and in parallel (the longest tiles no longer set
+// the kernel's duration).  A segment is walked in reverse from its end (or the
+// furthest stop index in it), recovering T_i = T_{i+1} / (1 - alpha_i)
+// (alpha <= alpha_max < 1), carrying D = dL/dI . B + dL/dT T_final with B the
+// colour blended behind (B = I_final - I_checkpoint at a segment end), and
+// folding each (pixel, splat) contribution into 7 per-lane partial sums.  A
+// chunk of 64 records is gathered one per lane, written to LDS and read back
+// as broadcasts.  The sums are reduced across each group of 4 lanes with DPP,
+// the 16 group sums of up to 8 splats are staged in LDS, and each flush
+// completes 56 sums and adds them to the per-item gradient records with one
+// 64-lane float atomic.
 #include "dpr_internal.h"
 
 namespace dpr {
@@ -89,11 +94,18 @@ constexpr int kFwdChunk = 2 * kFwdThreads;
 // A pixel is live while T >= t_min: T only decreases, by T alpha <= T, and
 // the pixel stops right after the blend that takes it below t_min, so the
 // test is exactly the stop rule.  Pixels outside the image start at T = -1.
-template <bool COLOR, bool PERSISTENT>
+//
+// With backward state requested (a.nlast non-null) the kernel also writes,
+// per pixel, the stop index and the final (T, I); at every list position
+// s * kBwdSeg it reaches, the (T, I) checkpoint of each pixel; and it appends
+// the tile's backward work items (tile, s) for s < ceil(max stop / kBwdSeg).
+static_assert(kBwdSeg % kFwdChunk == 0, "backward segments are whole forward chunks");
+
+template <bool PERSISTENT>
 __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     constexpr int PX = kFwdPx, kThreads = kFwdThreads, kChunk = kFwdChunk;
     __shared__ float4 s_r0[kChunk], s_r1[kChunk];
-    __shared__ uint32_t s_next;
+    __shared__ uint32_t s_next, s_max[2], s_work;
     const float neg_lambda = -a.th.lambda;
     const float alpha_max = a.th.alpha_max, t_min = a.th.t_min;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -104,8 +116,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
         const uint32_t ty = lt / (uint32_t)vd.tiles_x;
         const uint32_t tx = lt - ty * (uint32_t)vd.tiles_x;
         const uint32_t start = a.tile_base[tile], end = a.tile_base[tile + 1];
-        const int x0 = (int)(tx * kTile) + 2 * (lane & 7);
-        const int y0 = (int)(ty * kTile) + 8 * wave + (lane >> 3);
+        const int lx = 2 * (lane & 7), ly = 8 * wave + (lane >> 3);     // in-tile position of pixel 0
+        const int x0 = (int)(tx * kTile) + lx, y0 = (int)(ty * kTile) + ly;
         float ux[PX], uy[PX], T[PX], I0[PX], I1[PX], I2[PX];
         uint32_t nlast[PX], nblend[PX];
 #pragma unroll
@@ -129,6 +141,12 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             }
         }
         for (uint32_t base = start; base < end; base += kChunk) {
+            if (a.ckpt && base > start && (base - start) % (uint32_t)kBwdSeg == 0) {
+                float4 *dst = a.ckpt + ckpt_slot(start, tile, (base - start) / (uint32_t)kBwdSeg) * kTilePix +
+                              ly * kTile + lx;
+#pragma unroll
+                for (int p = 0; p < PX; ++p) dst[p] = make_float4(T[p], I0[p], I1[p], I2[p]);
+            }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 s_r0[h * kThreads + tid] = n0[h];
@@ -176,12 +194,10 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                         for (int p = 0; p < PX; ++p) {
                             const float alpha = hit[p] ? splat_alpha(e[p], alpha_max) : 0.f;
                             const float Ta = T[p] * alpha;
-                            if (COLOR) {
-                                I0[p] = fmaf(Ta, s.cr, I0[p]);
-                                I1[p] = fmaf(Ta, s.cg, I1[p]);
-                                I2[p] = fmaf(Ta, s.cb, I2[p]);
-                                nblend[p] += hit[p] ? 1u : 0u;
-                            }
+                            I0[p] = fmaf(Ta, s.cr, I0[p]);
+                            I1[p] = fmaf(Ta, s.cg, I1[p]);
+                            I2[p] = fmaf(Ta, s.cb, I2[p]);
+                            nblend[p] += hit[p] ? 1u : 0u;
                             T[p] = T[p] - Ta;                       // T (1 - alpha)
                             if (hit[p] && T[p] < t_min) nlast[p] = pos1;
                         }
@@ -193,25 +209,39 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             for (int p = 0; p < PX; ++p) any_live = any_live || T[p] >= t_min;
             if (__syncthreads_count(any_live) == 0) break;
         }
+        uint32_t mymax = 0;
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
             const int px = x0 + p, py = y0;
             if (px >= vd.width || py >= vd.height) continue;
             const uint64_t lpix = (uint64_t)py * (uint64_t)vd.width + (uint64_t)px;
             const uint64_t pix = vd.pix_off + lpix;
-            if (COLOR) {
+            if (a.write_views) {
                 float *img = vd.image + 3 * lpix;
                 img[0] = I0[p]; img[1] = I1[p]; img[2] = I2[p];
                 if (vd.trans) vd.trans[lpix] = T[p];
                 if (a.stats) a.stats[pix] = nblend[p];
-            } else {
-                a.tfinal[pix] = T[p];
             }
-            if (a.nlast) a.nlast[pix] = nlast[p];
+            if (a.nlast) {
+                a.nlast[pix] = nlast[p];
+                a.fin[pix] = make_float4(T[p], I0[p], I1[p], I2[p]);
+                mymax = max(mymax, nlast[p]);
+            }
+        }
+        if (a.nlast) {
+            // the tile's backward work items: one per kBwdSeg positions below its largest stop index
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) mymax = max(mymax, (uint32_t)__shfl_xor((int)mymax, d, 64));
+            if (lane == 0) s_max[wave] = mymax;
+            __syncthreads();
+            const uint32_t nseg = (max(s_max[0], s_max[1]) + (uint32_t)kBwdSeg - 1) / (uint32_t)kBwdSeg;
+            if (tid == 0) s_work = nseg ? atomicAdd(a.counters + 1, nseg) : 0u;
+            __syncthreads();
+            for (uint32_t i = tid; i < nseg; i += kThreads) a.work[s_work + i] = make_uint2(tile, i);
         }
         if (!PERSISTENT) break;
         __syncthreads();
-        if (tid == 0) s_next = atomicAdd(a.queue, 1u) + gridDim.x;
+        if (tid == 0) s_next = atomicAdd(a.counters, 1u) + gridDim.x;
         __syncthreads();
         tile = s_next;
     }
@@ -256,7 +286,10 @@ __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t 
     }
 }
 
-template <bool PERSISTENT>
+// Persistent: each wave pops (tile, segment) work items until the list is
+// exhausted.  Segment s covers list positions [s kBwdSeg, (s + 1) kBwdSeg); a
+// pixel still live after the segment starts from the checkpoint there, any
+// other pixel from its final state.
 __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     __shared__ float s_part[kSlots * kSlotStride];
     __shared__ uint32_t s_gid[kSlots];
@@ -266,10 +299,15 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     const float alpha_max = a.th.alpha_max;
     const int lane = threadIdx.x;
     float *const my_part = s_part + (lane >> 2) * kQuadStride;
+    const uint32_t nwork = *b.work_count;
 
-    for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_remap(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
+    for (uint32_t w = blockIdx.x; w < nwork;) {
+        const uint2 item = b.work[w];
+        const uint32_t tile = item.x;
+        const uint32_t seg_beg = item.y * (uint32_t)kBwdSeg, seg_end = seg_beg + (uint32_t)kBwdSeg;
         const TileCtx c = tile_ctx(a, tile);
         const ViewDesc &vd = a.views[c.v];
+        const float4 *ck = b.ckpt + ckpt_slot(c.start, tile, item.y + 1) * kTilePix;
         // per pixel: T (recovered front-to-back transmittance), dL/dI, and
         // D = dL/dI . B + dL/dT * T_final with B = sum over the blended splats
         // behind of T_k alpha_k c_k, so that dL/dalpha_i = T_i (dL/dI . c_i) - D / (1 - alpha_i)
@@ -286,21 +324,31 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 const uint64_t lpix = (uint64_t)py * (uint64_t)vd.width + (uint64_t)px;
                 const uint64_t pix = vd.pix_off + lpix;
                 nl[p] = b.nlast[pix];
-                T[p] = b.tfinal_from_views ? vd.trans[lpix] : b.tfinal[pix];
+                const float4 f = b.fin[pix];
                 const float *gi = b.dimage[c.v] + 3 * lpix;
                 gI0[p] = gi[0]; gI1[p] = gi[1]; gI2[p] = gi[2];
-                if (b.dtrans && b.dtrans[c.v]) D[p] = b.dtrans[c.v][lpix] * T[p];   // dL/dT * T_final
-                mymax = max(mymax, nl[p]);
+                const float gT = (b.dtrans && b.dtrans[c.v]) ? b.dtrans[c.v][lpix] : 0.f;
+                if (nl[p] > seg_end) {
+                    // live past this segment: B = I_final - (I after the first seg_end splats)
+                    const float4 k = ck[(py - (c.y0 & ~(kTile - 1))) * kTile + (px - (c.x0 & ~(kTile - 1)))];
+                    T[p] = k.x;
+                    D[p] = fmaf(gI0[p], f.y - k.y, fmaf(gI1[p], f.z - k.z, fmaf(gI2[p], f.w - k.w, gT * f.x)));
+                } else {
+                    T[p] = f.x;
+                    D[p] = gT * f.x;                                        // dL/dT * T_final
+                }
+                mymax = max(mymax, min(nl[p], seg_end));
             }
         }
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) mymax = max(mymax, (uint32_t)__shfl_xor((int)mymax, d, 64));
         const uint32_t maxn = (uint32_t)__builtin_amdgcn_readfirstlane((int)mymax);
 
-        // chunks back to front: [cbeg, cbeg + 64) aligned to the list start
+        // chunks back to front: [cbeg, cbeg + 64) aligned to the segment start
         int nslots = 0;
-        if (maxn > 0) {
-            uint32_t cbeg = c.start + ((maxn - 1) / kCompLanes) * kCompLanes;
+        if (maxn > seg_beg) {
+            const uint32_t sbeg = c.start + seg_beg;
+            uint32_t cbeg = sbeg + ((maxn - seg_beg - 1) / kCompLanes) * kCompLanes;
             const uint32_t lend = c.start + maxn;
             float4 n0, n1;
             uint32_t nid;
@@ -311,7 +359,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 s_rec[2 * lane] = n0;
                 s_rec[2 * lane + 1] = n1;
                 __syncthreads();
-                const bool more = cbeg > c.start;
+                const bool more = cbeg > sbeg;
                 if (more) load_rec(a, cbeg - kCompLanes + lane, lend, n0, n1, nid);
                 const int cnt = (int)min((uint32_t)kCompLanes, lend - cbeg);
                 for (int j = cnt - 1; j >= 0; --j) {
@@ -402,8 +450,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
             flush_slots(s_part, s_gid, nslots, b.grad, lane);
             __syncthreads();
         }
-        if (!PERSISTENT) break;
-        tile = pop_tile(a.queue);
+        w = pop_tile(b.queue);
     }
 }
 
@@ -419,33 +466,19 @@ static uint32_t persistent_grid(uint32_t tiles, uint32_t per_cu) {
 hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (a.total_tiles == 0) return hipSuccess;
     if (persistent) {
-        hipLaunchKernelGGL((k_composite<true, true>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0,
-                           st, a);
+        hipLaunchKernelGGL((k_composite<true>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0, st,
+                           a);
     } else {
-        hipLaunchKernelGGL((k_composite<true, false>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
+        hipLaunchKernelGGL((k_composite<false>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_recompute(const CompositeArgs &a, bool persistent, hipStream_t st) {
-    if (a.total_tiles == 0) return hipSuccess;
-    if (persistent) {
-        hipLaunchKernelGGL((k_composite<false, true>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0,
-                           st, a);
-    } else {
-        hipLaunchKernelGGL((k_composite<false, false>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_composite_bwd(const BackwardArgs &b, bool persistent, hipStream_t st) {
+// Persistent, 16 waves per CU; the grid is sized from the tile count (the
+// work-item count is read by the kernel itself).
+hipError_t launch_composite_bwd(const BackwardArgs &b, hipStream_t st) {
     if (b.c.total_tiles == 0) return hipSuccess;
-    if (persistent) {
-        hipLaunchKernelGGL((k_composite_bwd<true>), dim3(persistent_grid(b.c.total_tiles, 16)), dim3(kCompLanes), 0,
-                           st, b);
-    } else {
-        hipLaunchKernelGGL((k_composite_bwd<false>), dim3(b.c.total_tiles), dim3(kCompLanes), 0, st, b);
-    }
+    hipLaunchKernelGGL(k_composite_bwd, dim3(persistent_grid(b.c.total_tiles, 16)), dim3(kCompLanes), 0, st, b);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ constexpr int kTilePix = kTile * kTile;   // 256 pixels per tile
 constexpr int kChunkItems = 512;          // depth-sorted items per binning chunk
 constexpr int kBandTiles = 8192;          // tiles of one view handled per LDS band
 constexpr int kSegChunks = 16;            // chunks per column-scan segment
+constexpr int kBwdSeg = 512;              // list positions per backward work item
 constexpr int kSortThreads = 256;
 constexpr int kSortItemsPerThread = 8;
 constexpr int kSortTile = kSortThreads * kSortItemsPerThread;   // 2048 keys per sort block
@@ -183,6 +184,17 @@ hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *o
                             const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
                             const uint32_t *tile_base, uint32_t *pairs, hipStream_t st);
 
+// Backward state of a tile list at the list positions s * kBwdSeg (s >= 1):
+// per pixel (T, I) after the first s * kBwdSeg splats, 256 float4 per slot in
+// row-major pixel order.  Slot of (tile t, s) = floor(tile_base[t] / kBwdSeg)
+// + t + s: consecutive tiles' slot ranges never overlap, and every slot is
+// below floor(pairs / kBwdSeg) + tiles + 1.
+__host__ __device__ inline uint64_t ckpt_slot(uint32_t tile_base_t, uint32_t tile, uint32_t s) {
+    return (uint64_t)(tile_base_t / (uint32_t)kBwdSeg) + tile + s;
+}
+inline uint64_t ckpt_slots(uint64_t pairs, uint64_t tiles) { return pairs / kBwdSeg + tiles + 2; }
+inline uint64_t work_capacity(uint64_t pairs, uint64_t tiles) { return pairs / kBwdSeg + tiles + 1; }
+
 struct CompositeArgs {
     const ViewDesc *views;
     const uint32_t *tile_start;
@@ -191,25 +203,31 @@ struct CompositeArgs {
     const SplatRec *rec;
     const uint32_t *pairs;
     const uint32_t *tile_base;  // [tiles + 1] first pair of each tile
-    uint32_t *nlast;            // per-pixel stop index (or null)
-    float *tfinal;              // per-pixel final T for recompute (or null)
+    int write_views;            // 1: write image / trans / stats of each view
     uint32_t *stats;            // per-pixel blended count (or null)
-    uint32_t *queue;            // persistent work counter (or null)
+    // backward state (all null for a forward that no backward will follow)
+    uint32_t *nlast;            // per-pixel stop index
+    float4 *fin;                // per-pixel final (T, I)
+    float4 *ckpt;               // checkpoint slots (see ckpt_slot)
+    uint2 *work;                // (tile, segment) backward work items
+    uint32_t *counters;         // [0] persistent queue, [1] work items appended
     Thresholds th;
 };
 hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st);
-hipError_t launch_recompute(const CompositeArgs &a, bool persistent, hipStream_t st);
 
 struct BackwardArgs {
     CompositeArgs c;
     const float *const *dimage;     // device table [n_views] of dL/dimage pointers
     const float *const *dtrans;     // device table [n_views] (entries may be null) or null
-    const uint32_t *nlast;          // per-pixel stop index
-    const float *tfinal;            // per-pixel T (trans output or recomputed)
-    int tfinal_from_views;          // 1: read T from view.trans
+    const uint32_t *nlast;
+    const float4 *fin;
+    const float4 *ckpt;
+    const uint2 *work;
+    const uint32_t *work_count;
+    uint32_t *queue;
     float *grad;                    // [items][8] accumulators
 };
-hipError_t launch_composite_bwd(const BackwardArgs &a, bool persistent, hipStream_t st);
+hipError_t launch_composite_bwd(const BackwardArgs &a, hipStream_t st);
 
 hipError_t launch_point_bwd(const Tables &tb, const Thresholds &th, int sh_degree, uint32_t point_blocks,
                             const float *grad, hipStream_t st);

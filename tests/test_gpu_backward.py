@@ -240,3 +240,32 @@ def test_clamped_alpha_gradients(dpr, mode):
     ref = oracle.render(sc, cam, oparams(params))
     compare_images(to_np(plan.images[0]), to_np(plan.trans[0]), ref, label=f"clamped {mode}")
     _check_scene(dpr, sc, [cam], params, gI, gT, got[0], f"clamped {mode}")
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_long_lists_split_into_backward_segments(dpr, mode):
+    """5000 faint, wide splats over a 40x40 view: tile lists of thousands of
+    entries whose stop indices span several backward segments (512 list
+    positions each), some pixels stopping inside a segment and some not
+    stopping at all; full-frame gradients against the oracle."""
+    import torch
+    rng = np.random.default_rng(98)
+    n = 5000
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    xyz = (0.3 * d * rng.random(n)[:, None] ** (1.0 / 3.0)).astype(np.float32)
+    sh = (0.3 * rng.standard_normal((n, 9, 3))).astype(np.float32)
+    op = rng.uniform(0.005, 0.03, n).astype(np.float32)
+    sc = Scene(xyz, sh, op, np.full(n, 0.15, np.float32))
+    cams = [workloads.random_sphere_camera(rng, 40, 40), workloads.random_sphere_camera(rng, 21, 37)]
+    params = dpr.RenderParams(bwd_mode=mode)
+    gI, gT = _weights(98, cams)
+    plan, got = _gpu_grads(dpr, [sc], [(0, c) for c in cams], params, gI, gT)
+    if mode == "stored":
+        inf = plan.info()
+        nl = plan.ws[inf.nlast_off: inf.nlast_off + 4 * inf.pixels].view(torch.int32).cpu().numpy()
+        assert nl.max() > 3 * 512 and nl.min() < nl.max()
+    for v, cam in enumerate(cams):
+        ref = oracle.render(sc, cam, oparams(params))
+        compare_images(to_np(plan.images[v]), to_np(plan.trans[v]), ref, label=f"long lists {mode} view {v}")
+    _check_scene(dpr, sc, cams, params, gI, gT, got[0], f"long lists {mode}")
