@@ -182,7 +182,7 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes,
 /* Bytes of the forward workspace, known after dpr_plan_forward: the per-tile
  * pair lists and, in stored mode, the state the backward reads (per pixel the
  * stop index and final (T, I); per tile a (T, I) checkpoint of every pixel each
- * 512 list positions; the backward's work items), about 16 B per pair + 20 B
+ * 256 list positions; the backward's work items), up to 16 B per pair + 20 B
  * per pixel on top of the 4 B per pair of the lists. */
 size_t dpr_workspace_bytes(const dpr_plan *plan);
 

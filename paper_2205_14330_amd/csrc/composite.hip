@@ -13,7 +13,7 @@
 //
 // Backward: one wave per (tile, segment) work item; each lane owns a 2x2
 // pixel quad so that the per-splat reduction is shared by 256 pixels.  A
-// segment is 512 list positions; the forward left at each segment boundary a
+// segment is 256 list positions; the forward left at each segment boundary a
 // checkpoint of every pixel's (T, I), so the segments of one long list are
 // processed independently and in parallel (the longest tiles no longer set
 // the kernel's duration).  A segment is walked in reverse from its end (or the

@@ -13,7 +13,7 @@ constexpr int kTilePix = kTile * kTile;   // 256 pixels per tile
 constexpr int kChunkItems = 512;          // depth-sorted items per binning chunk
 constexpr int kBandTiles = 8192;          // tiles of one view handled per LDS band
 constexpr int kSegChunks = 16;            // chunks per column-scan segment
-constexpr int kBwdSeg = 512;              // list positions per backward work item
+constexpr int kBwdSeg = 256;              // list positions per backward work item
 constexpr int kSortThreads = 256;
 constexpr int kSortItemsPerThread = 8;
 constexpr int kSortTile = kSortThreads * kSortItemsPerThread;   // 2048 keys per sort block

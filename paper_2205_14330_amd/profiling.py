@@ -37,9 +37,8 @@ KERNELS = {
     "dpr::k_col_segscan": "col_segscan",
     "dpr::k_col_down": "col_down",
     "dpr::k_tile_emit": "tile_emit",
-    "dpr::k_composite<true": "composite_fwd",
-    "dpr::k_composite<false": "recompute",
     "dpr::k_composite_bwd": "composite_bwd",
+    "dpr::k_composite<": "composite_fwd",       # forward, and the backward's recompute pass
     "dpr::k_point_bwd": "point_bwd",
     "dpr::k_fill_u32": "fill",
 }
