@@ -39,13 +39,16 @@ class Params:
     alpha_max: float = ALPHA_MAX
     z_near: float = Z_NEAR
     sh_frame: int = 0          # 0 = camera-frame direction (Eq. 3), 1 = world frame
+    max_splats: int = 0        # > 0: a pixel blends at most this many splats (Sec. 3.3's n)
+    kernel_norm: int = 0       # 1: keep Eq. (5)'s 1/sqrt(2 pi r^2) prefactor, per axis (2 pi sx sy)^-1/2
 
     @staticmethod
     def untruncated(z_near: float = Z_NEAR, sh_frame: int = 0) -> "Params":
         return Params(0.0, 0.0, 1.0, z_near, sh_frame)
 
     def array(self) -> np.ndarray:
-        return np.array([self.alpha_min, self.t_min, self.alpha_max, self.z_near], np.float64)
+        return np.array([self.alpha_min, self.t_min, self.alpha_max, self.z_near, float(self.max_splats),
+                         float(self.kernel_norm)], np.float64)
 
 
 def build(force: bool = True) -> str:
@@ -258,3 +261,24 @@ def backward_double(xyz, sh, opacity, radius, cam, dL_dimage, dL_dtrans=None, pa
     if rc:
         raise ValueError("oracle_backward failed")
     return Grads(gx, gs, go)
+
+
+def loss_l2_tv(render, target, lam: float):
+    """Eq. (8) for one image: the squared L2 difference plus lam times the
+    anisotropic total variation |grad_x R|_1 + |grad_y R|_1 of the render, with
+    forward differences between horizontally and vertically adjacent pixels,
+    summed over pixels and channels.  Returns (loss, dL/drender) in FP64; the
+    subgradient of |d| at d = 0 is taken as 0.  render, target: [H][W][3]."""
+    R = np.asarray(render, np.float64)
+    I = np.asarray(target, np.float64)
+    diff = R - I
+    gx = R[:, 1:, :] - R[:, :-1, :]
+    gy = R[1:, :, :] - R[:-1, :, :]
+    loss = float(np.sum(diff * diff) + lam * (np.abs(gx).sum() + np.abs(gy).sum()))
+    grad = 2.0 * diff
+    sx, sy = np.sign(gx), np.sign(gy)
+    grad[:, 1:, :] += lam * sx
+    grad[:, :-1, :] -= lam * sx
+    grad[1:, :, :] += lam * sy
+    grad[:-1, :, :] -= lam * sy
+    return loss, grad

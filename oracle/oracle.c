@@ -37,6 +37,8 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#define OR_PI 3.14159265358979323846
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -146,6 +148,7 @@ typedef struct {
     double sx, sy;     /* screen-space Gaussian sigma (pixels)     */
     double dir[3];     /* SH direction (Eq. 3, camera or world)    */
     double c[3];       /* colour, Eq. (4)                          */
+    double k;          /* kernel prefactor: 1, or (2 pi sx sy)^-1/2 with the literal Eq. (5) normalisation */
     float zkey;        /* float32 depth key used for ordering      */
     int valid;         /* in front of the near plane               */
 } or_point;
@@ -160,7 +163,7 @@ static float depth_key(const double *cam, const double *P)
 }
 
 static void project_point(const double *cam, const double *P, const double *h, int degree,
-                          double radius, double z_near, int sh_frame, or_point *o)
+                          double radius, double z_near, int sh_frame, int kernel_norm, or_point *o)
 {
     const double *R = cam, *t = cam + 9;
     const double fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
@@ -180,6 +183,9 @@ static void project_point(const double *cam, const double *P, const double *h, i
     /* world radius scaled into pixels by the perspective divide */
     o->sx = fx * radius / o->X[2];
     o->sy = fy * radius / o->X[2];
+    /* Eq. (5) as printed carries 1/sqrt(2 pi r^2) with r the kernel radius; with
+     * a per-axis sigma the 2-D analogue is 1/sqrt(2 pi sx sy) */
+    o->k = kernel_norm ? 1.0 / sqrt(2.0 * OR_PI * o->sx * o->sy) : 1.0;
 
     /* Eq. (3): camera-frame unit direction; sh_frame = 1 rotates it back to world */
     {
@@ -213,7 +219,7 @@ int oracle_project(int64_t n, const double *xyz, const double *sh, int degree,
     for (i = 0; i < n; ++i) {
         or_point p;
         memset(&p, 0, sizeof(p));
-        project_point(cam, xyz + 3 * i, sh + (int64_t)K * 3 * i, degree, radius[i], z_near, sh_frame, &p);
+        project_point(cam, xyz + 3 * i, sh + (int64_t)K * 3 * i, degree, radius[i], z_near, sh_frame, 0, &p);
         out[i * 12 + 0] = p.px;  out[i * 12 + 1] = p.py;
         out[i * 12 + 2] = p.sx;  out[i * 12 + 3] = p.sy;
         out[i * 12 + 4] = p.X[2];
@@ -273,7 +279,16 @@ int oracle_depth_order(int64_t n, const double *xyz, const double *cam, double z
  * ------------------------------------------------------------------------- */
 typedef struct {
     double alpha_min, t_min, alpha_max, z_near;
+    int64_t max_splats;      /* > 0: a pixel blends at most this many splats */
+    int kernel_norm;         /* 1: Eq. (5)'s normalisation prefactor is kept  */
 } or_params;
+
+static void read_params(const double *params, or_params *pr)
+{
+    pr->alpha_min = params[0]; pr->t_min = params[1]; pr->alpha_max = params[2]; pr->z_near = params[3];
+    pr->max_splats = (int64_t)params[4];
+    pr->kernel_norm = params[5] != 0.0;
+}
 
 static int splat_alpha(const or_point *p, double o, double ux, double uy, const or_params *pr,
                        double *alpha, double *G, int *clamped, double *dx, double *dy)
@@ -281,7 +296,7 @@ static int splat_alpha(const or_point *p, double o, double ux, double uy, const 
     double ex = p->px - ux, ey = p->py - uy;
     double q = ex * ex / (p->sx * p->sx) + ey * ey / (p->sy * p->sy);
     double g = exp(-0.5 * q);
-    double a = o * g;
+    double a = o * p->k * g;
     if (!(a >= pr->alpha_min)) return 0;
     *G = g; *dx = ex; *dy = ey;
     if (a > pr->alpha_max) { *alpha = pr->alpha_max; *clamped = 1; }
@@ -295,8 +310,8 @@ static int support_box(const or_point *p, double o, const or_params *pr,
 {
     double s;
     if (!(pr->alpha_min > 0.0)) return -1;            /* unbounded */
-    if (!(o >= pr->alpha_min)) return 0;               /* never a candidate */
-    s = sqrt(2.0 * log(o / pr->alpha_min)) * (1.0 + 1e-9) + 1e-9;
+    if (!(o * p->k >= pr->alpha_min)) return 0;        /* never a candidate */
+    s = sqrt(2.0 * log(o * p->k / pr->alpha_min)) * (1.0 + 1e-9) + 1e-9;
     *x0 = p->px - s * p->sx; *x1 = p->px + s * p->sx;
     *y0 = p->py - s * p->sy; *y1 = p->py + s * p->sy;
     return 1;
@@ -431,6 +446,7 @@ static int64_t composite_pixel(const or_lists *L, const or_point *pts, const dou
         T *= (1.0 - alpha);
         ++nh;
         if (T < pr->t_min) { *stopped = 1; break; }
+        if (pr->max_splats > 0 && nh >= pr->max_splats) { *stopped = 1; break; }
     }
     (void)indirect;
     *T_out = T;
@@ -438,17 +454,18 @@ static int64_t composite_pixel(const or_lists *L, const or_point *pts, const dou
 }
 
 static void project_all(int64_t n, const double *xyz, const double *sh, int degree, const double *radius,
-                        const double *cam, double z_near, int sh_frame, or_point *pts)
+                        const double *cam, const or_params *pr, int sh_frame, or_point *pts)
 {
     int64_t i;
     int K = sh_count(degree);
     for (i = 0; i < n; ++i)
-        project_point(cam, xyz + 3 * i, sh + (int64_t)K * 3 * i, degree, radius[i], z_near, sh_frame, &pts[i]);
+        project_point(cam, xyz + 3 * i, sh + (int64_t)K * 3 * i, degree, radius[i], pr->z_near, sh_frame,
+                      pr->kernel_norm, &pts[i]);
 }
 
 /*
  * Forward render of one view.
- *   params[4] = alpha_min, t_min, alpha_max, z_near
+ *   params[6] = alpha_min, t_min, alpha_max, z_near, max_splats (0: no cap), kernel_norm (0/1)
  *   pix: npix linear pixel indices (y * width + x), or NULL for the whole image
  *        in row-major order (npix must then equal width * height)
  *   image[npix][3], trans[npix]; ncontrib[npix] (nullable) = number of blended
@@ -465,9 +482,9 @@ int oracle_render(int64_t n, const double *xyz, const double *sh, int degree, co
     int64_t p;
     if (degree < 0 || degree > 3 || width < 1 || height < 1 || n < 0) return 1;
     if (!pix && npix != (int64_t)width * height) return 1;
-    pr.alpha_min = params[0]; pr.t_min = params[1]; pr.alpha_max = params[2]; pr.z_near = params[3];
+    read_params(params, &pr);
     pts = (or_point *)calloc((size_t)(n > 0 ? n : 1), sizeof(or_point));
-    project_all(n, xyz, sh, degree, radius, cam, pr.z_near, sh_frame, pts);
+    project_all(n, xyz, sh, degree, radius, cam, &pr, sh_frame, pts);
     build_lists(n, pts, opacity, width, height, &pr, mode, &L);
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -521,9 +538,9 @@ int oracle_backward(int64_t n, const double *xyz, const double *sh, int degree, 
     if (degree < 0 || degree > 3 || width < 1 || height < 1 || n < 0) return 1;
     if (!pix && npix != (int64_t)width * height) return 1;
     K = sh_count(degree);
-    pr.alpha_min = params[0]; pr.t_min = params[1]; pr.alpha_max = params[2]; pr.z_near = params[3];
+    read_params(params, &pr);
     pts = (or_point *)calloc((size_t)(n > 0 ? n : 1), sizeof(or_point));
-    project_all(n, xyz, sh, degree, radius, cam, pr.z_near, sh_frame, pts);
+    project_all(n, xyz, sh, degree, radius, cam, &pr, sh_frame, pts);
     build_lists(n, pts, opacity, width, height, &pr, mode, &L);
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -565,13 +582,19 @@ int oracle_backward(int64_t n, const double *xyz, const double *sh, int degree, 
                 for (ch = 0; ch < 3; ++ch) R[ch] = e->alpha * q->c[ch] + (1.0 - e->alpha) * R[ch];
                 Q *= (1.0 - e->alpha);
                 if (!e->clamped) {
+                    /* alpha = o k G: dalpha/do = k G, dalpha/dq = -o k G / 2, and with the
+                     * normalisation k = (2 pi sx sy)^-1/2 also dalpha/dsx = -alpha / (2 sx) */
                     double o = opacity[e->i];
-                    double dq = dA * (-0.5 * o * e->G);
-                    g->dop += dA * e->G;
+                    double dq = dA * (-0.5 * o * q->k * e->G);
+                    g->dop += dA * q->k * e->G;
                     g->dpx += dq * 2.0 * e->dx / (q->sx * q->sx);
                     g->dpy += dq * 2.0 * e->dy / (q->sy * q->sy);
                     g->dsx += dq * (-2.0 * e->dx * e->dx / (q->sx * q->sx * q->sx));
                     g->dsy += dq * (-2.0 * e->dy * e->dy / (q->sy * q->sy * q->sy));
+                    if (pr.kernel_norm) {
+                        g->dsx += dA * (-0.5 * e->alpha / q->sx);
+                        g->dsy += dA * (-0.5 * e->alpha / q->sy);
+                    }
                 }
             }
         }
