@@ -105,8 +105,11 @@ enum { DPR_BWD_STORED = 0, DPR_BWD_RECOMPUTE = 1 };
 enum {
     DPR_FLAG_TIMING = 1,      /* record HIP events around every stage (dpr_stage_times)    */
     DPR_FLAG_STATS = 2,       /* count blended splats per pixel (dpr_plan_info.stats_off)  */
-    DPR_FLAG_PERSISTENT = 4   /* forward compositing pops tiles from a work queue (the
+    DPR_FLAG_PERSISTENT = 4,  /* forward compositing pops tiles from a work queue (the
                                  backward always pops (tile, segment) work items)           */
+    DPR_FLAG_KERNEL_NORM = 8  /* keep Eq. (5)'s normalisation: alpha = min(alpha_max,
+                                 o (2 pi sx sy)^-1/2 G), i.e. 1/sqrt(2 pi r^2) per the
+                                 printed formula with r the screen sigma (per axis)         */
 };
 
 typedef struct dpr_params {
@@ -119,7 +122,8 @@ typedef struct dpr_params {
                                 workspace (stored), or the backward composites again to
                                 rebuild it (recompute: smaller forward workspace)             */
     int32_t flags;           /* DPR_FLAG_* bitmask                                              */
-    int32_t reserved;        /* must be 0                                                       */
+    int32_t max_splats;      /* > 0: a pixel blends at most this many splats, its first ones
+                                in depth order (Sec. 3.3 uses n = 15); 0: no cap              */
 } dpr_params;
 
 typedef struct dpr_plan dpr_plan;   /* opaque, host-side */
@@ -209,6 +213,31 @@ int dpr_render_backward(dpr_plan *plan, const void *ws, size_t ws_bytes,
                         const float *const *dL_dimage, const float *const *dL_dtrans,
                         float *const *dL_dxyz, float *const *dL_dsh, float *const *dL_dopacity,
                         void *bwd_ws, size_t bwd_ws_bytes, void *stream);
+
+/* Bytes of the device workspace dpr_loss_l2_tv needs for n_images images of
+ * the given sizes (host arrays); 0 on invalid sizes (see dpr_last_error). */
+size_t dpr_loss_ws_bytes(int32_t n_images, const int32_t *widths, const int32_t *heights);
+
+/* The training loss of Eq. (8) (Sec. 3.3) and its gradient, for n_images
+ * images in one pass:
+ *   loss[v] = sum_{x,y,c} (R - I)^2
+ *             + lambda (sum |R(x+1,y,c) - R(x,y,c)| + sum |R(x,y+1,c) - R(x,y,c)|)
+ * i.e. squared L2 plus lambda times the anisotropic total variation (forward
+ * differences between adjacent pixels, summed over channels; the paper uses
+ * lambda = 0.01), and dL/dR with the subgradient of |d| at d = 0 taken as 0.
+ *   render[v], target[v]  device [H][W][3] float32 (host array of pointers)
+ *   dL_drender[v]         device [H][W][3] float32, OVERWRITTEN; may not alias
+ *                         render[v] or target[v]
+ *   widths, heights       host arrays
+ *   loss                  device double[n_images], OVERWRITTEN; each image's sum
+ *                         is reduced in a fixed order (deterministic)
+ *   ws                    device workspace of dpr_loss_ws_bytes bytes, needed
+ *                         until the work on `stream` has run
+ * Asynchronous on `stream`.  Returns DPR_ERR_INVALID_ARG on NULL pointers,
+ * aliasing outputs, sizes outside [1, 16384] or lambda < 0 / non-finite. */
+int dpr_loss_l2_tv(int32_t n_images, const float *const *render, const float *const *target,
+                   const int32_t *widths, const int32_t *heights, float lambda, float *const *dL_drender,
+                   double *loss, void *ws, size_t ws_bytes, void *stream);
 
 /* Releases a plan (host memory and HIP events only).  NULL is ignored. */
 void dpr_plan_free(dpr_plan *plan);

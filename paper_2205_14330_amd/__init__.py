@@ -8,7 +8,8 @@ marshalling, torch-allocated workspaces, the autograd form and the serving
 loop.  Importing it loads the HIP library and fails loudly if it is absent.
 """
 from ._abi import DprError, LIB_PATH, STAGES, load
-from .renderer import Plan, RenderFn, RenderParams, SceneTensors, Workspace, camera_struct, render, render_views
+from .renderer import (Plan, RenderFn, RenderParams, SceneTensors, Workspace, camera_struct, loss_l2_tv, render,
+                       render_views)
 
 __all__ = ["DprError", "LIB_PATH", "STAGES", "load", "Plan", "RenderFn", "RenderParams", "SceneTensors", "Workspace",
-           "camera_struct", "render", "render_views"]
+           "camera_struct", "loss_l2_tv", "render", "render_views"]

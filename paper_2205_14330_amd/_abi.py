@@ -15,7 +15,7 @@ c_f, c_i32, c_i64, c_p, c_sz = ctypes.c_float, ctypes.c_int32, ctypes.c_int64, c
 
 DPR_OK, DPR_ERR_INVALID_ARG, DPR_ERR_WORKSPACE, DPR_ERR_HIP, DPR_ERR_UNSUPPORTED, DPR_ERR_STATE = range(6)
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "WORKSPACE", 3: "HIP", 4: "UNSUPPORTED", 5: "STATE"}
-FLAG_TIMING, FLAG_STATS, FLAG_PERSISTENT = 1, 2, 4
+FLAG_TIMING, FLAG_STATS, FLAG_PERSISTENT, FLAG_KERNEL_NORM = 1, 2, 4, 8
 BWD_STORED, BWD_RECOMPUTE = 0, 1
 STAGES = ["upload", "project", "depth_sort", "tile_count", "tile_scan", "emit", "composite_fwd",
           "recompute", "composite_bwd", "point_bwd"]
@@ -23,7 +23,7 @@ STAGES = ["upload", "project", "depth_sort", "tile_count", "tile_scan", "emit", 
 EXPORTED = ["dpr_version", "dpr_last_error", "dpr_plan_ws_bytes", "dpr_plan_forward",
             "dpr_workspace_bytes", "dpr_render_forward", "dpr_backward_ws_bytes",
             "dpr_render_backward", "dpr_plan_free", "dpr_plan_get_info", "dpr_stage_times",
-            "dpr_render_forward_1"]
+            "dpr_render_forward_1", "dpr_loss_ws_bytes", "dpr_loss_l2_tv"]
 
 
 class Camera(ctypes.Structure):
@@ -42,7 +42,7 @@ class View(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("alpha_min", c_f), ("t_min", c_f), ("alpha_max", c_f), ("z_near", c_f),
-                ("sh_frame", c_i32), ("bwd_mode", c_i32), ("flags", c_i32), ("reserved", c_i32)]
+                ("sh_frame", c_i32), ("bwd_mode", c_i32), ("flags", c_i32), ("max_splats", c_i32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -90,6 +90,10 @@ def load(path: str = LIB_PATH):
     L.dpr_render_forward_1.argtypes = [ctypes.POINTER(Scene), ctypes.POINTER(Camera), ctypes.POINTER(Params),
                                        c_p, c_p, c_p, c_sz, ctypes.POINTER(c_sz), c_p]
     L.dpr_render_forward_1.restype = c_i32
+    I32P = ctypes.POINTER(c_i32)
+    L.dpr_loss_ws_bytes.argtypes, L.dpr_loss_ws_bytes.restype = [c_i32, I32P, I32P], c_sz
+    L.dpr_loss_l2_tv.argtypes = [c_i32, PP, PP, I32P, I32P, c_f, PP, c_p, c_p, c_sz, c_p]
+    L.dpr_loss_l2_tv.restype = c_i32
     _lib = L
     return L
 

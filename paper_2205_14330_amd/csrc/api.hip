@@ -105,9 +105,9 @@ int check_params(const dpr_params *pr) {
     if (!(pr->z_near > 0.f) || !std::isfinite(pr->z_near)) return fail(DPR_ERR_INVALID_ARG, "z_near must be > 0");
     if (pr->sh_frame != 0 && pr->sh_frame != 1) return fail(DPR_ERR_INVALID_ARG, "sh_frame must be 0 or 1");
     if (pr->bwd_mode != 0 && pr->bwd_mode != 1) return fail(DPR_ERR_INVALID_ARG, "bwd_mode must be 0 or 1");
-    if (pr->flags & ~(DPR_FLAG_TIMING | DPR_FLAG_STATS | DPR_FLAG_PERSISTENT))
+    if (pr->flags & ~(DPR_FLAG_TIMING | DPR_FLAG_STATS | DPR_FLAG_PERSISTENT | DPR_FLAG_KERNEL_NORM))
         return fail(DPR_ERR_INVALID_ARG, "unknown flags 0x%x", pr->flags);
-    if (pr->reserved != 0) return fail(DPR_ERR_INVALID_ARG, "params.reserved must be 0");
+    if (pr->max_splats < 0) return fail(DPR_ERR_INVALID_ARG, "max_splats must be >= 0");
     return DPR_OK;
 }
 
@@ -316,6 +316,33 @@ CompositeArgs composite_args(const dpr_plan *p, const void *ws) {
     return a;
 }
 
+// Workspace of dpr_loss_l2_tv: image table, block offsets, per-block sums.
+struct LossLayout {
+    Region tab, starts, partial;
+    uint32_t blocks = 0;
+    uint64_t total = 0;
+};
+
+int loss_layout(int32_t n, const int32_t *widths, const int32_t *heights, LossLayout *out) {
+    if (n < 1 || n > (1 << 20)) return fail(DPR_ERR_INVALID_ARG, "n_images must be in [1, 2^20]");
+    if (!widths || !heights) return fail(DPR_ERR_INVALID_ARG, "widths / heights is NULL");
+    uint64_t blocks = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (widths[v] < 1 || heights[v] < 1 || widths[v] > kLimitDim || heights[v] > kLimitDim)
+            return fail(DPR_ERR_INVALID_ARG, "image %d: size %dx%d outside [1, %d]", v, widths[v], heights[v],
+                        kLimitDim);
+        blocks += loss_blocks(widths[v], heights[v]);
+    }
+    if (blocks >= 0xFFFFFFFFull) return fail(DPR_ERR_UNSUPPORTED, "too many pixels");
+    Layout L;
+    out->tab = L.add(sizeof(LossImage) * (uint64_t)n);
+    out->starts = L.add(4ull * ((uint64_t)n + 1));
+    out->partial = L.add(4 * blocks);
+    out->blocks = (uint32_t)blocks;
+    out->total = L.total;
+    return DPR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -356,6 +383,8 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
     p->th.t_min = params->t_min;
     p->th.z_near = params->z_near;
     p->th.sh_frame = params->sh_frame;
+    p->th.max_splats = (uint32_t)params->max_splats;
+    p->th.kernel_norm = (params->flags & DPR_FLAG_KERNEL_NORM) ? 1 : 0;
     p->scenes.assign(scenes, scenes + n_scenes);
     p->views.assign(views, views + n_views);
     p->pws = static_cast<uint8_t *>(plan_ws);
@@ -722,6 +751,53 @@ int dpr_render_forward_1(const dpr_scene *scene, const dpr_camera *cam, const dp
     rc = dpr_render_forward(p, static_cast<uint8_t *>(ws) + pb_al, ws_bytes - pb_al, stream);
     dpr_plan_free(p);
     return rc;
+}
+
+size_t dpr_loss_ws_bytes(int32_t n_images, const int32_t *widths, const int32_t *heights) {
+    LossLayout L;
+    if (loss_layout(n_images, widths, heights, &L) != DPR_OK) return 0;
+    return (size_t)L.total;
+}
+
+int dpr_loss_l2_tv(int32_t n_images, const float *const *render, const float *const *target, const int32_t *widths,
+                   const int32_t *heights, float lambda, float *const *dL_drender, double *loss, void *ws,
+                   size_t ws_bytes, void *stream) {
+    g_err.clear();
+    LossLayout lay;
+    int rc = loss_layout(n_images, widths, heights, &lay);
+    if (rc) return rc;
+    if (!render || !target || !dL_drender || !loss)
+        return fail(DPR_ERR_INVALID_ARG, "render / target / dL_drender / loss is NULL");
+    if (!(lambda >= 0.f) || !std::isfinite(lambda)) return fail(DPR_ERR_INVALID_ARG, "lambda must be finite, >= 0");
+    if (!ws || ws_bytes < lay.total)
+        return fail(DPR_ERR_WORKSPACE, "loss workspace needs %llu bytes, got %llu", (unsigned long long)lay.total,
+                    (unsigned long long)ws_bytes);
+    std::vector<LossImage> tab((size_t)n_images);
+    std::vector<uint32_t> starts((size_t)n_images + 1);
+    uint32_t b = 0;
+    for (int32_t v = 0; v < n_images; ++v) {
+        if (!render[v] || !target[v] || !dL_drender[v])
+            return fail(DPR_ERR_INVALID_ARG, "image %d: NULL pointer", v);
+        if (dL_drender[v] == render[v] || dL_drender[v] == target[v])
+            return fail(DPR_ERR_INVALID_ARG, "image %d: dL_drender aliases an input", v);
+        tab[v].render = render[v];
+        tab[v].target = target[v];
+        tab[v].grad = dL_drender[v];
+        tab[v].width = widths[v];
+        tab[v].height = heights[v];
+        starts[v] = b;
+        b += loss_blocks(widths[v], heights[v]);
+    }
+    starts[n_images] = b;
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    HIP_TRY(upload_async(w + lay.tab.off, tab.data(), sizeof(LossImage) * tab.size(), st));
+    HIP_TRY(upload_async(w + lay.starts.off, starts.data(), 4 * starts.size(), st));
+    HIP_TRY(launch_loss(reinterpret_cast<const LossImage *>(w + lay.tab.off),
+                        reinterpret_cast<const uint32_t *>(w + lay.starts.off), n_images, lay.blocks, lambda,
+                        reinterpret_cast<float *>(w + lay.partial.off), loss, st));
+    return DPR_OK;
 }
 
 }  // extern "C"

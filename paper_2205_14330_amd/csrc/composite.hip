@@ -101,13 +101,16 @@ constexpr int kFwdChunk = 2 * kFwdThreads;
 // the tile's backward work items (tile, s) for s < ceil(max stop / kBwdSeg).
 static_assert(kBwdSeg % kFwdChunk == 0, "backward segments are whole forward chunks");
 
-template <bool PERSISTENT>
+// CAP: a pixel also stops after blending th.max_splats splats (then it is live
+// while T >= t_min and fewer than max_splats splats were blended).
+template <bool PERSISTENT, bool CAP>
 __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     constexpr int PX = kFwdPx, kThreads = kFwdThreads, kChunk = kFwdChunk;
     __shared__ float4 s_r0[kChunk], s_r1[kChunk];
     __shared__ uint32_t s_next, s_max[2], s_work;
     const float neg_lambda = -a.th.lambda;
     const float alpha_max = a.th.alpha_max, t_min = a.th.t_min;
+    const uint32_t cap = a.th.max_splats;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_remap(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
         const int v = find_segment(a.tile_start, a.n_views, tile);
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             for (int j0 = 0; j0 < cnt; j0 += 16) {
                 bool any_live = false;
 #pragma unroll
-                for (int p = 0; p < PX; ++p) any_live = any_live || T[p] >= t_min;
+                for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!CAP || nblend[p] < cap));
                 if (__ballot(any_live) == 0ull) break;
                 const int jn = min(j0 + 16, cnt);
                 for (int j = j0; j < jn; ++j) {
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                     for (int p = 0; p < PX; ++p) {
                         float dx, dy, q;
                         e[p] = splat_exponent(s, ux[p], uy[p], dx, dy, q);
-                        hit[p] = T[p] >= t_min && e[p] >= neg_lambda;
+                        hit[p] = T[p] >= t_min && (!CAP || nblend[p] < cap) && e[p] >= neg_lambda;
                         any = any || hit[p];
                     }
                     if (__ballot(any) != 0ull) {
@@ -199,14 +202,14 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                             I2[p] = fmaf(Ta, s.cb, I2[p]);
                             nblend[p] += hit[p] ? 1u : 0u;
                             T[p] = T[p] - Ta;                       // T (1 - alpha)
-                            if (hit[p] && T[p] < t_min) nlast[p] = pos1;
+                            if (hit[p] && (T[p] < t_min || (CAP && nblend[p] == cap))) nlast[p] = pos1;
                         }
                     }
                 }
             }
             bool any_live = false;
 #pragma unroll
-            for (int p = 0; p < PX; ++p) any_live = any_live || T[p] >= t_min;
+            for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!CAP || nblend[p] < cap));
             if (__syncthreads_count(any_live) == 0) break;
         }
         uint32_t mymax = 0;
@@ -463,14 +466,20 @@ static uint32_t persistent_grid(uint32_t tiles, uint32_t per_cu) {
     return tiles < g ? tiles : g;
 }
 
+template <bool CAP>
+static void launch_fwd(const CompositeArgs &a, bool persistent, hipStream_t st) {
+    if (persistent) {
+        hipLaunchKernelGGL((k_composite<true, CAP>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0,
+                           st, a);
+    } else {
+        hipLaunchKernelGGL((k_composite<false, CAP>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
+    }
+}
+
 hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (a.total_tiles == 0) return hipSuccess;
-    if (persistent) {
-        hipLaunchKernelGGL((k_composite<true>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0, st,
-                           a);
-    } else {
-        hipLaunchKernelGGL((k_composite<false>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
-    }
+    if (a.th.max_splats > 0) launch_fwd<true>(a, persistent, st);
+    else launch_fwd<false>(a, persistent, st);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ constexpr int kScanTile = kScanThreads * kScanItemsPerThread;   // 2048 elements
 constexpr uint32_t kDroppedKey = 0xFFFFFFFFu;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
+constexpr float kTwoPi = 6.283185307179586f;
 
 // Per-view descriptor in device memory.
 struct ViewDesc {
@@ -76,6 +77,8 @@ struct Thresholds {
     float t_min;
     float z_near;
     int32_t sh_frame;
+    uint32_t max_splats;   // 0: no per-pixel cap
+    int32_t kernel_norm;   // 1: w carries log2 (2 pi sx sy)^-1/2
 };
 
 // Splat record of one (view, point) item: 32 bytes.
@@ -233,6 +236,16 @@ hipError_t launch_point_bwd(const Tables &tb, const Thresholds &th, int sh_degre
                             const float *grad, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st);
+
+// Eq. (8) loss over a batch of images (loss.hip).
+struct LossImage {
+    const float *render, *target;
+    float *grad;
+    int32_t width, height;
+};
+uint32_t loss_blocks(int32_t width, int32_t height);
+hipError_t launch_loss(const LossImage *img, const uint32_t *block_start, int n, uint32_t total_blocks, float lambda,
+                       float *partial, double *loss, hipStream_t st);
 // Stream-ordered copy of a small host table (bytes % 4 == 0) through kernel arguments.
 hipError_t upload_async(void *dst, const void *src, size_t bytes, hipStream_t st);
 

@@ -1,7 +1,8 @@
 // Per-point chain rule from the per-(view, point) splat gradients to the
 // scene parameters: positions through Eq. (1) and the perspective-scaled
 // radius, SH coefficients through Eq. (4), the view direction through Eq. (3),
-// and the opacity through w = log2(o).
+// and the opacity through w = log2(o) (plus log2 (2 pi sx sy)^-1/2 with Eq. (5)'s
+// normalisation, which adds dL/dZ = A4 / Z).
 //
 // One thread per scene point loops over the scene's views in a fixed order,
 // so the sum over views is deterministic and each output is written once.
@@ -65,6 +66,8 @@ __global__ __launch_bounds__(kPointThreads) void k_point_bwd(Tables tb, Threshol
         float dX = g_px * vd.fx * iz;
         float dY = g_py * vd.fy * iz;
         float dZ = -(g_px * vd.fx * X + g_py * vd.fy * Yc) * iz * iz - 2.f * kLn2 * ga.z * iz;
+        // with Eq. (5)'s normalisation w = log2 o - log2 sqrt(2 pi sx sy) grows as log2 Z
+        if (th.kernel_norm) dZ += gb.x * iz;
         // opacity: w = log2(o)
         gO += g_w / (o * kLn2);
 

@@ -57,8 +57,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(Tables tb, Thresholds 
     const float z = sc.xyz[3 * (size_t)i + 2];
     const float o = sc.opacity[i];
     const float r = sc.radius[i];
-    const float w = __log2f(o);
-    const float thr = w + th.lambda;       // candidate iff a dx^2 + b dy^2 <= thr
+    const float log2o = __log2f(o);
     const float *h = s_sh + threadIdx.x * stride;
 
     for (uint32_t vv = 0; vv < sc.view_count; ++vv) {
@@ -82,7 +81,8 @@ __global__ __launch_bounds__(kProjThreads) void k_project(Tables tb, Thresholds 
             const float sy = vd.fy * r * iz;
             out.a = (0.5f * kLog2e) / (sx * sx);
             out.b = (0.5f * kLog2e) / (sy * sy);
-            out.w = w;
+            // log2 of the amplitude: o, or o (2 pi sx sy)^-1/2 with Eq. (5)'s normalisation
+            out.w = th.kernel_norm ? log2o - 0.5f * __log2f(kTwoPi * sx * sy) : log2o;
 
             // SH colour at the view direction (camera frame, or world frame)
             const float inrm = rsqrtf(X * X + Yc * Yc + Z * Z);
@@ -105,6 +105,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(Tables tb, Thresholds 
             out.cr = c0; out.cg = c1; out.cb = c2;
 
             // conservative tile rectangle of the ellipse a dx^2 + b dy^2 <= thr
+            const float thr = out.w + th.lambda;   // candidate iff a dx^2 + b dy^2 <= thr
             if (thr >= 0.f && isfinite(out.px) && isfinite(out.py)) {
                 const float slack = 1.0f + 1.0f / 1024.0f;
                 const float hx = sqrtf(thr / out.a) * slack + (1.0f / 64.0f);

@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import BWD_RECOMPUTE, BWD_STORED, FLAG_PERSISTENT, FLAG_STATS, FLAG_TIMING, check, load
+from ._abi import (BWD_RECOMPUTE, BWD_STORED, FLAG_KERNEL_NORM, FLAG_PERSISTENT, FLAG_STATS, FLAG_TIMING, check,
+                   load)
 
 
 @dataclasses.dataclass
@@ -30,12 +31,20 @@ class RenderParams:
     timing: bool = False
     stats: bool = False
     persistent: bool = False
+    max_splats: int = 0            # > 0: a pixel blends at most this many splats (the paper's n = 15)
+    kernel_norm: bool = False      # keep Eq. (5)'s normalisation prefactor
+
+    @staticmethod
+    def paper(**kw) -> "RenderParams":
+        """The paper's literal renderer: n = 15 splats per pixel, Eq. (5) normalised."""
+        return RenderParams(max_splats=15, kernel_norm=True, **kw)
 
     def to_c(self) -> _abi.Params:
         flags = (FLAG_TIMING if self.timing else 0) | (FLAG_STATS if self.stats else 0) | \
-                (FLAG_PERSISTENT if self.persistent else 0)
+                (FLAG_PERSISTENT if self.persistent else 0) | (FLAG_KERNEL_NORM if self.kernel_norm else 0)
         mode = {"stored": BWD_STORED, "recompute": BWD_RECOMPUTE}[self.bwd_mode]
-        return _abi.Params(self.alpha_min, self.t_min, self.alpha_max, self.z_near, self.sh_frame, mode, flags, 0)
+        return _abi.Params(self.alpha_min, self.t_min, self.alpha_max, self.z_near, self.sh_frame, mode, flags,
+                           int(self.max_splats))
 
 
 @dataclasses.dataclass
@@ -304,3 +313,34 @@ def render_views(scenes: Sequence[SceneTensors], views: Sequence[Tuple[int, obje
     p = Plan(scenes, views, params, stream=stream)
     p.forward()
     return p
+
+
+def loss_l2_tv(renders: Sequence[torch.Tensor], targets: Sequence[torch.Tensor], lam: float = 0.01,
+               grads: Optional[Sequence[torch.Tensor]] = None, stream: Optional[torch.cuda.Stream] = None,
+               workspace: Optional[Workspace] = None):
+    """Eq. (8) per image: squared L2 + lam * anisotropic TV, and its gradient,
+    in one pass (libdpr).  renders/targets: contiguous float32 [H, W, 3] device
+    tensors.  Returns (loss float64 tensor [n] on the device, list of dL/drender)."""
+    lib = load()
+    n = len(renders)
+    if n == 0 or len(targets) != n:
+        raise ValueError("need the same non-zero number of renders and targets")
+    for r, t in zip(renders, targets):
+        if (r.dtype != torch.float32 or t.dtype != torch.float32 or not r.is_contiguous() or not t.is_contiguous()
+                or r.dim() != 3 or r.shape[2] != 3 or tuple(r.shape) != tuple(t.shape) or not r.is_cuda):
+            raise ValueError("renders and targets must be matching contiguous float32 [H, W, 3] device tensors")
+    dev = renders[0].device
+    if grads is None:
+        grads = [torch.empty_like(r) for r in renders]
+    W = (ctypes.c_int32 * n)(*[int(r.shape[1]) for r in renders])
+    H = (ctypes.c_int32 * n)(*[int(r.shape[0]) for r in renders])
+    nb = int(lib.dpr_loss_ws_bytes(n, W, H))
+    if nb == 0:
+        check(_abi.DPR_ERR_INVALID_ARG)
+    ws = workspace.get("loss", nb) if workspace is not None else torch.empty(nb, dtype=torch.uint8, device=dev)
+    loss = torch.empty(n, dtype=torch.float64, device=dev)
+    P = _abi.ptr_array
+    check(lib.dpr_loss_l2_tv(n, P([r.data_ptr() for r in renders]), P([t.data_ptr() for t in targets]), W, H,
+                             float(lam), P([g.data_ptr() for g in grads]), loss.data_ptr(), ws.data_ptr(),
+                             int(ws.numel()), _stream_handle(stream)))
+    return loss, grads

@@ -22,7 +22,8 @@ def scene_tensors(scene):
 
 
 def oparams(p) -> oracle.Params:
-    return oracle.Params(p.alpha_min, p.t_min, p.alpha_max, p.z_near, p.sh_frame)
+    return oracle.Params(p.alpha_min, p.t_min, p.alpha_max, p.z_near, p.sh_frame, int(p.max_splats),
+                         int(p.kernel_norm))
 
 
 def gpu_plan(scenes, views, params, run_forward=True):

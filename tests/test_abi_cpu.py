@@ -114,7 +114,7 @@ def _plan(abi, scenes, views, params, ws=FAKE, ws_bytes=1 << 40):
 
 @pytest.mark.parametrize("case,expect", [
     ("alpha_min", 1), ("t_min", 1), ("alpha_max", 1), ("z_near", 1), ("sh_frame", 1), ("bwd_mode", 1),
-    ("flags", 1), ("reserved", 1), ("scene_index", 1), ("width", 1), ("height", 1), ("fx", 1),
+    ("flags", 1), ("max_splats", 1), ("scene_index", 1), ("width", 1), ("height", 1), ("fx", 1),
     ("null_image", 1), ("sh_degree", 1), ("neg_n", 1), ("null_xyz", 1), ("mixed_degree", 4),
     ("no_views", 1), ("workspace", 2), ("null_ws", 2),
 ])
@@ -139,8 +139,8 @@ def test_invalid_arguments_rejected(abi, case, expect):
         params.bwd_mode = 7
     elif case == "flags":
         params.flags = 64
-    elif case == "reserved":
-        params.reserved = 1
+    elif case == "max_splats":
+        params.max_splats = -1
     elif case == "scene_index":
         views = [_view(abi, scene=1)]
     elif case == "width":
@@ -231,3 +231,43 @@ def test_oracle_shares_no_code_with_hip_path():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "oracle.c" not in text, f
+
+
+def test_loss_workspace_sizes(abi):
+    lib = abi.load()
+    I = ctypes.c_int32
+    W, H = (I * 2)(800, 17), (I * 2)(600, 1)
+    n = lib.dpr_loss_ws_bytes(2, W, H)
+    assert n >= 32 * 2 + 4 * 3 + 4 * ((800 * 600 + 1023) // 1024 + 1)
+    assert lib.dpr_loss_ws_bytes(0, W, H) == 0
+    assert lib.dpr_loss_ws_bytes(1, (I * 1)(0), (I * 1)(5)) == 0
+    assert lib.dpr_loss_ws_bytes(1, (I * 1)(20000), (I * 1)(5)) == 0
+
+
+@pytest.mark.parametrize("case,expect", [("null_render", 1), ("alias", 1), ("lambda", 1), ("nan_lambda", 1),
+                                         ("workspace", 2), ("null_loss", 1), ("size", 1)])
+def test_loss_invalid_arguments_rejected(abi, case, expect):
+    """Every check runs on the host before anything is launched."""
+    lib = abi.load()
+    I = ctypes.c_int32
+    W, H = (I * 1)(8), (I * 1)(4)
+    r, t, g = FAKE, FAKE + 4096, FAKE + 8192
+    lam, loss, ws, nb = 0.01, FAKE + 12288, FAKE + 16384, 1 << 20
+    if case == "null_render":
+        r = None
+    elif case == "alias":
+        g = r
+    elif case == "lambda":
+        lam = -1.0
+    elif case == "nan_lambda":
+        lam = float("nan")
+    elif case == "workspace":
+        nb = 8
+    elif case == "null_loss":
+        loss = None
+    elif case == "size":
+        W = (I * 1)(0)
+    P = abi.ptr_array
+    rc = lib.dpr_loss_l2_tv(1, P([r or 0]), P([t]), W, H, lam, P([g]), loss, ws, nb, None)
+    assert rc == expect, lib.dpr_last_error().decode()
+    assert lib.dpr_last_error().decode()
