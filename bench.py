@@ -54,17 +54,17 @@ def load_traffic(kernel: str, workload: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, cams, targets_fn):
-    """FP64 oracle on one full step (all views, forward + backward)."""
+def cpu_baseline(scene, cams, targets_fn, max_splats=0, kernel_norm=0, lam=0.0):
+    """FP64 oracle on one full step (all views, forward, Eq. 8 loss, backward)."""
     import oracle
     cores = len(os.sched_getaffinity(0))
+    op = oracle.Params(max_splats=max_splats, kernel_norm=kernel_norm)
     t0 = time.perf_counter()
-    grads = None
     pix = 0
     for v, cam in enumerate(cams):
-        r = oracle.render(scene, cam, threads=cores)
-        gI = 2.0 * (r.image - targets_fn(v))
-        oracle.backward(scene, [cam], [gI], None, threads=cores)
+        r = oracle.render(scene, cam, op, threads=cores)
+        _, gI = oracle.loss_l2_tv(r.image, targets_fn(v), lam)
+        oracle.backward(scene, [cam], [gI], None, params=op, threads=cores)
         pix += cam.pixels
     dt = time.perf_counter() - t0
     return {"value": pix / dt / 1e6, "unit": "Mpix/s", "cores": min(cores, oracle.max_threads()), "kind": "oracle",
@@ -86,7 +86,9 @@ def main():
                     help="time only the forward + backward metric (skip the forward-only and recompute legs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (reference for HBM counters)")
-    ap.add_argument("--workload", choices=["train", "dynamic", "serve"], default="train")
+    ap.add_argument("--workload", choices=["train", "paper", "dynamic", "serve"], default="train",
+                    help="train: the default step; paper: the same step with the paper-literal renderer "
+                         "(n = 15 splats per pixel, normalised Eq. 5) and the L2 + 0.01 TV loss")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the serving trace (train: short leg in the same JSON line; 0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -133,14 +135,21 @@ def main():
     # two live plans at a time (one being inspected while the next runs), so two
     # workspaces, each reused every other step
     wss = [dpr.Workspace(dev), dpr.Workspace(dev)]
+    paper = args.workload == "paper"
+    lam = 0.01 if paper else 0.0
+    variant = dict(max_splats=15, kernel_norm=True) if paper else {}
+    # the loss gradient of a step is consumed by that step's backward on the same
+    # stream before the next step's loss kernel overwrites it
+    grads = [torch.empty((S, S, 3), dtype=torch.float32, device=dev) for _ in range(V)]
+    loss_ws = dpr.Workspace(dev)
 
     def step(k, params, backward=True):
         plan = dpr.Plan([scene], [(0, c) for c in step_views[k]], params, workspace=wss[k % 2])
         plan.forward()
         if backward:
             tgt = targets[k % len(targets)]
-            g = [(2.0 * (plan.images[v] - tgt[v])).contiguous() for v in range(V)]
-            plan.backward(g, None)
+            dpr.loss_l2_tv(plan.images, [tgt[v] for v in range(V)], lam, grads=grads, workspace=loss_ws)
+            plan.backward(grads, None)
         return plan
 
     def timed(params, backward, steps, warmup, collect=None, reset=None):
@@ -188,7 +197,7 @@ def main():
         return dt
 
     pix_step = V * S * S
-    base = dict(persistent=args.persistent)
+    base = dict(persistent=args.persistent, **variant)
     # main metric: forward + backward (stored T), with stage timing and blend counts
     stage_ms = {s: 0.0 for s in dpr.STAGES}
     blend_acc = torch.zeros((), dtype=torch.int64, device=dev)
@@ -240,6 +249,29 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                 "frac": None, "traffic": load_traffic(dom, "surface300k_4x800")}
 
+    # the loss kernel alone (Eq. 8, one launch for the step's views): HBM-bound,
+    # 36 algorithmic bytes per pixel (render and target read, gradient written)
+    tgt = targets[0]
+    imgs = [torch.rand((S, S, 3), device=dev) for _ in range(V)]
+    tl = [tgt[v] for v in range(V)]
+    for _ in range(3):
+        dpr.loss_l2_tv(imgs, tl, lam, grads=grads, workspace=loss_ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    nl = 50
+    for _ in range(nl):
+        dpr.loss_l2_tv(imgs, tl, lam, grads=grads, workspace=loss_ws)
+    e1.record()
+    torch.cuda.synchronize()
+    t_loss = e0.elapsed_time(e1) / nl / 1e3
+    loss_gbs = 36.0 * pix_step / t_loss / 1e9
+    loss_kernel = {"bound": "hbm", "achieved": round(loss_gbs, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                   "frac": round(loss_gbs * 1e9 / PEAK_HBM, 4), "launch_ms": round(t_loss * 1e3, 4),
+                   "per_unit": "36 B per pixel (render and target read, gradient written)",
+                   "units_per_launch": pix_step, "lambda": lam}
+    log(f"loss kernel: {t_loss * 1e3:.4f} ms for {V} x {S}x{S}, {loss_gbs:.0f} GB/s")
+    del imgs
+
     if args.copy_calibration_mib > 0:
         src = torch.empty(args.copy_calibration_mib * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -252,7 +284,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         t_np = targets[0].cpu().numpy().astype(np.float64)
-        cpu = cpu_baseline(scene_np, step_views[0], lambda v: t_np[v])
+        cpu = cpu_baseline(scene_np, step_views[0], lambda v: t_np[v], 15 if paper else 0, int(paper), lam)
         log(f"cpu baseline: {cpu}")
 
     serving = None
@@ -262,18 +294,22 @@ def main():
         serving = bench_serving(args.serve_seconds, args.serve_rate)
 
     out = {
-        "metric": METRIC, "value": round(mpix_fb, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": K,
+        "metric": METRIC if not paper else "Mpix/s fwd+bwd, paper-literal renderer (n = 15, normalised Eq. 5), "
+                                           "L2 + 0.01 TV loss",
+        "value": round(mpix_fb, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(t_fb / K * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "300k points (30% on a 20-bump surface), SH degree 2, 4 views x 800x800 "
-                               "per step, forward + backward (stored T), L2 loss",
+                               "per step, forward + backward (stored T), " +
+                               ("n = 15 splats per pixel, normalised Eq. 5, L2 + 0.01 TV loss" if paper
+                                else "L2 loss"),
                    "points": args.points, "views_per_step": V, "width": S, "height": S,
                    "persistent": bool(args.persistent)},
         "fwd_mpix_s": mpix_f, "fwd_bwd_mpix_s": round(mpix_fb, 2),
         "fwd_bwd_recompute_mpix_s": mpix_r,
         "stage_ms_per_step": {s: round(v / K, 4) for s, v in stage_ms.items()},
         "pairs_per_step": pairs / K, "blended_per_step": blends / K,
-        "roofline": roof, "cpu_baseline": cpu, "serving": serving,
+        "roofline": roof, "loss_kernel": loss_kernel, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

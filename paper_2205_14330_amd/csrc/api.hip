@@ -316,29 +316,27 @@ CompositeArgs composite_args(const dpr_plan *p, const void *ws) {
     return a;
 }
 
-// Workspace of dpr_loss_l2_tv: image table, block offsets, per-block sums.
+// Workspace of dpr_loss_l2_tv: per-block sums of the largest batch of images.
 struct LossLayout {
-    Region tab, starts, partial;
-    uint32_t blocks = 0;
+    Region partial;
     uint64_t total = 0;
 };
 
 int loss_layout(int32_t n, const int32_t *widths, const int32_t *heights, LossLayout *out) {
     if (n < 1 || n > (1 << 20)) return fail(DPR_ERR_INVALID_ARG, "n_images must be in [1, 2^20]");
     if (!widths || !heights) return fail(DPR_ERR_INVALID_ARG, "widths / heights is NULL");
-    uint64_t blocks = 0;
+    uint64_t most = 0, batch = 0;
     for (int32_t v = 0; v < n; ++v) {
         if (widths[v] < 1 || heights[v] < 1 || widths[v] > kLimitDim || heights[v] > kLimitDim)
             return fail(DPR_ERR_INVALID_ARG, "image %d: size %dx%d outside [1, %d]", v, widths[v], heights[v],
                         kLimitDim);
-        blocks += loss_blocks(widths[v], heights[v]);
+        if (v % kLossBatch == 0) batch = 0;
+        batch += loss_blocks(widths[v], heights[v]);
+        most = std::max(most, batch);
     }
-    if (blocks >= 0xFFFFFFFFull) return fail(DPR_ERR_UNSUPPORTED, "too many pixels");
+    if (most >= 0xFFFFFFFFull) return fail(DPR_ERR_UNSUPPORTED, "too many pixels in one batch");
     Layout L;
-    out->tab = L.add(sizeof(LossImage) * (uint64_t)n);
-    out->starts = L.add(4ull * ((uint64_t)n + 1));
-    out->partial = L.add(4 * blocks);
-    out->blocks = (uint32_t)blocks;
+    out->partial = L.add(4 * most);
     out->total = L.total;
     return DPR_OK;
 }
@@ -773,8 +771,6 @@ int dpr_loss_l2_tv(int32_t n_images, const float *const *render, const float *co
         return fail(DPR_ERR_WORKSPACE, "loss workspace needs %llu bytes, got %llu", (unsigned long long)lay.total,
                     (unsigned long long)ws_bytes);
     std::vector<LossImage> tab((size_t)n_images);
-    std::vector<uint32_t> starts((size_t)n_images + 1);
-    uint32_t b = 0;
     for (int32_t v = 0; v < n_images; ++v) {
         if (!render[v] || !target[v] || !dL_drender[v])
             return fail(DPR_ERR_INVALID_ARG, "image %d: NULL pointer", v);
@@ -785,18 +781,11 @@ int dpr_loss_l2_tv(int32_t n_images, const float *const *render, const float *co
         tab[v].grad = dL_drender[v];
         tab[v].width = widths[v];
         tab[v].height = heights[v];
-        starts[v] = b;
-        b += loss_blocks(widths[v], heights[v]);
     }
-    starts[n_images] = b;
     if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t *w = static_cast<uint8_t *>(ws);
-    HIP_TRY(upload_async(w + lay.tab.off, tab.data(), sizeof(LossImage) * tab.size(), st));
-    HIP_TRY(upload_async(w + lay.starts.off, starts.data(), 4 * starts.size(), st));
-    HIP_TRY(launch_loss(reinterpret_cast<const LossImage *>(w + lay.tab.off),
-                        reinterpret_cast<const uint32_t *>(w + lay.starts.off), n_images, lay.blocks, lambda,
-                        reinterpret_cast<float *>(w + lay.partial.off), loss, st));
+    HIP_TRY(launch_loss(tab.data(), n_images, lambda, reinterpret_cast<float *>(w + lay.partial.off), loss, st));
     return DPR_OK;
 }
 

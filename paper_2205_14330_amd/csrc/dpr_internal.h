@@ -243,9 +243,10 @@ struct LossImage {
     float *grad;
     int32_t width, height;
 };
+constexpr int kLossBatch = 16;     // images per launch (passed in the kernel arguments)
 uint32_t loss_blocks(int32_t width, int32_t height);
-hipError_t launch_loss(const LossImage *img, const uint32_t *block_start, int n, uint32_t total_blocks, float lambda,
-                       float *partial, double *loss, hipStream_t st);
+// partial: per-block sums, as many as the largest batch of kLossBatch images needs
+hipError_t launch_loss(const LossImage *img, int n, float lambda, float *partial, double *loss, hipStream_t st);
 // Stream-ordered copy of a small host table (bytes % 4 == 0) through kernel arguments.
 hipError_t upload_async(void *dst, const void *src, size_t bytes, hipStream_t st);
 
