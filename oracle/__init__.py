@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "hybrid.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -53,11 +54,12 @@ class Params:
 
 def build(force: bool = True) -> str:
     """Compile oracle.c with gcc (plain C99, OpenMP, no FP contraction)."""
-    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+    if not force and os.path.exists(_LIB_PATH) and \
+            os.path.getmtime(_LIB_PATH) >= max(os.path.getmtime(f) for f in _SRCS):
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+           "-fPIC", "-shared", "-o", tmp] + _SRCS + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -66,7 +68,7 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(f) for f in _SRCS):
             build()
         L = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
@@ -79,6 +81,14 @@ def lib():
         L.oracle_backward.argtypes = [i64, P, P, i32, P, P, P, i32, i32, P, i32, i32, i64, P,
                                       P, P, P, P, P, i32]
         L.oracle_max_threads.argtypes = []
+        L.hybrid_voxel_keys.argtypes = [i64, P, i32, P]
+        L.hybrid_voxel_keys.restype = ctypes.c_int
+        L.hybrid_voxel_reduce.argtypes = [i64, i32, P, P, P, P, i32, P, P, P, P]
+        L.hybrid_voxel_reduce.restype = i64
+        L.hybrid_knn.argtypes = [i64, P, i32, P, P]
+        L.hybrid_knn.restype = ctypes.c_int
+        L.hybrid_filter_generate.argtypes = [i64, i32, P, P, P, P, i32, ctypes.c_float, P, P, P, P, P]
+        L.hybrid_filter_generate.restype = i64
         for f in (L.oracle_sh_basis, L.oracle_project, L.oracle_depth_order, L.oracle_render,
                   L.oracle_backward, L.oracle_max_threads):
             f.restype = ctypes.c_int
@@ -282,3 +292,84 @@ def loss_l2_tv(render, target, lam: float):
     grad[1:, :, :] += lam * sy
     grad[:-1, :, :] -= lam * sy
     return loss, grad
+
+
+# ---------------------------------------------------------------------------
+# Hybrid coarse-to-fine update (Sec. 3.3, Alg. 1); readings in hybrid.c
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Cloud:
+    """Point cloud with every per-point parameter: xyz [m,3], sh [m,K,3],
+    opacity [m], radius [m]."""
+    xyz: np.ndarray
+    sh: np.ndarray
+    opacity: np.ndarray
+    radius: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.xyz.shape[0])
+
+    def astype(self, dt) -> "Cloud":
+        return Cloud(*(np.ascontiguousarray(a, dtype=dt) for a in (self.xyz, self.sh, self.opacity, self.radius)))
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def voxel_keys(xyz, N: int) -> np.ndarray:
+    x = _f32(xyz)
+    keys = np.zeros(x.shape[0], np.uint64)
+    if lib().hybrid_voxel_keys(x.shape[0], _p(x), N, _p(keys)) != 0:
+        raise ValueError("bad input")
+    return keys
+
+
+def voxel_reduce(cloud, N: int) -> Cloud:
+    """Step 1 of Alg. 1: one point per non-empty voxel of an N^3 grid over the
+    bounding box, the FP64 average of every parameter, in ascending voxel order."""
+    c = cloud.astype(np.float32) if not isinstance(cloud, Cloud) else cloud.astype(np.float32)
+    n, K = c.n, c.sh.shape[1]
+    ox, os_, oo, orad = np.zeros((n, 3)), np.zeros((n, K, 3)), np.zeros(n), np.zeros(n)
+    m = lib().hybrid_voxel_reduce(n, 3 * K, _p(c.xyz), _p(c.sh), _p(c.opacity), _p(c.radius), N, _p(ox), _p(os_),
+                                  _p(oo), _p(orad))
+    if m < 0:
+        raise ValueError("bad input")
+    return Cloud(ox[:m], os_[:m], oo[:m], orad[:m])
+
+
+def knn(xyz, K: int):
+    """Brute-force K nearest neighbours among the other points: (idx [m,K]
+    with -1 past min(K, m - 1), float32 squared distances [m,K])."""
+    x = _f32(xyz)
+    m = x.shape[0]
+    idx = np.zeros((m, K), np.int64)
+    d2 = np.zeros((m, K), np.float32)
+    if lib().hybrid_knn(m, _p(x), K, _p(idx), _p(d2)) != 0:
+        raise ValueError("bad input")
+    return idx, d2
+
+
+def filter_generate(cloud, K: int, eps: float):
+    """Steps 2-3 of Alg. 1 on float32 points: (keep mask, output cloud = kept
+    points then one generated point per kept point)."""
+    c = cloud.astype(np.float32)
+    m, Kc = c.n, c.sh.shape[1]
+    keep = np.zeros(m, np.int32)
+    ox, os_, oo, orad = np.zeros((2 * m, 3)), np.zeros((2 * m, Kc, 3)), np.zeros(2 * m), np.zeros(2 * m)
+    cnt = lib().hybrid_filter_generate(m, 3 * Kc, _p(c.xyz), _p(c.sh), _p(c.opacity), _p(c.radius), K, float(eps),
+                                       _p(keep), _p(ox), _p(os_), _p(oo), _p(orad))
+    if cnt < 0:
+        raise ValueError("bad input")
+    return keep.astype(bool), Cloud(ox[:cnt], os_[:cnt], oo[:cnt], orad[:cnt])
+
+
+def hybrid_update(cloud, N: int, K: int, eps: float):
+    """Alg. 1: voxel reduction, then outlier removal and point generation on the
+    reduced cloud (rounded to float32, as the points are stored).  Returns
+    (reduced cloud, keep mask over it, output cloud)."""
+    red = voxel_reduce(cloud, N)
+    keep, out = filter_generate(red.astype(np.float32), K, eps)
+    return red, keep, out
