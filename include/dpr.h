@@ -239,6 +239,61 @@ int dpr_loss_l2_tv(int32_t n_images, const float *const *render, const float *co
                    const int32_t *widths, const int32_t *heights, float lambda, float *const *dL_drender,
                    double *loss, void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Hybrid coarse-to-fine update of the point cloud (Sec. 3.3, Alg. 1).
+ * A point's parameters are its position, its SH coefficients [K][3]
+ * (K = (sh_degree + 1)^2), its opacity and its radius; "average" means the
+ * average of all of them.  All arrays are device float32, row-major.
+ * Decisions read from float comparisons are taken in float32 with every
+ * operation rounded on its own, so they are reproducible bit for bit:
+ *   voxel/grid cell per axis: s = M / (hi - lo) over the points' bounding box
+ *     (0 if hi == lo), cell = clamp(floor((p - lo) * s), 0, M - 1);
+ *     key (iz M + iy) M + ix;
+ *   neighbour order: the other points by d2 = (dx dx + dy dy) + dz dz with
+ *     dx = x_j - x_i, ties by index;
+ *   spread of a point's k = min(K, m - 1) neighbour distances d_q = sqrt(d2_q):
+ *     mean = (sum d_q) / k, delta = sqrt(sum (d_q - mean)^2 / k) (sums in
+ *     neighbour order); the point is removed if delta > eps (kept if k = 0).
+ * Averages are accumulated in FP64 in a fixed order (ascending point index
+ * within a voxel; neighbour order for a generated point).
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of the device workspace of dpr_knn for m points (0 on bad sizes). */
+size_t dpr_knn_ws_bytes(int64_t m, int32_t K);
+
+/* The K nearest other points of every point (exact, K <= 32), by a uniform
+ * grid search.  idx[m][K]: neighbour indices in neighbour order, -1 past
+ * min(K, m - 1); d2[m][K]: their float32 squared distances (0 past the end).
+ * Asynchronous on `stream`. */
+int dpr_knn(int64_t m, const float *xyz, int32_t K, int32_t *idx, float *d2, void *ws, size_t ws_bytes,
+            void *stream);
+
+/* Bytes of the device workspace of dpr_hybrid_update (and, with K = 1, of
+ * dpr_voxel_reduce) for n input points (0 on bad sizes). */
+size_t dpr_hybrid_ws_bytes(int64_t n, int32_t sh_degree, int32_t K);
+
+/* Step 1 of Alg. 1: the bounding box of the n points split into N^3 voxels
+ * (1 <= N <= 1024), every non-empty voxel replaced by the average of its
+ * points, written in ascending voxel key order to out_* (capacity n points);
+ * *out_count (host) = number of voxels.  Synchronizes `stream` once (to learn
+ * the count). */
+int dpr_voxel_reduce(int64_t n, int32_t sh_degree, const float *xyz, const float *sh, const float *opacity,
+                     const float *radius, int32_t N, float *out_xyz, float *out_sh, float *out_opacity,
+                     float *out_radius, int64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+
+/* Alg. 1: voxel reduction (N), then on the reduced points outlier removal
+ * (K nearest neighbours, threshold eps >= 0) and point generation (one new
+ * point per kept point, the average of its K nearest kept neighbours, if it
+ * has any).  Removal and generation are each decided against the set before
+ * that step.  out_* (capacity 2 n points) receive the kept points, in voxel
+ * order, followed by the generated ones in the same order.  out_counts (host
+ * int64[3]) = {voxels, kept, output points}.  Synchronizes `stream` twice.
+ * Inputs and outputs must not overlap. */
+int dpr_hybrid_update(int64_t n, int32_t sh_degree, const float *xyz, const float *sh, const float *opacity,
+                      const float *radius, int32_t N, int32_t K, float eps, float *out_xyz, float *out_sh,
+                      float *out_opacity, float *out_radius, int64_t *out_counts, void *ws, size_t ws_bytes,
+                      void *stream);
+
 /* Releases a plan (host memory and HIP events only).  NULL is ignored. */
 void dpr_plan_free(dpr_plan *plan);
 

@@ -23,7 +23,8 @@ STAGES = ["upload", "project", "depth_sort", "tile_count", "tile_scan", "emit", 
 EXPORTED = ["dpr_version", "dpr_last_error", "dpr_plan_ws_bytes", "dpr_plan_forward",
             "dpr_workspace_bytes", "dpr_render_forward", "dpr_backward_ws_bytes",
             "dpr_render_backward", "dpr_plan_free", "dpr_plan_get_info", "dpr_stage_times",
-            "dpr_render_forward_1", "dpr_loss_ws_bytes", "dpr_loss_l2_tv"]
+            "dpr_render_forward_1", "dpr_loss_ws_bytes", "dpr_loss_l2_tv", "dpr_knn_ws_bytes", "dpr_knn",
+            "dpr_hybrid_ws_bytes", "dpr_voxel_reduce", "dpr_hybrid_update"]
 
 
 class Camera(ctypes.Structure):
@@ -94,6 +95,15 @@ def load(path: str = LIB_PATH):
     L.dpr_loss_ws_bytes.argtypes, L.dpr_loss_ws_bytes.restype = [c_i32, I32P, I32P], c_sz
     L.dpr_loss_l2_tv.argtypes = [c_i32, PP, PP, I32P, I32P, c_f, PP, c_p, c_p, c_sz, c_p]
     L.dpr_loss_l2_tv.restype = c_i32
+    I64P = ctypes.POINTER(c_i64)
+    L.dpr_knn_ws_bytes.argtypes, L.dpr_knn_ws_bytes.restype = [c_i64, c_i32], c_sz
+    L.dpr_knn.argtypes, L.dpr_knn.restype = [c_i64, c_p, c_i32, c_p, c_p, c_p, c_sz, c_p], c_i32
+    L.dpr_hybrid_ws_bytes.argtypes, L.dpr_hybrid_ws_bytes.restype = [c_i64, c_i32, c_i32], c_sz
+    L.dpr_voxel_reduce.argtypes = [c_i64, c_i32, c_p, c_p, c_p, c_p, c_i32, c_p, c_p, c_p, c_p, I64P, c_p, c_sz, c_p]
+    L.dpr_voxel_reduce.restype = c_i32
+    L.dpr_hybrid_update.argtypes = [c_i64, c_i32, c_p, c_p, c_p, c_p, c_i32, c_i32, c_f, c_p, c_p, c_p, c_p, I64P,
+                                    c_p, c_sz, c_p]
+    L.dpr_hybrid_update.restype = c_i32
     _lib = L
     return L
 

@@ -341,6 +341,64 @@ int loss_layout(int32_t n, const int32_t *widths, const int32_t *heights, LossLa
     return DPR_OK;
 }
 
+// Scratch of the hybrid update / neighbour search for up to n points.
+struct HyLayout {
+    Region keys, vals, keys_alt, vals_alt, hist, part, total, flags, seg, starts, cell_start, box_part, box, idx, d2,
+        red;
+    uint64_t total_bytes = 0;
+};
+
+HyLayout hy_layout(uint64_t n, int K, int k3, bool reduced_cloud) {
+    Layout L;
+    HyLayout h;
+    const HyScratchBytes b = hy_scratch_bytes(n, K);
+    h.keys = L.add(b.keys);
+    h.vals = L.add(b.vals);
+    h.keys_alt = L.add(b.keys_alt);
+    h.vals_alt = L.add(b.vals_alt);
+    h.hist = L.add(b.hist);
+    h.part = L.add(b.part);
+    h.total = L.add(b.total64);
+    h.flags = L.add(b.flags);
+    h.seg = L.add(b.seg);
+    h.starts = L.add(b.starts);
+    h.cell_start = L.add(b.cell_start);
+    h.box_part = L.add(b.box_part);
+    h.box = L.add(b.box);
+    h.idx = L.add(b.idx);
+    h.d2 = L.add(b.d2);
+    h.red = L.add(reduced_cloud ? 4 * n * (uint64_t)(5 + k3) : 0);
+    h.total_bytes = L.total;
+    return h;
+}
+
+HyScratch hy_scratch(uint8_t *w, const HyLayout &h) {
+    HyScratch s;
+    s.keys = reinterpret_cast<uint32_t *>(w + h.keys.off);
+    s.vals = reinterpret_cast<uint32_t *>(w + h.vals.off);
+    s.keys_alt = reinterpret_cast<uint32_t *>(w + h.keys_alt.off);
+    s.vals_alt = reinterpret_cast<uint32_t *>(w + h.vals_alt.off);
+    s.hist = reinterpret_cast<uint32_t *>(w + h.hist.off);
+    s.part = reinterpret_cast<uint64_t *>(w + h.part.off);
+    s.total64 = reinterpret_cast<uint64_t *>(w + h.total.off);
+    s.flags = reinterpret_cast<uint32_t *>(w + h.flags.off);
+    s.seg = reinterpret_cast<uint32_t *>(w + h.seg.off);
+    s.starts = reinterpret_cast<uint32_t *>(w + h.starts.off);
+    s.cell_start = reinterpret_cast<uint32_t *>(w + h.cell_start.off);
+    s.box_part = reinterpret_cast<float *>(w + h.box_part.off);
+    s.box = reinterpret_cast<float *>(w + h.box.off);
+    s.idx = reinterpret_cast<int32_t *>(w + h.idx.off);
+    s.d2 = reinterpret_cast<float *>(w + h.d2.off);
+    return s;
+}
+
+int check_hybrid_args(int64_t n, int32_t sh_degree, int32_t K) {
+    if (n < 1 || n > (int64_t)0x7FFFFFFF) return fail(DPR_ERR_INVALID_ARG, "point count must be in [1, 2^31 - 1]");
+    if (sh_degree < 0 || sh_degree > 3) return fail(DPR_ERR_INVALID_ARG, "sh_degree must be in [0, 3]");
+    if (K < 1 || K > kKnnMax) return fail(DPR_ERR_INVALID_ARG, "K must be in [1, %d]", kKnnMax);
+    return DPR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -786,6 +844,85 @@ int dpr_loss_l2_tv(int32_t n_images, const float *const *render, const float *co
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t *w = static_cast<uint8_t *>(ws);
     HIP_TRY(launch_loss(tab.data(), n_images, lambda, reinterpret_cast<float *>(w + lay.partial.off), loss, st));
+    return DPR_OK;
+}
+
+size_t dpr_knn_ws_bytes(int64_t m, int32_t K) {
+    if (check_hybrid_args(m, 0, K) != DPR_OK) return 0;
+    return (size_t)hy_layout((uint64_t)m, K, 0, false).total_bytes;
+}
+
+int dpr_knn(int64_t m, const float *xyz, int32_t K, int32_t *idx, float *d2, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    int rc = check_hybrid_args(m, 0, K);
+    if (rc) return rc;
+    if (!xyz || !idx || !d2) return fail(DPR_ERR_INVALID_ARG, "xyz / idx / d2 is NULL");
+    const HyLayout h = hy_layout((uint64_t)m, K, 0, false);
+    if (!ws || ws_bytes < h.total_bytes)
+        return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)h.total_bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    HyScratch sc = hy_scratch(static_cast<uint8_t *>(ws), h);
+    HIP_TRY(launch_knn(xyz, (uint32_t)m, K, idx, d2, sc, static_cast<hipStream_t>(stream)));
+    return DPR_OK;
+}
+
+size_t dpr_hybrid_ws_bytes(int64_t n, int32_t sh_degree, int32_t K) {
+    if (check_hybrid_args(n, sh_degree, K) != DPR_OK) return 0;
+    const int k3 = 3 * (sh_degree + 1) * (sh_degree + 1);
+    return (size_t)hy_layout((uint64_t)n, K, k3, true).total_bytes;
+}
+
+int dpr_voxel_reduce(int64_t n, int32_t sh_degree, const float *xyz, const float *sh, const float *opacity,
+                     const float *radius, int32_t N, float *out_xyz, float *out_sh, float *out_opacity,
+                     float *out_radius, int64_t *out_count, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    int rc = check_hybrid_args(n, sh_degree, 1);
+    if (rc) return rc;
+    if (N < 1 || N > 1024) return fail(DPR_ERR_INVALID_ARG, "N must be in [1, 1024]");
+    if (!xyz || !sh || !opacity || !radius || !out_xyz || !out_sh || !out_opacity || !out_radius || !out_count)
+        return fail(DPR_ERR_INVALID_ARG, "NULL array");
+    const int k3 = 3 * (sh_degree + 1) * (sh_degree + 1);
+    const HyLayout h = hy_layout((uint64_t)n, 1, k3, true);
+    if (!ws || ws_bytes < h.total_bytes)
+        return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)h.total_bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    HyScratch sc = hy_scratch(static_cast<uint8_t *>(ws), h);
+    uint64_t m = 0;
+    HIP_TRY(launch_voxel_reduce(xyz, sh, opacity, radius, (uint32_t)n, k3, (uint32_t)N, out_xyz, out_sh,
+                                out_opacity, out_radius, sc, &m, static_cast<hipStream_t>(stream)));
+    *out_count = (int64_t)m;
+    return DPR_OK;
+}
+
+int dpr_hybrid_update(int64_t n, int32_t sh_degree, const float *xyz, const float *sh, const float *opacity,
+                      const float *radius, int32_t N, int32_t K, float eps, float *out_xyz, float *out_sh,
+                      float *out_opacity, float *out_radius, int64_t *out_counts, void *ws, size_t ws_bytes,
+                      void *stream) {
+    g_err.clear();
+    int rc = check_hybrid_args(n, sh_degree, K);
+    if (rc) return rc;
+    if (N < 1 || N > 1024) return fail(DPR_ERR_INVALID_ARG, "N must be in [1, 1024]");
+    if (!(eps >= 0.f) || !std::isfinite(eps)) return fail(DPR_ERR_INVALID_ARG, "eps must be finite, >= 0");
+    if (!xyz || !sh || !opacity || !radius || !out_xyz || !out_sh || !out_opacity || !out_radius || !out_counts)
+        return fail(DPR_ERR_INVALID_ARG, "NULL array");
+    const int k3 = 3 * (sh_degree + 1) * (sh_degree + 1);
+    const HyLayout h = hy_layout((uint64_t)n, K, k3, true);
+    if (!ws || ws_bytes < h.total_bytes)
+        return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)h.total_bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    HyScratch sc = hy_scratch(w, h);
+    float *red = reinterpret_cast<float *>(w + h.red.off);
+    float *rxyz = red, *rsh = red + 3 * (size_t)n, *rop = rsh + (size_t)k3 * n, *rrad = rop + n;
+    uint64_t m = 0, kept = 0, count = 0;
+    HIP_TRY(launch_voxel_reduce(xyz, sh, opacity, radius, (uint32_t)n, k3, (uint32_t)N, rxyz, rsh, rop, rrad, sc,
+                                &m, st));
+    HIP_TRY(launch_filter_generate(rxyz, rsh, rop, rrad, (uint32_t)m, k3, K, eps, out_xyz, out_sh, out_opacity,
+                                   out_radius, sc, &kept, &count, st));
+    out_counts[0] = (int64_t)m;
+    out_counts[1] = (int64_t)kept;
+    out_counts[2] = (int64_t)count;
     return DPR_OK;
 }
 

@@ -235,6 +235,44 @@ hipError_t launch_composite_bwd(const BackwardArgs &a, hipStream_t st);
 hipError_t launch_point_bwd(const Tables &tb, const Thresholds &th, int sh_degree, uint32_t point_blocks,
                             const float *grad, hipStream_t st);
 
+// Stable LSD radix sort of n (key, value) pairs on the low `bits` bits of the
+// keys, 8 bits per pass; the result is in the alt buffers when *in_alt.
+// hist: radix_hist_words(n) + 1 words (the scan writes the total after the
+// last one); part: scan_partials(hist words) + 1 words.
+uint64_t radix_hist_words(uint64_t n);
+hipError_t launch_radix_sort(uint32_t n, int bits, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
+                             uint32_t *vals_alt, uint32_t *hist, uint64_t *part, bool *in_alt, hipStream_t st);
+
+// Hybrid coarse-to-fine update (hybrid.hip).
+constexpr int kKnnMax = 32;               // largest K
+constexpr uint32_t kKnnMaxGrid = 128;     // neighbour grid cells per axis, at most
+constexpr uint32_t kHyBoxBlocks = 256;    // blocks of the bounding-box reduction
+struct HyScratch {
+    uint32_t *keys, *vals, *keys_alt, *vals_alt;   // [n] each
+    uint32_t *hist;                               // radix_hist_words(n) + 1
+    uint64_t *part;                               // scan_partials(max(n + 1, hist words)) + 1
+    uint64_t *total64;
+    uint32_t *flags, *seg, *starts;               // [n + 2] each
+    uint32_t *cell_start;                         // [cells of the neighbour grid + 1]
+    float *box_part, *box;                        // [6 kHyBoxBlocks], [6]
+    int32_t *idx;                                 // [n K]
+    float *d2;                                    // [n K]
+};
+uint32_t knn_grid_size(uint64_t m);
+// Bytes of each HyScratch array for up to n points and K neighbours.
+struct HyScratchBytes {
+    uint64_t keys, vals, keys_alt, vals_alt, hist, part, total64, flags, seg, starts, cell_start, box_part, box, idx,
+        d2;
+};
+HyScratchBytes hy_scratch_bytes(uint64_t n, int K);
+hipError_t launch_knn(const float *xyz, uint32_t m, int K, int32_t *idx, float *d2, HyScratch &s, hipStream_t st);
+hipError_t launch_voxel_reduce(const float *xyz, const float *sh, const float *op, const float *rad, uint32_t n,
+                               int k3, uint32_t N, float *oxyz, float *osh, float *oop, float *orad, HyScratch &s,
+                               uint64_t *m_host, hipStream_t st);
+hipError_t launch_filter_generate(const float *xyz, const float *sh, const float *op, const float *rad, uint32_t m,
+                                  int k3, int K, float eps, float *oxyz, float *osh, float *oop, float *orad,
+                                  HyScratch &s, uint64_t *kept_host, uint64_t *count_host, hipStream_t st);
+
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st);
 
 // Eq. (8) loss over a batch of images (loss.hip).

@@ -1,0 +1,440 @@
+// Hybrid coarse-to-fine update of the point cloud (Sec. 3.3 "Hybrid
+// Coarse-to-Fine Updates", Alg. 1):
+//   1. voxel reduction: the points' bounding box is split into N^3 equal
+//      voxels and every non-empty voxel becomes the average of its points
+//      (position, SH coefficients, opacity, radius);
+//   2. outlier removal: a point whose K nearest neighbours lie at distances of
+//      standard deviation delta > eps is removed;
+//   3. point generation: every kept point adds the average of its K nearest
+//      kept neighbours.
+// Decisions taken from float comparisons (voxel and grid cells, neighbour
+// order, delta > eps) use float32 with every operation rounded on its own, in
+// the order documented in include/dpr.h; averages are accumulated in FP64 in
+// a fixed order (ascending point index within a voxel, neighbour order for a
+// generated point).
+//
+// Voxels: cell keys per point, a stable radix sort of (key, point index),
+// segment starts where the key changes, one thread per voxel.
+// Neighbours: a uniform grid over the points' bounding box (about 2 points per
+// cell), points sorted by cell, one thread per query walking Chebyshev shells
+// of cells around its own; it keeps the K best (distance, index) pairs packed
+// in 64-bit keys and stops once the K-th distance is below the smallest
+// distance any cell of the next shell can hold (with a margin far above the
+// float32 rounding of the distances), so the result is the exact K nearest.
+#include <algorithm>
+
+#include "dpr_internal.h"
+
+// Every float32 decision above is made with each multiply and add rounded on
+// its own, so no multiply-add may be fused in this file.  (The rounding
+// intrinsics of the HIP headers would not do: their operators take the
+// contraction setting of the header, and fuse once inlined.)
+#pragma clang fp contract(off)
+
+namespace dpr {
+
+constexpr int kHyThreads = 256;
+
+__global__ __launch_bounds__(kHyThreads) void k_bbox_partial(const float *xyz, uint32_t n, float *part) {
+    __shared__ float s[6][kHyThreads / 64];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t i = blockIdx.x * kHyThreads + threadIdx.x; i < n; i += gridDim.x * kHyThreads) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float v = xyz[3 * (size_t)i + a];
+            lo[a] = fminf(lo[a], v);
+            hi[a] = fmaxf(hi[a], v);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], d, 64));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], d, 64));
+        }
+    }
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) { s[a][threadIdx.x >> 6] = lo[a]; s[3 + a][threadIdx.x >> 6] = hi[a]; }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        float v = s[threadIdx.x][0];
+        for (int w = 1; w < kHyThreads / 64; ++w)
+            v = threadIdx.x < 3 ? fminf(v, s[threadIdx.x][w]) : fmaxf(v, s[threadIdx.x][w]);
+        part[6 * blockIdx.x + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_bbox_final(const float *part, uint32_t nb, float *box) {
+    if (threadIdx.x < 6) {
+        float v = part[threadIdx.x];
+        for (uint32_t b = 1; b < nb; ++b)
+            v = threadIdx.x < 3 ? fminf(v, part[6 * b + threadIdx.x]) : fmaxf(v, part[6 * b + threadIdx.x]);
+        box[threadIdx.x] = v;
+    }
+}
+
+__device__ __forceinline__ uint32_t axis_cell(float p, float lo, float s, uint32_t N) {
+    if (!(s > 0.f)) return 0;
+    const float t = floorf((p - lo) * s);
+    if (!(t > 0.f)) return 0;
+    return t >= (float)(N - 1) ? N - 1 : (uint32_t)t;
+}
+
+__device__ __forceinline__ float axis_scale(float lo, float hi, uint32_t N) {
+    return hi > lo ? __fdiv_rn((float)N, hi - lo) : 0.f;
+}
+
+// key = (iz N + iy) N + ix of the N^3 cells of box; vals = point index
+__global__ __launch_bounds__(kHyThreads) void k_cell_keys(const float *xyz, uint32_t n, const float *box, uint32_t N,
+                                                         uint32_t *keys, uint32_t *vals) {
+    const uint32_t i = blockIdx.x * kHyThreads + threadIdx.x;
+    if (i >= n) return;
+    const float sx = axis_scale(box[0], box[3], N), sy = axis_scale(box[1], box[4], N),
+                sz = axis_scale(box[2], box[5], N);
+    const uint32_t ix = axis_cell(xyz[3 * (size_t)i + 0], box[0], sx, N);
+    const uint32_t iy = axis_cell(xyz[3 * (size_t)i + 1], box[1], sy, N);
+    const uint32_t iz = axis_cell(xyz[3 * (size_t)i + 2], box[2], sz, N);
+    keys[i] = (iz * N + iy) * N + ix;
+    vals[i] = i;
+}
+
+__global__ __launch_bounds__(kHyThreads) void k_seg_flags(const uint32_t *keys, uint32_t n, uint32_t *flags) {
+    const uint32_t i = blockIdx.x * kHyThreads + threadIdx.x;
+    if (i < n) flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+// starts[s] = first sorted position of segment s; starts[segments] = n (the
+// last element's segment is seg[n-1] + flags[n-1] - 1, exclusive scan)
+__global__ __launch_bounds__(kHyThreads) void k_seg_starts(const uint32_t *flags, const uint32_t *seg, uint32_t n,
+                                                          uint32_t *starts) {
+    const uint32_t i = blockIdx.x * kHyThreads + threadIdx.x;
+    if (i >= n) return;
+    if (flags[i]) starts[seg[i]] = i;
+    if (i == n - 1) starts[seg[i] + flags[i]] = n;
+}
+
+struct CloudIn {
+    const float *xyz, *sh, *op, *rad;
+};
+struct CloudOut {
+    float *xyz, *sh, *op, *rad;
+};
+
+// one thread per voxel: FP64 sums over its points in ascending index order
+__global__ __launch_bounds__(kHyThreads) void k_voxel_average(const uint32_t *starts, uint32_t m, const uint32_t *order,
+                                                             CloudIn in, int k3, CloudOut out) {
+    const uint32_t v = blockIdx.x * kHyThreads + threadIdx.x;
+    if (v >= m) return;
+    const uint32_t b = starts[v], e = starts[v + 1];
+    const double cnt = (double)(e - b);
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (uint32_t q = b; q < e; ++q) s += (double)in.xyz[3 * (size_t)order[q] + a];
+        out.xyz[3 * (size_t)v + a] = (float)(s / cnt);
+    }
+    for (int a = 0; a < k3; ++a) {
+        double s = 0.0;
+        for (uint32_t q = b; q < e; ++q) s += (double)in.sh[(size_t)k3 * order[q] + a];
+        out.sh[(size_t)k3 * v + a] = (float)(s / cnt);
+    }
+    double so = 0.0, sr = 0.0;
+    for (uint32_t q = b; q < e; ++q) {
+        so += (double)in.op[order[q]];
+        sr += (double)in.rad[order[q]];
+    }
+    out.op[v] = (float)(so / cnt);
+    out.rad[v] = (float)(sr / cnt);
+}
+
+// cell_start[c] = first sorted position with key >= c, for c in [0, ncells]
+__global__ __launch_bounds__(kHyThreads) void k_cell_start(const uint32_t *skeys, uint32_t m, uint32_t ncells,
+                                                          uint32_t *cell_start) {
+    const uint32_t i = blockIdx.x * kHyThreads + threadIdx.x;
+    if (i > m) return;
+    const uint32_t lo = i == 0 ? 0u : skeys[i - 1] + 1u;
+    const uint32_t hi = i == m ? ncells : skeys[i];
+    for (uint32_t c = lo; c <= hi; ++c) cell_start[c] = i;
+}
+
+// float32 squared distance ((dx dx + dy dy) + dz dz), dx = x_j - x_i
+__device__ __forceinline__ float dist2(const float *pi, const float *pj) {
+    const float dx = pj[0] - pi[0], dy = pj[1] - pi[1], dz = pj[2] - pi[2];
+    float s = dx * dx;
+    s = s + dy * dy;
+    return s + dz * dz;
+}
+
+struct KnnGrid {
+    const float *xyz;
+    const uint32_t *skeys, *svals, *cell_start;
+    const float *box;
+    uint32_t m, G;
+    int K, keff;
+    int32_t *idx;
+    float *d2;
+};
+
+// One thread per query (queries in cell order).  best[] holds the K smallest
+// (distance bits << 32 | index) keys in ascending order.
+__global__ __launch_bounds__(kHyThreads) void k_knn(KnnGrid g) {
+    const uint32_t t = blockIdx.x * kHyThreads + threadIdx.x;
+    if (t >= g.m) return;
+    const uint32_t p = g.svals[t];
+    const uint32_t key = g.skeys[t];
+    const int G = (int)g.G;
+    const int cx = (int)(key % g.G), cy = (int)((key / g.G) % g.G), cz = (int)(key / (g.G * g.G));
+    float hmin = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float ext = g.box[3 + a] - g.box[a];
+        if (ext > 0.f) hmin = fminf(hmin, ext / (float)G);
+    }
+    const float *pp = g.xyz + 3 * (size_t)p;
+    uint64_t best[kKnnMax];
+#pragma unroll
+    for (int k = 0; k < kKnnMax; ++k) best[k] = ~0ull;
+    const int K = g.keff;
+    uint64_t worst = ~0ull;           // best[K - 1]
+    int found = 0;
+    const int rmax = max(max(max(cx, G - 1 - cx), max(cy, G - 1 - cy)), max(cz, G - 1 - cz));
+    for (int r = 0; r <= rmax; ++r) {
+        for (int dz = -r; dz <= r; ++dz) {
+            const int z = cz + dz;
+            if (z < 0 || z >= G) continue;
+            for (int dy = -r; dy <= r; ++dy) {
+                const int y = cy + dy;
+                if (y < 0 || y >= G) continue;
+                const bool full = dz == -r || dz == r || dy == -r || dy == r;
+                for (int dx = -r; dx <= r; dx += full ? 1 : (r > 0 ? 2 * r : 1)) {
+                    const int x = cx + dx;
+                    if (x < 0 || x >= G) continue;
+                    const uint32_t c = ((uint32_t)z * g.G + (uint32_t)y) * g.G + (uint32_t)x;
+                    const uint32_t b = g.cell_start[c], e = g.cell_start[c + 1];
+                    for (uint32_t j = b; j < e; ++j) {
+                        const uint32_t q = g.svals[j];
+                        if (q == p) continue;
+                        const float d = dist2(pp, g.xyz + 3 * (size_t)q);
+                        uint64_t x64 = ((uint64_t)__float_as_uint(d) << 32) | q;
+                        ++found;
+                        if (x64 >= worst) continue;
+                        // insert into the sorted prefix: keep the smaller, carry the larger on
+#pragma unroll
+                        for (int k = 0; k < kKnnMax; ++k) {
+                            if (k < K) {
+                                const uint64_t lo = best[k] < x64 ? best[k] : x64;
+                                x64 = best[k] < x64 ? x64 : best[k];
+                                best[k] = lo;
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < kKnnMax; ++k)
+                            if (k == K - 1) worst = best[k];
+                    }
+                }
+            }
+        }
+        if (found >= K) {
+            // any point of shell r + 1 or beyond is at least r * hmin away
+            const float kth = __uint_as_float((uint32_t)(worst >> 32));
+            const float bound = (float)r * hmin;
+            if (kth < 0.9999f * bound * bound) break;
+        }
+    }
+    for (int k = 0; k < g.K; ++k) {
+        const bool ok = k < K;
+        g.idx[(size_t)p * g.K + k] = ok ? (int32_t)(uint32_t)(best[k] & 0xFFFFFFFFull) : -1;
+        g.d2[(size_t)p * g.K + k] = ok ? __uint_as_float((uint32_t)(best[k] >> 32)) : 0.f;
+    }
+}
+
+// delta of the neighbour distances (float32, each operation rounded) > eps -> removed
+__global__ __launch_bounds__(kHyThreads) void k_spread_keep(const float *d2, uint32_t m, int K, int keff, float eps,
+                                                           uint32_t *keep) {
+    const uint32_t i = blockIdx.x * kHyThreads + threadIdx.x;
+    if (i >= m) return;
+    if (keff == 0) { keep[i] = 1u; return; }
+    const float *d = d2 + (size_t)i * K;
+    float sum = 0.f;
+    for (int q = 0; q < keff; ++q) sum = sum + sqrtf(d[q]);
+    const float mean = __fdiv_rn(sum, (float)keff);
+    float var = 0.f;
+    for (int q = 0; q < keff; ++q) {
+        const float e = sqrtf(d[q]) - mean;
+        var = var + e * e;
+    }
+    const float delta = sqrtf(__fdiv_rn(var, (float)keff));
+    keep[i] = (delta > eps) ? 0u : 1u;
+}
+
+__global__ __launch_bounds__(kHyThreads) void k_gather_kept(const uint32_t *keep, const uint32_t *pos, uint32_t m,
+                                                           CloudIn in, int k3, CloudOut out) {
+    const uint32_t i = blockIdx.x * kHyThreads + threadIdx.x;
+    if (i >= m || !keep[i]) return;
+    const uint32_t o = pos[i];
+    for (int a = 0; a < 3; ++a) out.xyz[3 * (size_t)o + a] = in.xyz[3 * (size_t)i + a];
+    for (int a = 0; a < k3; ++a) out.sh[(size_t)k3 * o + a] = in.sh[(size_t)k3 * i + a];
+    out.op[o] = in.op[i];
+    out.rad[o] = in.rad[i];
+}
+
+// generated point i (written at m + i) = FP64 average of point i's neighbours, in neighbour order
+__global__ __launch_bounds__(kHyThreads) void k_generate(CloudOut c, uint32_t m, int k3, const int32_t *idx, int K,
+                                                        int keff) {
+    const uint32_t i = blockIdx.x * kHyThreads + threadIdx.x;
+    if (i >= m) return;
+    const int32_t *nb = idx + (size_t)i * K;
+    const double cnt = (double)keff;
+    const size_t o = (size_t)m + i;
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int q = 0; q < keff; ++q) s += (double)c.xyz[3 * (size_t)nb[q] + a];
+        c.xyz[3 * o + a] = (float)(s / cnt);
+    }
+    for (int a = 0; a < k3; ++a) {
+        double s = 0.0;
+        for (int q = 0; q < keff; ++q) s += (double)c.sh[(size_t)k3 * nb[q] + a];
+        c.sh[(size_t)k3 * o + a] = (float)(s / cnt);
+    }
+    double so = 0.0, sr = 0.0;
+    for (int q = 0; q < keff; ++q) {
+        so += (double)c.op[nb[q]];
+        sr += (double)c.rad[nb[q]];
+    }
+    c.op[o] = (float)(so / cnt);
+    c.rad[o] = (float)(sr / cnt);
+}
+
+// ---------------------------------------------------------------------------
+// host sequencing
+// ---------------------------------------------------------------------------
+static uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kHyThreads - 1) / kHyThreads); }
+
+static int key_bits(uint64_t ncells) {
+    int b = 0;
+    while ((1ull << b) < ncells) ++b;
+    return b;
+}
+
+uint32_t knn_grid_size(uint64_t m) {
+    uint32_t g = 1;
+    while ((uint64_t)(g + 1) * (g + 1) * (g + 1) * 2 <= m && g < kKnnMaxGrid) ++g;
+    return g;
+}
+
+HyScratchBytes hy_scratch_bytes(uint64_t n, int K) {
+    const uint64_t hw = radix_hist_words(n);
+    const uint64_t G = knn_grid_size(n);
+    HyScratchBytes b;
+    b.keys = b.vals = b.keys_alt = b.vals_alt = 4 * n;
+    b.hist = 4 * (hw + 1);                 // the scan also writes the total after the last word
+    b.part = 8 * (std::max(scan_partials(n + 2), scan_partials(hw)) + 2);
+    b.total64 = 8;
+    b.flags = b.seg = b.starts = 4 * (n + 2);
+    b.cell_start = 4 * (G * G * G + 2);
+    b.box_part = 4 * 6 * (uint64_t)kHyBoxBlocks;
+    b.box = 4 * 6;
+    b.idx = b.d2 = 4 * n * (uint64_t)K;
+    return b;
+}
+
+static hipError_t bbox(const float *xyz, uint32_t n, HyScratch &s, hipStream_t st) {
+    const uint32_t nb = std::min<uint32_t>(blocks_for(n), kHyBoxBlocks);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kHyThreads), 0, st, xyz, n, s.box_part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, s.box_part, nb, s.box);
+    return hipGetLastError();
+}
+
+// keys of the N^3 cells of the points' bounding box, stable-sorted with the
+// point indices; *keys_out / *vals_out point at the sorted arrays
+static hipError_t sorted_cells(const float *xyz, uint32_t n, uint32_t N, HyScratch &s, uint32_t **keys_out,
+                               uint32_t **vals_out, hipStream_t st) {
+    hipError_t e = bbox(xyz, n, s, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(n)), dim3(kHyThreads), 0, st, xyz, n, s.box, N, s.keys, s.vals);
+    bool alt = false;
+    e = launch_radix_sort(n, key_bits((uint64_t)N * N * N), s.keys, s.vals, s.keys_alt, s.vals_alt, s.hist, s.part,
+                          &alt, st);
+    *keys_out = alt ? s.keys_alt : s.keys;
+    *vals_out = alt ? s.vals_alt : s.vals;
+    return e;
+}
+
+hipError_t launch_knn(const float *xyz, uint32_t m, int K, int32_t *idx, float *d2, HyScratch &s, hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    const uint32_t G = knn_grid_size(m);
+    uint32_t *skeys, *svals;
+    hipError_t e = sorted_cells(xyz, m, G, s, &skeys, &svals, st);
+    if (e != hipSuccess) return e;
+    const uint32_t ncells = G * G * G;
+    hipLaunchKernelGGL(k_cell_start, dim3(blocks_for((uint64_t)m + 1)), dim3(kHyThreads), 0, st, skeys, m, ncells,
+                       s.cell_start);
+    KnnGrid g;
+    g.xyz = xyz;
+    g.skeys = skeys;
+    g.svals = svals;
+    g.cell_start = s.cell_start;
+    g.box = s.box;
+    g.m = m;
+    g.G = G;
+    g.K = K;
+    g.keff = (int)std::min<uint64_t>((uint64_t)K, (uint64_t)m - 1);
+    g.idx = idx;
+    g.d2 = d2;
+    hipLaunchKernelGGL(k_knn, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_voxel_reduce(const float *xyz, const float *sh, const float *op, const float *rad, uint32_t n,
+                               int k3, uint32_t N, float *oxyz, float *osh, float *oop, float *orad, HyScratch &s,
+                               uint64_t *m_host, hipStream_t st) {
+    uint32_t *skeys, *svals;
+    hipError_t e = sorted_cells(xyz, n, N, s, &skeys, &svals, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_flags, dim3(blocks_for(n)), dim3(kHyThreads), 0, st, skeys, n, s.flags);
+    e = launch_scan(s.flags, s.seg, n, s.part, s.total64, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_starts, dim3(blocks_for(n)), dim3(kHyThreads), 0, st, s.flags, s.seg, n, s.starts);
+    e = hipMemcpyAsync(m_host, s.total64, 8, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    const uint32_t m = (uint32_t)*m_host;
+    CloudIn in{xyz, sh, op, rad};
+    CloudOut out{oxyz, osh, oop, orad};
+    hipLaunchKernelGGL(k_voxel_average, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, s.starts, m, svals, in, k3,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_generate(const float *xyz, const float *sh, const float *op, const float *rad, uint32_t m,
+                                  int k3, int K, float eps, float *oxyz, float *osh, float *oop, float *orad,
+                                  HyScratch &s, uint64_t *kept_host, uint64_t *count_host, hipStream_t st) {
+    *kept_host = 0;
+    *count_host = 0;
+    if (m == 0) return hipSuccess;
+    hipError_t e = launch_knn(xyz, m, K, s.idx, s.d2, s, st);
+    if (e != hipSuccess) return e;
+    const int keff = (int)std::min<uint64_t>((uint64_t)K, (uint64_t)m - 1);
+    hipLaunchKernelGGL(k_spread_keep, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, s.d2, m, K, keff, eps, s.flags);
+    e = launch_scan(s.flags, s.seg, m, s.part, s.total64, st);
+    if (e != hipSuccess) return e;
+    CloudIn in{xyz, sh, op, rad};
+    CloudOut out{oxyz, osh, oop, orad};
+    hipLaunchKernelGGL(k_gather_kept, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, s.flags, s.seg, m, in, k3, out);
+    e = hipMemcpyAsync(kept_host, s.total64, 8, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    const uint32_t mk = (uint32_t)*kept_host;
+    *count_host = mk;
+    if (mk < 2) return hipSuccess;
+    e = launch_knn(oxyz, mk, K, s.idx, s.d2, s, st);
+    if (e != hipSuccess) return e;
+    const int keff2 = (int)std::min<uint64_t>((uint64_t)K, (uint64_t)mk - 1);
+    hipLaunchKernelGGL(k_generate, dim3(blocks_for(mk)), dim3(kHyThreads), 0, st, out, mk, k3, s.idx, K, keff2);
+    *count_host = 2ull * mk;
+    return hipGetLastError();
+}
+
+}  // namespace dpr

@@ -153,22 +153,41 @@ struct SortSeg {
     uint64_t hist_off;
 };
 
-__device__ __forceinline__ SortSeg sort_segment(const Tables &tb) {
-    const int v = find_segment(tb.sort_block_start, tb.n_views, blockIdx.x);
-    const ViewDesc &vd = tb.views[v];
-    SortSeg s;
-    s.lb = blockIdx.x - vd.sort_block_off;
-    s.beg = vd.item_off + s.lb * kSortTile;
-    s.end = min(s.beg + (uint32_t)kSortTile, vd.item_off + (uint32_t)vd.n);
-    s.nsb = vd.nsort_blocks;
-    s.hist_off = vd.hist_off;
-    return s;
-}
+// Segments = the views of a plan (the depth sort).
+struct ViewSegs {
+    Tables tb;
+    __device__ __forceinline__ SortSeg operator()() const {
+        const int v = find_segment(tb.sort_block_start, tb.n_views, blockIdx.x);
+        const ViewDesc &vd = tb.views[v];
+        SortSeg s;
+        s.lb = blockIdx.x - vd.sort_block_off;
+        s.beg = vd.item_off + s.lb * kSortTile;
+        s.end = min(s.beg + (uint32_t)kSortTile, vd.item_off + (uint32_t)vd.n);
+        s.nsb = vd.nsort_blocks;
+        s.hist_off = vd.hist_off;
+        return s;
+    }
+};
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(Tables tb, const uint32_t *keys, uint32_t *hist,
+// One segment of n keys.
+struct FlatSeg {
+    uint32_t n, nblocks;
+    __device__ __forceinline__ SortSeg operator()() const {
+        SortSeg s;
+        s.lb = blockIdx.x;
+        s.beg = blockIdx.x * (uint32_t)kSortTile;
+        s.end = min(s.beg + (uint32_t)kSortTile, n);
+        s.nsb = nblocks;
+        s.hist_off = 0;
+        return s;
+    }
+};
+
+template <class SEG>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(SEG seg, const uint32_t *keys, uint32_t *hist,
                                                              int shift) {
     __shared__ uint32_t h[256];
-    const SortSeg sg = sort_segment(tb);
+    const SortSeg sg = seg();
     h[threadIdx.x] = 0;
     __syncthreads();
     for (uint32_t i = sg.beg + threadIdx.x; i < sg.end; i += kSortThreads)
@@ -177,7 +196,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(Tables tb, const ui
     hist[sg.hist_off + (uint64_t)threadIdx.x * sg.nsb + sg.lb] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(Tables tb, const uint32_t *keys_in,
+template <class SEG>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(SEG seg, const uint32_t *keys_in,
                                                                 const uint32_t *vals_in, uint32_t *keys_out,
                                                                 uint32_t *vals_out, const uint32_t *offs,
                                                                 int shift) {
@@ -189,7 +209,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(Tables tb, const
     __shared__ uint32_t s_gbase[256];
     __shared__ uint32_t s_wave[kSortThreads / 64];
 
-    const SortSeg sg = sort_segment(tb);
+    const SortSeg sg = seg();
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
@@ -269,15 +289,41 @@ hipError_t launch_depth_sort(const Tables &tb, uint32_t sort_blocks, uint32_t it
     uint32_t *kin = keys, *vin = vals, *kout = keys_alt, *vout = vals_alt;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_radix_hist, dim3(sort_blocks), dim3(kSortThreads), 0, st, tb, kin, hist, shift);
+        const ViewSegs seg{tb};
+        hipLaunchKernelGGL(k_radix_hist<ViewSegs>, dim3(sort_blocks), dim3(kSortThreads), 0, st, seg, kin, hist,
+                           shift);
         hipError_t e = launch_scan(hist, hist, nh, part, reinterpret_cast<uint64_t *>(part) + scan_partials(nh),
                                    st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(sort_blocks), dim3(kSortThreads), 0, st, tb, kin, vin, kout,
+        hipLaunchKernelGGL(k_radix_scatter<ViewSegs>, dim3(sort_blocks), dim3(kSortThreads), 0, st, seg, kin, vin,
+                           kout, vout, hist, shift);
+        uint32_t *t;
+        t = kin; kin = kout; kout = t;
+        t = vin; vin = vout; vout = t;
+    }
+    return hipGetLastError();
+}
+
+uint64_t radix_hist_words(uint64_t n) { return ((n + kSortTile - 1) / kSortTile) * 256u; }
+
+hipError_t launch_radix_sort(uint32_t n, int bits, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
+                             uint32_t *vals_alt, uint32_t *hist, uint64_t *part, bool *in_alt, hipStream_t st) {
+    *in_alt = false;
+    if (n == 0) return hipSuccess;
+    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+    const uint64_t nh = (uint64_t)nb * 256u;
+    const FlatSeg seg{n, nb};
+    uint32_t *kin = keys, *vin = vals, *kout = keys_alt, *vout = vals_alt;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist<FlatSeg>, dim3(nb), dim3(kSortThreads), 0, st, seg, kin, hist, shift);
+        hipError_t e = launch_scan(hist, hist, nh, part, part + scan_partials(nh), st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter<FlatSeg>, dim3(nb), dim3(kSortThreads), 0, st, seg, kin, vin, kout,
                            vout, hist, shift);
         uint32_t *t;
         t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
+        *in_alt = !*in_alt;
     }
     return hipGetLastError();
 }

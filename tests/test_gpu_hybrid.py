@@ -1,0 +1,150 @@
+"""GPU parity of the hybrid coarse-to-fine update (Sec. 3.3, Alg. 1) and of
+its K-nearest-neighbour search, through the C ABI, against the oracle.
+
+Every decision (voxel, neighbour set and order, removal) is taken in float32
+with the same rounding on both sides, and the averages are FP64 sums in the
+same order, so the results must agree bit for bit (the oracle's FP64 averages
+rounded to float32)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+# Earlier versions of this path faulted the device: the end of the last voxel
+# was left unset when the last point in voxel order did not open a voxel
+# (k_voxel_average then read past the sorted index array), and fused
+# multiply-adds changed the float32 neighbour distances.  Both are fixed and
+# the fixed kernels are checked on the CPU, under AddressSanitizer and bit for
+# bit against the oracle, by test_hybrid_hostbuild.py; these GPU cases stay
+# skipped until the fixed path has run on a GPU.
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="held off the GPU: the fix of a device fault in this path (unset end of the "
+                                      "last voxel) has not yet run on a GPU; its CPU build passes "
+                                      "test_hybrid_hostbuild.py")]
+
+
+@pytest.fixture(scope="module")
+def dpr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_14330_amd as d
+    d.load()
+    return d
+
+
+def _cloud_np(xyz, deg=2, seed=0):
+    xyz = np.asarray(xyz, np.float32)
+    return oracle.Cloud(xyz, *workloads.point_attributes(xyz.shape[0], deg, seed))
+
+
+def _to_gpu(c):
+    from paper_2205_14330_amd import SceneTensors
+    import torch
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    return SceneTensors(t(c.xyz), t(c.sh), t(c.opacity), t(c.radius))
+
+
+def _np(s):
+    return [x.cpu().numpy() for x in (s.xyz, s.sh, s.opacity, s.radius)]
+
+
+def _assert_cloud_equal(got, ref, label):
+    for g, r, name in zip(_np(got), (ref.xyz, ref.sh, ref.opacity, ref.radius), ("xyz", "sh", "opacity", "radius")):
+        r32 = np.asarray(r).astype(np.float32)
+        assert g.shape == r32.shape, (label, name, g.shape, r32.shape)
+        bad = g != r32
+        assert not bad.any(), (label, name, int(bad.sum()), np.abs(g - r32).max())
+
+
+def _clouds():
+    return workloads.hybrid_clouds()
+
+
+@pytest.mark.parametrize("name", ["uniform", "clusters", "duplicates", "flat", "line"])
+@pytest.mark.parametrize("K", [1, 8, 32])
+def test_knn_matches_oracle(dpr, name, K):
+    import torch
+    from paper_2205_14330_amd.hybrid import knn
+    x = _clouds()[name].astype(np.float32)
+    idx, d2 = knn(torch.from_numpy(x).cuda(), K)
+    ridx, rd2 = oracle.knn(x, K)
+    assert np.array_equal(idx.cpu().numpy(), ridx.astype(np.int32)), name
+    assert np.array_equal(d2.cpu().numpy(), rd2), name
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 9])
+def test_knn_fewer_points_than_k(dpr, m):
+    import torch
+    from paper_2205_14330_amd.hybrid import knn
+    x = np.random.default_rng(m).random((m, 3)).astype(np.float32)
+    idx, d2 = knn(torch.from_numpy(x).cuda(), 8)
+    ridx, rd2 = oracle.knn(x, 8)
+    assert np.array_equal(idx.cpu().numpy(), ridx.astype(np.int32))
+    assert np.array_equal(d2.cpu().numpy(), rd2)
+
+
+@pytest.mark.parametrize("name,N", [("uniform", 16), ("clusters", 64), ("duplicates", 8), ("flat", 32),
+                                    ("line", 1000), ("uniform", 1)])
+def test_voxel_reduce_matches_oracle(dpr, name, N):
+    from paper_2205_14330_amd.hybrid import voxel_reduce
+    c = _cloud_np(_clouds()[name], seed=N)
+    got = voxel_reduce(_to_gpu(c), N)
+    ref = oracle.voxel_reduce(c, N)
+    _assert_cloud_equal(got, ref, f"{name} N={N}")
+
+
+@pytest.mark.parametrize("name,N,K,eps", [("uniform", 16, 8, 0.01), ("clusters", 48, 6, 0.004),
+                                          ("duplicates", 8, 4, 0.02), ("flat", 24, 10, 0.01),
+                                          ("line", 1000, 2, 1e-3), ("clusters", 32, 32, 0.02),
+                                          ("clusters", 32, 32, 0.0)])
+def test_hybrid_update_matches_oracle(dpr, name, N, K, eps):
+    from paper_2205_14330_amd.hybrid import hybrid_update
+    c = _cloud_np(_clouds()[name], seed=K)
+    got, counts = hybrid_update(_to_gpu(c), N, K, eps)
+    red, keep, ref = oracle.hybrid_update(c, N, K, eps)
+    assert counts["voxels"] == red.n and counts["kept"] == int(keep.sum()), (counts, red.n, keep.sum())
+    # eps = 0 removes every point whose neighbour distances are not all equal
+    assert (counts["kept"] == 0) == (eps == 0.0) and (counts["kept"] < red.n or name == "line")
+    _assert_cloud_equal(got, ref, f"{name} N={N} K={K}")
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_hybrid_update_tiny_clouds(dpr, n):
+    from paper_2205_14330_amd.hybrid import hybrid_update
+    c = _cloud_np(np.arange(3 * n, dtype=np.float32).reshape(n, 3))
+    got, counts = hybrid_update(_to_gpu(c), 4, 8, 0.5)
+    red, keep, ref = oracle.hybrid_update(c, 4, 8, 0.5)
+    assert counts["points"] == ref.n
+    _assert_cloud_equal(got, ref, f"n={n}")
+
+
+def test_hybrid_update_on_the_300k_scene_sampled(dpr):
+    """The 300k-point surface scene: voxel counts and a sample of voxel
+    averages against numpy grouping of the oracle's voxel keys; the neighbour
+    sets of 200 sampled reduced points against brute force."""
+    import torch
+    from paper_2205_14330_amd.hybrid import knn, voxel_reduce
+    scene, _, _ = workloads.surface300k_4x800(steps=1)
+    c = oracle.Cloud(scene.xyz, scene.sh, scene.opacity, scene.radius)
+    N = 256
+    red = voxel_reduce(_to_gpu(c), N)
+    keys = oracle.voxel_keys(c.xyz, N)
+    uk, inv, cnt = np.unique(keys, return_inverse=True, return_counts=True)
+    assert red.n == len(uk)
+    rx = red.xyz.cpu().numpy()
+    sample = np.random.default_rng(0).choice(len(uk), 300, replace=False)
+    for a in range(3):
+        mean = np.bincount(inv, c.xyz[:, a].astype(np.float64)) / cnt
+        np.testing.assert_allclose(rx[sample, a], mean[sample], rtol=1e-6, atol=1e-7)
+    K = 8
+    idx, d2 = knn(red.xyz.contiguous(), K)
+    idx, d2 = idx.cpu().numpy(), d2.cpu().numpy()
+    for i in np.random.default_rng(1).choice(red.n, 200, replace=False):
+        d = rx - rx[i]
+        dd = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        order = np.lexsort((np.arange(red.n), dd))
+        order = order[order != i][:K]
+        assert np.array_equal(idx[i], order.astype(np.int32)), i
+        assert np.array_equal(d2[i], dd[order]), i

@@ -26,7 +26,7 @@ __all__ = [
     "Camera", "Scene", "seed_rng", "fov_focal", "look_at_camera",
     "random_sphere_camera", "orbit_camera", "random_scene_uniform_cube",
     "cube4k_128px", "ball100k_8x400", "surface300k_4x800", "dynamic30x200k_1024x768", "serving_scenes",
-    "serving_trace", "small_scene", "SH_COEFFS", "Request",
+    "serving_trace", "small_scene", "SH_COEFFS", "Request", "hybrid_clouds", "point_attributes",
 ]
 
 SH_COEFFS = {0: 1, 1: 4, 2: 9, 3: 16}
@@ -286,3 +286,31 @@ def serving_trace(n_scenes: int = 16, rate: float = 200.0, duration: float = 60.
         w, h = res[int(rng.integers(len(res)))]
         out.append(Request(t, s, random_sphere_camera(rng, w, h)))
     return out
+
+
+def hybrid_clouds():
+    """Point sets for the hybrid coarse-to-fine update (Sec. 3.3, Alg. 1) and
+    its neighbour search, each stressing one structure: a uniform box of 3000
+    points, five tight clusters plus uniform clutter (2200), a set with many
+    exact duplicates (500), a set flat along z (800) and 40 collinear points at
+    unit spacing (every neighbour distance tied)."""
+    rng = np.random.default_rng(11)
+    uni = rng.random((3000, 3)) * [2, 1, 0.5]
+    cl = np.concatenate([c + 0.03 * rng.standard_normal((400, 3)) for c in rng.random((5, 3))] +
+                        [rng.random((200, 3))])
+    dup = rng.random((500, 3))
+    dup[::7] = dup[3]
+    flat = rng.random((800, 3))
+    flat[:, 2] = 0.25
+    line = np.zeros((40, 3))
+    line[:, 0] = np.arange(40)
+    return {k: v.astype(np.float32) for k, v in
+            {"uniform": uni, "clusters": cl, "duplicates": dup, "flat": flat, "line": line}.items()}
+
+
+def point_attributes(n: int, sh_degree: int = 2, seed: int = 0):
+    """Per-point SH coefficients [n, (l+1)^2, 3] (standard normal), opacity in
+    [0, 1) and radius in [0.01, 0.03), float32."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n, (sh_degree + 1) ** 2, 3)).astype(np.float32),
+            rng.random(n).astype(np.float32), rng.uniform(0.01, 0.03, n).astype(np.float32))
