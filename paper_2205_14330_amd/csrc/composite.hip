@@ -300,6 +300,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     const CompositeArgs &a = b.c;
     const float neg_lambda = -a.th.lambda;
     const float alpha_max = a.th.alpha_max;
+    const float w_noclamp = __log2f(alpha_max) - 1e-5f;
     const int lane = threadIdx.x;
     float *const my_part = s_part + (lane >> 2) * kQuadStride;
     const uint32_t nwork = *b.work_count;
@@ -366,32 +367,46 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 if (more) load_rec(a, cbeg - kCompLanes + lane, lend, n0, n1, nid);
                 const int cnt = (int)min((uint32_t)kCompLanes, lend - cbeg);
                 for (int j = cnt - 1; j >= 0; --j) {
-                    const float4 f0 = s_rec[2 * j], f1 = s_rec[2 * j + 1];
+                    const float4 f0 = s_rec[2 * j];
                     SplatRec s;
                     s.px = f0.x; s.py = f0.y; s.a = f0.z; s.b = f0.w;
-                    s.w = f1.x; s.cr = f1.y; s.cg = f1.z; s.cb = f1.w;
+                    s.w = s_rec[2 * j + 1].x;
                     const uint32_t pos = cbeg - c.start + (uint32_t)j;
                     float gw[kQuad], Ta[kQuad], e[kQuad], g[kQuad], alpha[kQuad], qs[kQuad];
                     float dx0 = 0.f, dy0 = 0.f;
                     bool hit[kQuad];
-                    bool any = false, any_clamped = false;
+                    bool any = false;
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
                         float dx, dy;
                         e[p] = splat_exponent(s, ux[p], uy[p], dx, dy, qs[p]);
                         if (p == 0) { dx0 = dx; dy0 = dy; }
                         hit[p] = pos < nl[p] && e[p] >= neg_lambda;
+                        any = any || hit[p];
+                    }
+                    // a splat that no pixel of the tile blended changes nothing below
+                    // (alpha = 0 for every pixel makes every update an exact no-op)
+                    if (__ballot(any) == 0ull) continue;
+                    const float4 f1 = s_rec[2 * j + 1];
+                    s.cr = f1.y; s.cg = f1.z; s.cb = f1.w;
+                    bool any_clamped = false;
+#pragma unroll
+                    for (int p = 0; p < kQuad; ++p) {
                         g[p] = __builtin_amdgcn_exp2f(e[p]);
                         // a pixel that did not blend this splat gets alpha = 0, so
                         // 1/(1 - alpha) = 1 and every update below is an exact no-op for it
                         alpha[p] = hit[p] ? g[p] : 0.f;
-                        any = any || hit[p];
-                        any_clamped = any_clamped || (hit[p] && g[p] > alpha_max);
                     }
-                    const bool wave_any = __ballot(any) != 0ull;
                     // the alpha_max clamp, which also blocks the gradient to e, is rare:
-                    // it is applied on a path of its own, before and after the update
-                    const bool wave_clamped = __builtin_expect(__ballot(any_clamped) != 0ull, 0);
+                    // it is applied on a path of its own, before and after the update.
+                    // e <= w (q >= 0), so a splat whose peak 2^w stays below alpha_max
+                    // (with a margin far above the error of exp2) clamps no pixel.
+                    bool wave_clamped = false;
+                    if (__builtin_expect(s.w > w_noclamp, 0)) {
+#pragma unroll
+                        for (int p = 0; p < kQuad; ++p) any_clamped = any_clamped || (hit[p] && g[p] > alpha_max);
+                        wave_clamped = __ballot(any_clamped) != 0ull;
+                    }
                     if (wave_clamped) {
 #pragma unroll
                         for (int p = 0; p < kQuad; ++p)
@@ -412,7 +427,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         for (int p = 0; p < kQuad; ++p)
                             if (hit[p] && g[p] > alpha_max) gw[p] = 0.f;
                     }
-                    if (wave_any) {
+                    {
                         // quad pixel p sits at (+(p & 1), +(p >> 1)) from pixel 0, so its
                         // dx is dx0 - (p & 1) and its dy is dy0 - (p >> 1)
                         const float gx = gw[1] + gw[3], gz = gw[0] + gw[2];
