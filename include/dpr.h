@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define DPR_ABI_VERSION 1
+#define DPR_ABI_VERSION 2
 
 typedef enum dpr_status {
     DPR_OK = 0,
@@ -124,6 +124,10 @@ typedef struct dpr_params {
     int32_t flags;           /* DPR_FLAG_* bitmask                                              */
     int32_t max_splats;      /* > 0: a pixel blends at most this many splats, its first ones
                                 in depth order (Sec. 3.3 uses n = 15); 0: no cap              */
+    int32_t timing_stages;   /* with DPR_FLAG_TIMING: the stages to time, bit s = DPR_STAGE s;
+                                0: every stage.  Each timed stage records two HIP events on
+                                the stream, so timing only the stage of interest keeps the
+                                others' launches back to back                                   */
 } dpr_params;
 
 typedef struct dpr_plan dpr_plan;   /* opaque, host-side */
@@ -302,7 +306,7 @@ int dpr_plan_get_info(const dpr_plan *plan, dpr_plan_info *out);
 
 /* With DPR_FLAG_TIMING: milliseconds of each stage of the most recent call
  * that ran it, measured with HIP events on the plan's stream (-1 where the
- * stage did not run).  Synchronizes on those events.  cap >= DPR_STAGE_COUNT. */
+ * stage did not run or is not in timing_stages).  Synchronizes on those events.  cap >= DPR_STAGE_COUNT. */
 int dpr_stage_times(const dpr_plan *plan, float *ms, int32_t cap);
 
 /* Convenience form of the single-scene, single-camera renderer:

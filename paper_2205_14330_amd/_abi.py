@@ -43,7 +43,8 @@ class View(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("alpha_min", c_f), ("t_min", c_f), ("alpha_max", c_f), ("z_near", c_f),
-                ("sh_frame", c_i32), ("bwd_mode", c_i32), ("flags", c_i32), ("max_splats", c_i32)]
+                ("sh_frame", c_i32), ("bwd_mode", c_i32), ("flags", c_i32), ("max_splats", c_i32),
+                ("timing_stages", c_i32)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -108,6 +108,8 @@ int check_params(const dpr_params *pr) {
     if (pr->flags & ~(DPR_FLAG_TIMING | DPR_FLAG_STATS | DPR_FLAG_PERSISTENT | DPR_FLAG_KERNEL_NORM))
         return fail(DPR_ERR_INVALID_ARG, "unknown flags 0x%x", pr->flags);
     if (pr->max_splats < 0) return fail(DPR_ERR_INVALID_ARG, "max_splats must be >= 0");
+    if (pr->timing_stages & ~((1 << DPR_STAGE_COUNT) - 1))
+        return fail(DPR_ERR_INVALID_ARG, "timing_stages 0x%x names no stage", pr->timing_stages);
     return DPR_OK;
 }
 
@@ -192,6 +194,7 @@ struct dpr_plan {
     const void *fwd_ws = nullptr;
     Events ev;
     bool timing = false;
+    uint32_t timed = 0;             // bit s: stage s records its events
     // backward host tables (kept alive while copies may be in flight)
     std::vector<uint64_t> bwd_tab;
     std::vector<SceneDesc> sdesc_bwd;
@@ -223,10 +226,10 @@ struct StageScope {
     int stage;
     hipStream_t st;
     StageScope(dpr_plan *p_, int s, hipStream_t st_) : p(p_), stage(s), st(st_) {
-        if (p->timing) hipEventRecord(p->ev.a[stage], st);
+        if ((p->timed >> stage) & 1u) hipEventRecord(p->ev.a[stage], st);
     }
     ~StageScope() {
-        if (p->timing) {
+        if ((p->timed >> stage) & 1u) {
             hipEventRecord(p->ev.b[stage], st);
             p->ev.ran[stage] = true;
         }
@@ -445,6 +448,8 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
     p->views.assign(views, views + n_views);
     p->pws = static_cast<uint8_t *>(plan_ws);
     p->timing = (params->flags & DPR_FLAG_TIMING) != 0;
+    p->timed = !p->timing ? 0u
+                          : (params->timing_stages ? (uint32_t)params->timing_stages : (1u << DPR_STAGE_COUNT) - 1u);
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     auto cleanup_fail = [&](int code) {
@@ -453,6 +458,7 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
     };
     if (p->timing) {
         for (int i = 0; i < DPR_STAGE_COUNT; ++i) {
+            if (!((p->timed >> i) & 1u)) continue;
             if (hipEventCreate(&p->ev.a[i]) != hipSuccess || hipEventCreate(&p->ev.b[i]) != hipSuccess)
                 return cleanup_fail(fail(DPR_ERR_HIP, "hipEventCreate failed"));
         }

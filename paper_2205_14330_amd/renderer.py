@@ -33,6 +33,7 @@ class RenderParams:
     persistent: bool = False
     max_splats: int = 0            # > 0: a pixel blends at most this many splats (the paper's n = 15)
     kernel_norm: bool = False      # keep Eq. (5)'s normalisation prefactor
+    timing_stages: tuple = ()      # with timing: names of the stages to time (empty: all)
 
     @staticmethod
     def paper(**kw) -> "RenderParams":
@@ -43,8 +44,11 @@ class RenderParams:
         flags = (FLAG_TIMING if self.timing else 0) | (FLAG_STATS if self.stats else 0) | \
                 (FLAG_PERSISTENT if self.persistent else 0) | (FLAG_KERNEL_NORM if self.kernel_norm else 0)
         mode = {"stored": BWD_STORED, "recompute": BWD_RECOMPUTE}[self.bwd_mode]
+        mask = 0
+        for name in self.timing_stages:
+            mask |= 1 << _abi.STAGES.index(name)
         return _abi.Params(self.alpha_min, self.t_min, self.alpha_max, self.z_near, self.sh_frame, mode, flags,
-                           int(self.max_splats))
+                           int(self.max_splats), mask)
 
 
 @dataclasses.dataclass

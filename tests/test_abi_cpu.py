@@ -96,7 +96,7 @@ def _view(abi, scene=0, w=64, h=48, image=FAKE, trans=FAKE, fx=50.0):
 
 
 def _params(abi, **kw):
-    p = abi.Params(1e-5, 1e-5, 0.99, 0.01, 0, 0, 0, 0)
+    p = abi.Params(1e-5, 1e-5, 0.99, 0.01, 0, 0, 0, 0, 0)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -114,7 +114,7 @@ def _plan(abi, scenes, views, params, ws=FAKE, ws_bytes=1 << 40):
 
 @pytest.mark.parametrize("case,expect", [
     ("alpha_min", 1), ("t_min", 1), ("alpha_max", 1), ("z_near", 1), ("sh_frame", 1), ("bwd_mode", 1),
-    ("flags", 1), ("max_splats", 1), ("scene_index", 1), ("width", 1), ("height", 1), ("fx", 1),
+    ("flags", 1), ("max_splats", 1), ("timing_stages", 1), ("scene_index", 1), ("width", 1), ("height", 1), ("fx", 1),
     ("null_image", 1), ("sh_degree", 1), ("neg_n", 1), ("null_xyz", 1), ("mixed_degree", 4),
     ("no_views", 1), ("workspace", 2), ("null_ws", 2),
 ])
@@ -141,6 +141,9 @@ def test_invalid_arguments_rejected(abi, case, expect):
         params.flags = 64
     elif case == "max_splats":
         params.max_splats = -1
+    elif case == "timing_stages":
+        params.flags = 1
+        params.timing_stages = 1 << 12
     elif case == "scene_index":
         views = [_view(abi, scene=1)]
     elif case == "width":
@@ -205,7 +208,7 @@ def test_null_plan_calls(abi):
     assert lib.dpr_render_forward(None, FAKE, 100, None) == 1
     info = abi.PlanInfo()
     assert lib.dpr_plan_get_info(None, ctypes.byref(info)) == 1
-    assert lib.dpr_version() == 1
+    assert lib.dpr_version() == 2
 
 
 def test_forward_1_query_size_without_workspace(abi):

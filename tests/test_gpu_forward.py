@@ -268,6 +268,20 @@ def test_stats_count_blended_splats(dpr):
     assert abs(int(st.sum()) - int(ref.ncontrib.sum())) <= 0.001 * ref.ncontrib.sum() + 5
 
 
+def test_timing_of_selected_stages(dpr):
+    """With timing_stages only the named stages report a time; the image is the
+    same as without timing."""
+    sc, cam = _scene_cam(71, n=3000, size=(48, 48))
+    ref = gpu_plan([sc], [(0, cam)], dpr.RenderParams())
+    for stages in (("composite_fwd",), ("depth_sort", "emit"), ()):
+        plan = gpu_plan([sc], [(0, cam)], dpr.RenderParams(timing=True, timing_stages=stages))
+        st = plan.stage_times()
+        timed = {k for k, v in st.items() if v >= 0}
+        expect = set(stages) if stages else {k for k in st if k not in ("composite_bwd", "recompute", "point_bwd")}
+        assert timed == expect, (stages, st)
+        assert np.array_equal(to_np(plan.images[0]), to_np(ref.images[0]))
+
+
 def test_ball100k_forward_parity_sampled(dpr):
     """100k points, 8 views of 400x400: 2 full frames + 4096 pixels of every view."""
     sc, cams, _, _ = workloads.ball100k_8x400()
