@@ -208,9 +208,7 @@ def main():
         for s_, v in p.stage_times().items():
             if v > 0:
                 stage_ms[s_] += v
-        inf = p.info()
-        blend_acc.add_(p.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32).sum())
-        pair_acc[0] += inf.pairs
+        pair_acc[0] += p.info().pairs
 
     def reset():
         for s_ in stage_ms:
@@ -222,18 +220,29 @@ def main():
     # events on the stream, which stretch the step, so this loop is short and
     # only names the dominant kernel and splits the step into stages.
     KB = min(args.steps, 10)
-    timed(dpr.RenderParams(timing=True, stats=True, **base), True, KB, args.warmup, collect, reset)
+    timed(dpr.RenderParams(timing=True, **base), True, KB, args.warmup, collect, reset)
     breakdown = {s_: v / KB for s_, v in stage_ms.items()}
     dom = max(breakdown, key=lambda s_: breakdown[s_])
     log("stage ms/step (every stage timed): " + ", ".join(f"{s_}={v:.3f}" for s_, v in breakdown.items()))
 
     # main metric: forward + backward (stored T), HIP events around the dominant
-    # kernel only (its live launch duration for the roofline), blend counts
-    t_fb = timed(dpr.RenderParams(timing=True, stats=True, timing_stages=(dom,), **base), True, args.steps,
+    # kernel only (its live launch duration for the roofline)
+    t_fb = timed(dpr.RenderParams(timing=True, timing_stages=(dom,), **base), True, args.steps,
                  args.warmup, collect, reset)
-    blends = int(blend_acc.item())
     pairs = pair_acc[0]
     K = args.steps
+    # blended (pixel, splat) pairs of the timed steps, from the forward's
+    # per-pixel counters in a pass of their own over the same views (the
+    # forward is bitwise deterministic, so the counts are those of the timed
+    # launches; counting inside the timed loop would add a reduction per step)
+    for k in range(args.warmup, args.warmup + K):
+        p = dpr.Plan([scene], [(0, c) for c in step_views[k]], dpr.RenderParams(stats=True, **base),
+                     workspace=wss[k % 2])
+        p.forward()
+        inf = p.info()
+        blend_acc.add_(p.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32).sum())
+        p.free()
+    blends = int(blend_acc.item())
     mpix_fb = pix_step * K / t_fb / 1e6
     log(f"fwd+bwd: {t_fb / K * 1e3:.3f} ms/step, {mpix_fb:.1f} Mpix/s; {dom} {stage_ms[dom] / K:.3f} ms/launch")
 
