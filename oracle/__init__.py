@@ -21,7 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "hybrid.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "hybrid.c"), os.path.join(_HERE, "hull.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -89,6 +89,14 @@ def lib():
         L.hybrid_knn.restype = ctypes.c_int
         L.hybrid_filter_generate.argtypes = [i64, i32, P, P, P, P, i32, ctypes.c_float, P, P, P, P, P]
         L.hybrid_filter_generate.restype = i64
+        L.hull_philox.argtypes = [P, P, P]
+        L.hull_philox.restype = None
+        L.hull_candidates.argtypes = [ctypes.c_uint64, i64, P, P, P]
+        L.hull_candidates.restype = None
+        L.hull_consistent.argtypes = [i64, P, i32, P, P, P, P]
+        L.hull_consistent.restype = ctypes.c_int
+        L.hull_sample.argtypes = [i32, P, P, P, P, P, ctypes.c_uint64, i64, P, i64]
+        L.hull_sample.restype = i64
         for f in (L.oracle_sh_basis, L.oracle_project, L.oracle_depth_order, L.oracle_render,
                   L.oracle_backward, L.oracle_max_threads):
             f.restype = ctypes.c_int
@@ -373,3 +381,67 @@ def hybrid_update(cloud, N: int, K: int, eps: float):
     red = voxel_reduce(cloud, N)
     keep, out = filter_generate(red.astype(np.float32), K, eps)
     return red, keep, out
+
+
+# ---------------------------------------------------------------------------
+# visual-hull initialisation and consistency filter (oracle/hull.c)
+# ---------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """Philox4x32-10 (Salmon et al., SC 2011) of a 4-word counter and 2-word key."""
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().hull_philox(_p(c), _p(k), _p(out))
+    return out
+
+
+def hull_candidates(seed: int, n: int, lo, hi) -> np.ndarray:
+    """The first n candidates of the rejection sampler, float32 [n, 3]."""
+    lo = _f32(lo); hi = _f32(hi)
+    out = np.zeros((n, 3), np.float32)
+    lib().hull_candidates(int(seed), int(n), _p(lo), _p(hi), _p(out))
+    return out
+
+
+def _hull_tables(cams, masks):
+    if len(cams) != len(masks) or not cams:
+        raise ValueError("one mask per camera, at least one camera")
+    cam = np.stack([cam_array(c) for c in cams]).astype(np.float32)
+    ms = [np.ascontiguousarray(m, np.uint8) for m in masks]
+    dims = np.array([[m.shape[1], m.shape[0]] for m in ms], np.int32)
+    for c, m in zip(cams, ms):
+        if (c.width, c.height) != (m.shape[1], m.shape[0]):
+            raise ValueError("mask size differs from its camera's image size")
+    ptrs = (ctypes.c_void_p * len(ms))(*[m.ctypes.data for m in ms])
+    return cam, dims, ms, ptrs
+
+
+def hull_consistent(xyz, cams, masks) -> np.ndarray:
+    """CC of every point: inside the foreground of every mask (bool [n])."""
+    x = _f32(xyz).reshape(-1, 3)
+    cam, dims, ms, ptrs = _hull_tables(cams, masks)
+    keep = np.zeros(x.shape[0], np.uint8)
+    if lib().hull_consistent(x.shape[0], _p(x), len(ms), _p(cam), _p(dims), ptrs, _p(keep)) != 0:
+        raise ValueError("bad input")
+    return keep.astype(bool)
+
+
+def hull_sample(cams, masks, lo, hi, seed: int, n: int, capacity: Optional[int] = None):
+    """Rejection sampling of n candidates in [lo, hi]: (number kept, kept
+    points float32 [min(kept, capacity), 3] in candidate order)."""
+    lo = _f32(lo); hi = _f32(hi)
+    cam, dims, ms, ptrs = _hull_tables(cams, masks)
+    cap = n if capacity is None else int(capacity)
+    out = np.zeros((max(cap, 1), 3), np.float32)
+    kept = lib().hull_sample(len(ms), _p(cam), _p(dims), ptrs, _p(lo), _p(hi), int(seed), int(n), _p(out), cap)
+    if kept < 0:
+        raise ValueError("bad input")
+    return int(kept), out[:min(kept, cap)]
+
+
+def consistency_filter(cloud, cams, masks):
+    """The points of the cloud with CC = 1, in input order: (keep [n], Cloud)."""
+    c = cloud.astype(np.float32)
+    keep = hull_consistent(c.xyz, cams, masks)
+    return keep, Cloud(c.xyz[keep], c.sh[keep], c.opacity[keep], c.radius[keep])

@@ -27,6 +27,7 @@ __all__ = [
     "random_sphere_camera", "orbit_camera", "random_scene_uniform_cube",
     "cube4k_128px", "ball100k_8x400", "surface300k_4x800", "dynamic30x200k_1024x768", "serving_scenes",
     "serving_trace", "small_scene", "SH_COEFFS", "Request", "hybrid_clouds", "point_attributes",
+    "sphere_masks", "disc_views",
 ]
 
 SH_COEFFS = {0: 1, 1: 4, 2: 9, 3: 16}
@@ -314,3 +315,35 @@ def point_attributes(n: int, sh_degree: int = 2, seed: int = 0):
     rng = np.random.default_rng(seed)
     return (rng.standard_normal((n, (sh_degree + 1) ** 2, 3)).astype(np.float32),
             rng.random(n).astype(np.float32), rng.uniform(0.01, 0.03, n).astype(np.float32))
+
+
+def disc_views(k: int, size: int = 64, dist: float = 3.0, seed: int = 0) -> List[Camera]:
+    """k cameras at distance `dist` from the origin, looking at it from random
+    directions, square images of `size` pixels (fov 50 degrees)."""
+    rng = np.random.default_rng(np.random.SeedSequence(0, spawn_key=(6, seed)))
+    cams = []
+    for _ in range(k):
+        v = rng.standard_normal(3)
+        cams.append(look_at_camera(dist * v / np.linalg.norm(v), size, size))
+    return cams
+
+
+def sphere_masks(cams, radius: float):
+    """Foreground masks (uint8 [H, W]) of a sphere of `radius` at the origin:
+    pixel (c, r) is foreground when the ray from the camera centre through the
+    pixel centre (c + 0.5, r + 0.5) meets the sphere, i.e. its angle to the
+    direction of the origin is at most asin(radius / distance)."""
+    out = []
+    for cam in cams:
+        R = np.asarray(cam.R, np.float64).reshape(3, 3)
+        t = np.asarray(cam.t, np.float64)
+        C = -R.T @ t                                      # camera centre in the world
+        d = np.linalg.norm(C)
+        xs = (np.arange(cam.width) + 0.5 - cam.cx) / cam.fx
+        ys = (np.arange(cam.height) + 0.5 - cam.cy) / cam.fy
+        X, Y = np.meshgrid(xs, ys)
+        dirs = np.stack([X, Y, np.ones_like(X)], -1) @ R   # camera -> world directions (rows)
+        dirs /= np.linalg.norm(dirs, axis=-1, keepdims=True)
+        cosang = dirs @ (-C / d)
+        out.append((cosang >= np.sqrt(max(0.0, 1.0 - (radius / d) ** 2))).astype(np.uint8))
+    return out
