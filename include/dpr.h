@@ -298,6 +298,55 @@ int dpr_hybrid_update(int64_t n, int32_t sh_degree, const float *xyz, const floa
                       float *out_opacity, float *out_radius, int64_t *out_counts, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Visual-hull initialisation and multi-view consistency filter (Sec. 3.1
+ * "Initialization" and the appendix's consistency check CC: a point is kept
+ * when it projects onto a foreground pixel of every camera's mask).
+ * The pixel decision is taken in float32, each operation rounded once:
+ *   X_c = fma(R_c0, x, fma(R_c1, y, fma(R_c2, z, t_c)))   (c = 0, 1, 2)
+ *   px = fma(fx, X_0 / X_2, cx),  py = fma(fy, X_1 / X_2, cy)
+ * P is inside mask i iff X_2 > 0, 0 <= px < width, 0 <= py < height and the
+ * mask byte at (floor(py), floor(px)) is non-zero.
+ * Sampling draws candidate j (j = 0 .. n-1) from Philox4x32-10 (Salmon et al.,
+ * SC 2011) with counter (j mod 2^32, j div 2^32, 0, 0) and key (seed mod 2^32,
+ * seed div 2^32): with its first three output words r, coordinate d is
+ * fma((r_d >> 8) * 2^-24, hi_d - lo_d, lo_d) (hi_d - lo_d rounded once).
+ * At most 4096 cameras per call; each mask must have its camera's image size.
+ * ------------------------------------------------------------------------- */
+
+/* Foreground mask of one camera: device bytes, row-major, width x height;
+ * foreground where non-zero.  The caller owns it. */
+typedef struct dpr_mask {
+    const uint8_t *data;
+    int32_t width, height;
+} dpr_mask;
+
+/* Bytes of the device workspace for n candidates or points and n_cams cameras
+ * (0 on bad sizes). */
+size_t dpr_hull_ws_bytes(int64_t n, int32_t n_cams);
+
+/* Rejection sampling of n candidates (0 <= n < 2^31) in the box [lo, hi] (host
+ * float[3] each, lo < hi): the consistent ones, in candidate order, are written
+ * to out_xyz (device float[capacity][3]; the first `capacity` of them);
+ * *out_count (host) = the number of consistent candidates, which may exceed
+ * capacity.  Synchronizes `stream` once. */
+int dpr_hull_sample(int32_t n_cams, const dpr_camera *cams, const dpr_mask *masks, const float *lo, const float *hi,
+                    uint64_t seed, int64_t n, float *out_xyz, int64_t capacity, int64_t *out_count, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* keep[j] = CC(P_j) (1 or 0) for n points (device float[n][3] -> device
+ * uint8[n]).  Asynchronous on `stream`. */
+int dpr_consistency(int64_t n, const float *xyz, int32_t n_cams, const dpr_camera *cams, const dpr_mask *masks,
+                    uint8_t *keep, void *ws, size_t ws_bytes, void *stream);
+
+/* The consistent points of a cloud (every parameter, input order) into out_*
+ * (capacity n points; must not overlap the inputs); *out_count (host) = their
+ * number.  Synchronizes `stream` once. */
+int dpr_consistency_filter(int64_t n, int32_t sh_degree, const float *xyz, const float *sh, const float *opacity,
+                           const float *radius, int32_t n_cams, const dpr_camera *cams, const dpr_mask *masks,
+                           float *out_xyz, float *out_sh, float *out_opacity, float *out_radius, int64_t *out_count,
+                           void *ws, size_t ws_bytes, void *stream);
+
 /* Releases a plan (host memory and HIP events only).  NULL is ignored. */
 void dpr_plan_free(dpr_plan *plan);
 

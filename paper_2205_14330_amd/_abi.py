@@ -24,12 +24,17 @@ EXPORTED = ["dpr_version", "dpr_last_error", "dpr_plan_ws_bytes", "dpr_plan_forw
             "dpr_workspace_bytes", "dpr_render_forward", "dpr_backward_ws_bytes",
             "dpr_render_backward", "dpr_plan_free", "dpr_plan_get_info", "dpr_stage_times",
             "dpr_render_forward_1", "dpr_loss_ws_bytes", "dpr_loss_l2_tv", "dpr_knn_ws_bytes", "dpr_knn",
-            "dpr_hybrid_ws_bytes", "dpr_voxel_reduce", "dpr_hybrid_update"]
+            "dpr_hybrid_ws_bytes", "dpr_voxel_reduce", "dpr_hybrid_update", "dpr_hull_ws_bytes", "dpr_hull_sample",
+            "dpr_consistency", "dpr_consistency_filter"]
 
 
 class Camera(ctypes.Structure):
     _fields_ = [("R", c_f * 9), ("t", c_f * 3), ("fx", c_f), ("fy", c_f), ("cx", c_f), ("cy", c_f),
                 ("width", c_i32), ("height", c_i32)]
+
+
+class Mask(ctypes.Structure):
+    _fields_ = [("data", c_p), ("width", c_i32), ("height", c_i32)]
 
 
 class Scene(ctypes.Structure):
@@ -105,6 +110,14 @@ def load(path: str = LIB_PATH):
     L.dpr_hybrid_update.argtypes = [c_i64, c_i32, c_p, c_p, c_p, c_p, c_i32, c_i32, c_f, c_p, c_p, c_p, c_p, I64P,
                                     c_p, c_sz, c_p]
     L.dpr_hybrid_update.restype = c_i32
+    L.dpr_hull_ws_bytes.argtypes, L.dpr_hull_ws_bytes.restype = [c_i64, c_i32], c_sz
+    L.dpr_hull_sample.argtypes = [c_i32, c_p, c_p, c_p, c_p, ctypes.c_uint64, c_i64, c_p, c_i64, I64P, c_p, c_sz, c_p]
+    L.dpr_hull_sample.restype = c_i32
+    L.dpr_consistency.argtypes = [c_i64, c_p, c_i32, c_p, c_p, c_p, c_p, c_sz, c_p]
+    L.dpr_consistency.restype = c_i32
+    L.dpr_consistency_filter.argtypes = [c_i64, c_i32, c_p, c_p, c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, I64P,
+                                         c_p, c_sz, c_p]
+    L.dpr_consistency_filter.restype = c_i32
     _lib = L
     return L
 

@@ -395,6 +395,31 @@ HyScratch hy_scratch(uint8_t *w, const HyLayout &h) {
     return s;
 }
 
+// Camera / mask table of the consistency check; 0 or an error code.
+int hull_table(int32_t n_cams, const dpr_camera *cams, const dpr_mask *masks, std::vector<HullCam> &out) {
+    if (n_cams < 1 || n_cams > kHullMaxCams) return fail(DPR_ERR_INVALID_ARG, "n_cams must be in [1, %d]", kHullMaxCams);
+    if (!cams || !masks) return fail(DPR_ERR_INVALID_ARG, "cams or masks is NULL");
+    out.resize((size_t)n_cams);
+    for (int32_t i = 0; i < n_cams; ++i) {
+        const dpr_camera &c = cams[i];
+        if (c.width < 1 || c.width > kLimitDim || c.height < 1 || c.height > kLimitDim)
+            return fail(DPR_ERR_INVALID_ARG, "camera %d: width/height must be in [1, %d]", i, kLimitDim);
+        if (!(c.fx > 0.f) || !(c.fy > 0.f) || !std::isfinite(c.fx) || !std::isfinite(c.fy))
+            return fail(DPR_ERR_INVALID_ARG, "camera %d: fx, fy must be finite and > 0", i);
+        if (!masks[i].data) return fail(DPR_ERR_INVALID_ARG, "mask %d is NULL", i);
+        if (masks[i].width != c.width || masks[i].height != c.height)
+            return fail(DPR_ERR_INVALID_ARG, "mask %d is %dx%d, its camera's image %dx%d", i, masks[i].width,
+                        masks[i].height, c.width, c.height);
+        HullCam &h = out[(size_t)i];
+        memcpy(h.R, c.R, sizeof(h.R));
+        memcpy(h.t, c.t, sizeof(h.t));
+        h.fx = c.fx; h.fy = c.fy; h.cx = c.cx; h.cy = c.cy;
+        h.width = c.width; h.height = c.height;
+        h.mask = masks[i].data;
+    }
+    return DPR_OK;
+}
+
 int check_hybrid_args(int64_t n, int32_t sh_degree, int32_t K) {
     if (n < 1 || n > (int64_t)0x7FFFFFFF) return fail(DPR_ERR_INVALID_ARG, "point count must be in [1, 2^31 - 1]");
     if (sh_degree < 0 || sh_degree > 3) return fail(DPR_ERR_INVALID_ARG, "sh_degree must be in [0, 3]");
@@ -929,6 +954,98 @@ int dpr_hybrid_update(int64_t n, int32_t sh_degree, const float *xyz, const floa
     out_counts[0] = (int64_t)m;
     out_counts[1] = (int64_t)kept;
     out_counts[2] = (int64_t)count;
+    return DPR_OK;
+}
+
+size_t dpr_hull_ws_bytes(int64_t n, int32_t n_cams) {
+    if (n < 0 || n > (int64_t)0x7FFFFFFF || n_cams < 1 || n_cams > kHullMaxCams) return 0;
+    return (size_t)hull_layout((uint64_t)n, n_cams).bytes;
+}
+
+int dpr_hull_sample(int32_t n_cams, const dpr_camera *cams, const dpr_mask *masks, const float *lo, const float *hi,
+                    uint64_t seed, int64_t n, float *out_xyz, int64_t capacity, int64_t *out_count, void *ws,
+                    size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(DPR_ERR_INVALID_ARG, "n must be in [0, 2^31 - 1]");
+    if (capacity < 0) return fail(DPR_ERR_INVALID_ARG, "capacity must be >= 0");
+    if (!lo || !hi || !out_count || (capacity > 0 && !out_xyz)) return fail(DPR_ERR_INVALID_ARG, "NULL argument");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]) || !(lo[d] < hi[d]))
+            return fail(DPR_ERR_INVALID_ARG, "the box needs finite lo < hi on every axis");
+    std::vector<HullCam> tab;
+    int rc = hull_table(n_cams, cams, masks, tab);
+    if (rc) return rc;
+    const HullLayout L = hull_layout((uint64_t)n, n_cams);
+    if (!ws || ws_bytes < L.bytes) return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)L.bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    HullJob job = {};
+    job.n_cams = n_cams;
+    job.cams = tab.data();
+    job.n = (uint64_t)n;
+    job.seed = seed;
+    for (int d = 0; d < 3; ++d) { job.lo[d] = lo[d]; job.hi[d] = hi[d]; }
+    job.out_xyz = out_xyz;
+    job.capacity = (uint64_t)capacity;
+    job.sync = true;
+    uint64_t kept = 0;
+    HIP_TRY(launch_hull(job, static_cast<uint8_t *>(ws), &kept, static_cast<hipStream_t>(stream)));
+    *out_count = (int64_t)kept;
+    return DPR_OK;
+}
+
+int dpr_consistency(int64_t n, const float *xyz, int32_t n_cams, const dpr_camera *cams, const dpr_mask *masks,
+                    uint8_t *keep, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(DPR_ERR_INVALID_ARG, "n must be in [0, 2^31 - 1]");
+    if (n > 0 && (!xyz || !keep)) return fail(DPR_ERR_INVALID_ARG, "xyz or keep is NULL");
+    std::vector<HullCam> tab;
+    int rc = hull_table(n_cams, cams, masks, tab);
+    if (rc) return rc;
+    const HullLayout L = hull_layout((uint64_t)n, n_cams);
+    if (!ws || ws_bytes < L.bytes) return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)L.bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    HullJob job = {};
+    job.n_cams = n_cams;
+    job.cams = tab.data();
+    job.n = (uint64_t)n;
+    job.xyz = xyz;
+    job.keep = keep;
+    job.sync = false;
+    uint64_t kept = 0;
+    HIP_TRY(launch_hull(job, static_cast<uint8_t *>(ws), &kept, static_cast<hipStream_t>(stream)));
+    return DPR_OK;
+}
+
+int dpr_consistency_filter(int64_t n, int32_t sh_degree, const float *xyz, const float *sh, const float *opacity,
+                           const float *radius, int32_t n_cams, const dpr_camera *cams, const dpr_mask *masks,
+                           float *out_xyz, float *out_sh, float *out_opacity, float *out_radius, int64_t *out_count,
+                           void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(DPR_ERR_INVALID_ARG, "n must be in [0, 2^31 - 1]");
+    if (sh_degree < 0 || sh_degree > 3) return fail(DPR_ERR_INVALID_ARG, "sh_degree must be in [0, 3]");
+    if (!out_count || (n > 0 && (!xyz || !sh || !opacity || !radius || !out_xyz || !out_sh || !out_opacity ||
+                                 !out_radius)))
+        return fail(DPR_ERR_INVALID_ARG, "NULL array");
+    std::vector<HullCam> tab;
+    int rc = hull_table(n_cams, cams, masks, tab);
+    if (rc) return rc;
+    const HullLayout L = hull_layout((uint64_t)n, n_cams);
+    if (!ws || ws_bytes < L.bytes) return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)L.bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    HullJob job = {};
+    job.n_cams = n_cams;
+    job.cams = tab.data();
+    job.n = (uint64_t)n;
+    job.xyz = xyz;
+    job.out_xyz = out_xyz;
+    job.capacity = (uint64_t)n;
+    job.sh = sh; job.opacity = opacity; job.radius = radius;
+    job.out_sh = out_sh; job.out_opacity = out_opacity; job.out_radius = out_radius;
+    job.k3 = 3 * (sh_degree + 1) * (sh_degree + 1);
+    job.sync = true;
+    uint64_t kept = 0;
+    HIP_TRY(launch_hull(job, static_cast<uint8_t *>(ws), &kept, static_cast<hipStream_t>(stream)));
+    *out_count = (int64_t)kept;
     return DPR_OK;
 }
 

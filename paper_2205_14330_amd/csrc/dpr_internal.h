@@ -275,6 +275,35 @@ hipError_t launch_filter_generate(const float *xyz, const float *sh, const float
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t st);
 
+// Visual hull / consistency check (hull.hip).
+constexpr int32_t kHullMaxCams = 4096;
+struct HullCam {                 // 80 bytes, one per camera, in the workspace
+    float R[9], t[3], fx, fy, cx, cy;
+    int32_t width, height;
+    const uint8_t *mask;         // device, width x height, foreground where non-zero
+};
+struct HullLayout {
+    uint64_t cams, bits, counts, offsets, part, total, bytes;
+};
+struct HullJob {
+    int32_t n_cams;
+    const HullCam *cams;         // host table (uploaded into the workspace)
+    uint64_t n;                  // candidates (sampling) or points (filter)
+    const float *xyz;            // filter: points; sampling: null
+    uint64_t seed;
+    float lo[3], hi[3];
+    uint8_t *keep;               // optional: CC per item
+    float *out_xyz;              // optional: kept items (first `capacity`)
+    uint64_t capacity;
+    const float *sh, *opacity, *radius;       // filter: the other parameters
+    float *out_sh, *out_opacity, *out_radius;
+    int k3;
+    bool sync;                   // wait for the kept count
+};
+uint64_t hull_blocks(uint64_t n);
+HullLayout hull_layout(uint64_t n, int32_t n_cams);
+hipError_t launch_hull(const HullJob &job, uint8_t *ws, uint64_t *kept_host, hipStream_t st);
+
 // Eq. (8) loss over a batch of images (loss.hip).
 struct LossImage {
     const float *render, *target;

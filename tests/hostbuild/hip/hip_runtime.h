@@ -1,11 +1,11 @@
 // Host stand-in for the part of the HIP runtime and device library that the
-// hybrid-update kernels use, so that those kernels compile with g++ and run on
+// hybrid-update and visual-hull kernels use, so that those kernels compile with g++ and run on
 // CPU threads under AddressSanitizer.  Test infrastructure only: it checks the
 // kernels' indexing and host sequencing, not GPU code generation.
 //
 // Execution model: the blocks of a launch run one after another; the threads
-// of a block run concurrently on a pool of host threads, so __syncthreads and
-// 64-lane __shfl_xor are real barriers.  __shared__ variables are function
+// of a block run concurrently on a pool of host threads, so __syncthreads,
+// 64-lane __shfl_xor and __ballot are real barriers.  __shared__ variables are function
 // statics, which is block-shared memory when one block runs at a time.
 #pragma once
 
@@ -131,7 +131,9 @@ class Pool {
                 threadIdx.x = t;
                 blockIdx.x = block_;
                 (*body_)();
-                // an exited thread no longer takes part in barriers
+                // an exited thread no longer takes part in barriers, and a
+                // ballot reads its predicate as 0
+                blk_.slot[t] = 0;
                 blk_.wave[t / 64]->arrive_and_drop();
                 blk_.bar->arrive_and_drop();
             }
@@ -178,6 +180,24 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
     std::memcpy(&r, &o, sizeof(T));
     return r;
 }
+
+// 64-lane ballot: bit l of the result is lane l's predicate (lanes of the
+// wave that have exited count as 0).
+inline uint64_t __ballot(int pred) {
+    hostrt::Block &b = hostrt::pool().block();
+    const uint32_t t = threadIdx.x, w0 = t & ~63u;
+    b.slot[t] = pred ? 1u : 0u;
+    b.wave[t / 64]->arrive_and_wait();
+    uint64_t m = 0;
+    for (uint32_t l = 0; l < 64 && w0 + l < blockDim.x; ++l)
+        if (b.slot[w0 + l] == 1u) m |= 1ull << l;
+    b.wave[t / 64]->arrive_and_wait();
+    return m;
+}
+
+inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
+inline int __popc(uint32_t x) { return __builtin_popcount(x); }
+inline int __popcll(uint64_t x) { return __builtin_popcountll(x); }
 
 #define hipLaunchKernelGGL(kernel, grid, block, shmem, stream, ...) \
     hostrt::launch(kernel, dim3(grid), dim3(block), __VA_ARGS__)

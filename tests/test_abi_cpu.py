@@ -274,3 +274,60 @@ def test_loss_invalid_arguments_rejected(abi, case, expect):
     rc = lib.dpr_loss_l2_tv(1, P([r or 0]), P([t]), W, H, lam, P([g]), loss, ws, nb, None)
     assert rc == expect, lib.dpr_last_error().decode()
     assert lib.dpr_last_error().decode()
+
+
+def test_hull_workspace_sizes(abi):
+    lib = abi.load()
+    assert lib.dpr_hull_ws_bytes(0, 1) > 0
+    assert lib.dpr_hull_ws_bytes(5000, 16) >= 80 * 16 + 4 * 32 * 5
+    assert lib.dpr_hull_ws_bytes(-1, 1) == 0
+    assert lib.dpr_hull_ws_bytes(10, 0) == 0
+    assert lib.dpr_hull_ws_bytes(10, 5000) == 0
+
+
+@pytest.mark.parametrize("case,expect", [("n_cams", 1), ("mask_size", 1), ("null_mask", 1), ("box", 1), ("nan_box", 1),
+                                         ("capacity", 1), ("null_out", 1), ("workspace", 2), ("camera", 1),
+                                         ("n", 1)])
+def test_hull_invalid_arguments_rejected(abi, case, expect):
+    """Every check of the consistency-check entry points runs on the host
+    before anything is launched."""
+    lib = abi.load()
+    cam = abi.Camera()
+    cam.R[:] = [1, 0, 0, 0, 1, 0, 0, 0, 1]
+    cam.t[:] = [0, 0, 3]
+    cam.fx = cam.fy = 50.0
+    cam.cx = cam.cy = 16.0
+    cam.width = cam.height = 32
+    cams = (abi.Camera * 2)(cam, cam)
+    masks = (abi.Mask * 2)(abi.Mask(FAKE, 32, 32), abi.Mask(FAKE + 4096, 32, 32))
+    lo = (ctypes.c_float * 3)(-1, -1, -1)
+    hi = (ctypes.c_float * 3)(1, 1, 1)
+    n_cams, n, cap, out, ws, nb = 2, 100, 100, FAKE + 8192, FAKE + 16384, 1 << 30
+    if case == "n_cams":
+        n_cams = 0
+    elif case == "mask_size":
+        masks[1].width = 31
+    elif case == "null_mask":
+        masks[0].data = None
+    elif case == "box":
+        hi[1] = -1.0
+    elif case == "nan_box":
+        lo[2] = float("nan")
+    elif case == "capacity":
+        cap = -1
+    elif case == "null_out":
+        out = None
+    elif case == "workspace":
+        nb = 64
+    elif case == "camera":
+        cams[1].fx = 0.0
+    elif case == "n":
+        n = -5
+    cnt = ctypes.c_int64(0)
+    rc = lib.dpr_hull_sample(n_cams, cams, masks, lo, hi, 1, n, out, cap, ctypes.byref(cnt), ws, nb, None)
+    assert rc == expect, lib.dpr_last_error()
+    assert lib.dpr_last_error()
+    if case in ("n_cams", "mask_size", "null_mask", "workspace", "camera"):
+        keep = FAKE + 32768
+        rc2 = lib.dpr_consistency(100, FAKE, n_cams, cams, masks, keep, ws, nb, None)
+        assert rc2 == expect

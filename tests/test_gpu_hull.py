@@ -1,0 +1,127 @@
+"""GPU parity of the visual-hull initialisation and the consistency filter
+(Sec. 3.1 initialisation, the appendix's consistency check CC), through the C
+ABI, against the oracle.  Every decision is taken in float32 with the same
+operations on both sides and the candidates come from the same counter-based
+generator, so results must agree bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hull():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_14330_amd as d
+    d.load()
+    from paper_2205_14330_amd import hull as h
+    return h
+
+
+def _dev_masks(masks):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(m, np.uint8)).cuda() for m in masks]
+
+
+def _noisy_masks(cams, seed, frac=0.8):
+    rng = np.random.default_rng(seed)
+    return [(rng.random((c.height, c.width)) < frac).astype(np.uint8) for c in cams]
+
+
+LO, HI = [-1.0, -1.0, -1.0], [1.0, 1.0, 1.0]
+
+
+@pytest.mark.parametrize("n,capacity", [(5000, None), (5000, 7), (5000, 0), (1, None), (0, None), (1024, None)])
+def test_sample_matches_oracle(hull, n, capacity):
+    cams = workloads.disc_views(8, size=72)
+    masks = workloads.sphere_masks(cams, 0.6)
+    cap = n if capacity is None else capacity
+    got, kept = hull.hull_sample(cams, _dev_masks(masks), LO, HI, 12345, n, capacity=cap)
+    rk, ref = oracle.hull_sample(cams, masks, LO, HI, 12345, n, capacity=cap)
+    assert kept == rk
+    assert np.array_equal(got.cpu().numpy(), ref)
+
+
+def test_sample_mixed_sizes_and_noisy_masks(hull):
+    cams = workloads.disc_views(3, size=64) + workloads.disc_views(2, size=40, seed=1)
+    masks = _noisy_masks(cams, 3, 0.9)
+    seed = (7 << 40) | 99
+    got, kept = hull.hull_sample(cams, _dev_masks(masks), LO, HI, seed, 20000)
+    rk, ref = oracle.hull_sample(cams, masks, LO, HI, seed, 20000)
+    assert kept == rk > 0
+    assert np.array_equal(got.cpu().numpy(), ref)
+
+
+def test_sample_large_many_cameras(hull):
+    """2^22 candidates, 16 views of 400x400 (4096 blocks, the full launch shape
+    of a bench-sized call)."""
+    cams = workloads.disc_views(16, size=400, seed=4)
+    masks = workloads.sphere_masks(cams, 0.55)
+    n = 1 << 22
+    got, kept = hull.hull_sample(cams, _dev_masks(masks), LO, HI, 2024, n)
+    rk, ref = oracle.hull_sample(cams, masks, LO, HI, 2024, n)
+    assert kept == rk
+    assert np.array_equal(got.cpu().numpy(), ref)
+
+
+def test_consistency_matches_oracle(hull):
+    import torch
+    cams = workloads.disc_views(6, size=64, seed=2)
+    masks = workloads.sphere_masks(cams, 0.7)
+    rng = np.random.default_rng(5)
+    xyz = rng.uniform(-4, 4, (3001, 3)).astype(np.float32)
+    xyz[:1000] = rng.uniform(-0.8, 0.8, (1000, 3))
+    keep = hull.consistency(torch.from_numpy(xyz).cuda(), cams, _dev_masks(masks))
+    assert np.array_equal(keep.cpu().numpy().astype(bool), oracle.hull_consistent(xyz, cams, masks))
+
+
+def test_empty_mask_rejects_all(hull):
+    import torch
+    cams = workloads.disc_views(3, size=48)
+    masks = workloads.sphere_masks(cams, 0.7)
+    masks[1][:] = 0
+    xyz = np.random.default_rng(6).uniform(-0.5, 0.5, (700, 3)).astype(np.float32)
+    keep = hull.consistency(torch.from_numpy(xyz).cuda(), cams, _dev_masks(masks))
+    assert not keep.cpu().numpy().any()
+    _, kept = hull.hull_sample(cams, _dev_masks(masks), LO, HI, 1, 4000)
+    assert kept == 0
+
+
+@pytest.mark.parametrize("n", [2500, 1, 1023, 1025])
+def test_filter_matches_oracle(hull, n):
+    import torch
+    from paper_2205_14330_amd import SceneTensors
+    cams = workloads.disc_views(5, size=64)
+    masks = workloads.sphere_masks(cams, 0.6)
+    rng = np.random.default_rng(n)
+    xyz = rng.uniform(-1, 1, (n, 3)).astype(np.float32)
+    cloud = oracle.Cloud(xyz, *workloads.point_attributes(n, 2, 4))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    got = hull.consistency_filter(SceneTensors(t(cloud.xyz), t(cloud.sh), t(cloud.opacity), t(cloud.radius)), cams,
+                                  _dev_masks(masks))
+    keep, ref = oracle.consistency_filter(cloud, cams, masks)
+    assert got.n == int(keep.sum())
+    for g, r in zip((got.xyz, got.sh, got.opacity, got.radius), (ref.xyz, ref.sh, ref.opacity, ref.radius)):
+        assert np.array_equal(g.cpu().numpy(), r)
+
+
+def test_filter_with_render_masks(hull):
+    """Masks from renders of a synthetic scene (foreground where the oracle's
+    transmittance is below 0.5), then the consistency filter of that scene's
+    own points: the points of the rendered object are mostly kept."""
+    import torch
+    from paper_2205_14330_amd import SceneTensors
+    sc = workloads.small_scene(31, 3000)
+    cams = workloads.disc_views(4, size=56, seed=8)
+    masks = [(oracle.render(sc, c).trans < 0.5).astype(np.uint8) for c in cams]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    got = hull.consistency_filter(SceneTensors(t(sc.xyz), t(sc.sh), t(sc.opacity), t(sc.radius)), cams,
+                                  _dev_masks(masks))
+    keep, ref = oracle.consistency_filter(oracle.Cloud(sc.xyz, sc.sh, sc.opacity, sc.radius), cams, masks)
+    assert got.n == int(keep.sum()) > 0
+    assert np.array_equal(got.xyz.cpu().numpy(), ref.xyz)

@@ -12,41 +12,22 @@ This checks the kernels' indexing, the scratch sizes and the float32 decision
 arithmetic on the CPU; the GPU's own code generation is checked by the GPU
 parity tests of the same cases."""
 import os
-import shutil
-import subprocess
 
 import numpy as np
 import pytest
 
 import oracle
 import workloads
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HOSTBUILD = os.path.join(ROOT, "tests", "hostbuild")
+from _hostbuild import compile_harness, run
 
 
 @pytest.fixture(scope="module")
 def exe(tmp_path_factory):
-    gxx = shutil.which("g++")
-    if gxx is None:
-        pytest.skip("g++ not available")
-    out = str(tmp_path_factory.mktemp("hostbuild") / "hybrid_host")
-    cmd = [gxx, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-           "-fno-omit-frame-pointer", "-ffp-contract=off", "-pthread", "-I", HOSTBUILD,
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2205_14330_amd", "csrc"),
-           "-x", "c++", os.path.join(HOSTBUILD, "hybrid_host.cpp"), "-o", out]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    assert r.returncode == 0, r.stderr[-4000:]
-    return out
+    return compile_harness("hybrid_host", tmp_path_factory.mktemp("hostbuild"))
 
 
 def _run(exe, d, mode, arrays, *args):
-    for name, a in arrays.items():
-        np.ascontiguousarray(a, np.float32).tofile(os.path.join(d, name + ".bin"))
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1")
-    r = subprocess.run([exe, mode, str(d)] + [str(a) for a in args], capture_output=True, text=True, env=env,
-                       timeout=300)
-    assert r.returncode == 0, r.stderr[-4000:]
+    run(exe, d, mode, {k: np.asarray(v, np.float32) for k, v in arrays.items()}, *args)
 
 
 def _cloud(xyz, seed):
