@@ -88,7 +88,7 @@ def main():
                     help="time only the forward + backward metric (skip the forward-only and recompute legs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (reference for HBM counters)")
-    ap.add_argument("--workload", choices=["train", "paper", "dynamic", "serve"], default="train",
+    ap.add_argument("--workload", choices=["train", "paper", "dynamic", "serve", "hull"], default="train",
                     help="train: the default step; paper: the same step with the paper-literal renderer "
                          "(n = 15 splats per pixel, normalised Eq. 5) and the L2 + 0.01 TV loss")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -111,6 +111,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "dynamic":
         return bench_dynamic(args)
+    if args.workload == "hull":
+        return bench_hull(args)
     if args.workload == "serve":
         out = {"metric": "served p50/p99 latency and Mpix/s (16 resident scenes, Poisson requests)",
                "n_gpus": 1, "dtype": "f32", "data": "synthetic"}
@@ -332,6 +334,87 @@ def main():
         "roofline": roof, "loss_kernel": loss_kernel, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+HULL_OPS_PER_CANDIDATE = 90      # Philox4x32-10 and the box mapping, lane-ops
+HULL_OPS_PER_TEST = 40           # one projection into a mask (two divisions) and the lookup, lane-ops
+
+
+def bench_hull(args):
+    """Visual-hull initialisation: 16 views of 800x800 of the 100k-point ball
+    scene, masks where a render's transmittance is below 0.5 (untimed setup),
+    rejection sampling of 2^24 candidates in [-1.2, 1.2]^3 per call; also the
+    consistency predicate alone and the filter of the scene's own points."""
+    import torch
+    import workloads
+    import paper_2205_14330_amd as dpr
+    from paper_2205_14330_amd import hull
+    scene_np, _, _, _ = workloads.ball100k_8x400()
+    rng = workloads.seed_rng(7)
+    cams = [workloads.random_sphere_camera(rng, 800, 800) for _ in range(16)]
+    scene = dpr.SceneTensors.from_numpy(scene_np)
+    plan = dpr.Plan([scene], [(0, c) for c in cams], dpr.RenderParams(bwd_mode="recompute"))
+    plan.forward()
+    masks = [(t < 0.5).to(torch.uint8).contiguous() for t in plan.trans]
+    plan.free()
+    lo, hi, n = [-1.2] * 3, [1.2] * 3, 1 << 24
+    K, W = args.steps, args.warmup
+    for k in range(W):
+        hull.hull_sample(cams, masks, lo, hi, k, n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kept = 0
+    for k in range(K):
+        _, c = hull.hull_sample(cams, masks, lo, hi, W + k, n)
+        kept += c
+    torch.cuda.synchronize()
+    t_call = (time.perf_counter() - t0) / K
+    # the predicate alone on the candidates of one call, HIP events on the stream
+    xyz = (torch.rand((n, 3), device="cuda", generator=torch.Generator(device="cuda").manual_seed(3)) * 2.4
+           - 1.2).contiguous()
+    for _ in range(W):
+        hull.consistency(xyz, cams, masks)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        hull.consistency(xyz, cams, masks)
+    e1.record()
+    torch.cuda.synchronize()
+    t_pred = e0.elapsed_time(e1) / K / 1e3
+    # camera tests per candidate: item i is tested against camera c while it
+    # is inside cameras 0 .. c-1 (survival fractions of camera prefixes)
+    tests = 0.0
+    for c in range(len(cams)):
+        tests += 1.0 if c == 0 else float(hull.consistency(xyz, cams[:c], masks[:c]).float().mean())
+    ops = n * (HULL_OPS_PER_CANDIDATE + HULL_OPS_PER_TEST * tests)
+    achieved = ops / t_pred / 1e12
+    # the filter of the scene's own points
+    for _ in range(W):
+        hull.consistency_filter(scene, cams, masks)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        out = hull.consistency_filter(scene, cams, masks)
+    torch.cuda.synchronize()
+    t_filt = (time.perf_counter() - t0) / K
+    log(f"hull: sample {n} candidates {t_call * 1e3:.3f} ms/call ({n / t_call / 1e9:.2f} G/s, kept {kept / K:.0f}); "
+        f"predicate {t_pred * 1e3:.3f} ms ({tests:.2f} tests per candidate); filter {scene.n} points "
+        f"{t_filt * 1e3:.3f} ms, kept {out.n}")
+    print(json.dumps({
+        "metric": "visual-hull rejection sampling, candidates per second (16 masks of 800x800)",
+        "value": round(n / t_call / 1e9, 3), "unit": "Gcandidates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(t_call * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "2^24 Philox candidates in [-1.2, 1.2]^3, 16 views of 800x800 of a 100k-point ball "
+                               "scene, masks = rendered transmittance < 0.5", "candidates": n, "cameras": 16},
+        "kept_per_call": kept / K, "camera_tests_per_candidate": round(tests, 3),
+        "predicate_ms": round(t_pred * 1e3, 4), "filter_ms": round(t_filt * 1e3, 4), "filter_points": scene.n,
+        "roofline": {"kernel": "hull_flags (+ upload, scan)", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
+                     "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": None,
+                     "per_unit": f"{HULL_OPS_PER_CANDIDATE} lane-ops per candidate + {HULL_OPS_PER_TEST} per camera "
+                                 "test", "units_per_launch": n},
+    }), flush=True)
 
 
 def bench_dynamic(args):

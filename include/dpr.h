@@ -321,9 +321,10 @@ typedef struct dpr_mask {
     int32_t width, height;
 } dpr_mask;
 
-/* Bytes of the device workspace for n candidates or points and n_cams cameras
- * (0 on bad sizes). */
-size_t dpr_hull_ws_bytes(int64_t n, int32_t n_cams);
+/* Bytes of the device workspace for n candidates or points and the n_cams
+ * cameras cams (their image sizes; 0 on bad sizes).  The workspace holds the
+ * masks packed to one bit per pixel. */
+size_t dpr_hull_ws_bytes(int64_t n, int32_t n_cams, const dpr_camera *cams);
 
 /* Rejection sampling of n candidates (0 <= n < 2^31) in the box [lo, hi] (host
  * float[3] each, lo < hi): the consistent ones, in candidate order, are written

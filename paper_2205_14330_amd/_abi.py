@@ -110,7 +110,7 @@ def load(path: str = LIB_PATH):
     L.dpr_hybrid_update.argtypes = [c_i64, c_i32, c_p, c_p, c_p, c_p, c_i32, c_i32, c_f, c_p, c_p, c_p, c_p, I64P,
                                     c_p, c_sz, c_p]
     L.dpr_hybrid_update.restype = c_i32
-    L.dpr_hull_ws_bytes.argtypes, L.dpr_hull_ws_bytes.restype = [c_i64, c_i32], c_sz
+    L.dpr_hull_ws_bytes.argtypes, L.dpr_hull_ws_bytes.restype = [c_i64, c_i32, c_p], c_sz
     L.dpr_hull_sample.argtypes = [c_i32, c_p, c_p, c_p, c_p, ctypes.c_uint64, c_i64, c_p, c_i64, I64P, c_p, c_sz, c_p]
     L.dpr_hull_sample.restype = c_i32
     L.dpr_consistency.argtypes = [c_i64, c_p, c_i32, c_p, c_p, c_p, c_p, c_sz, c_p]

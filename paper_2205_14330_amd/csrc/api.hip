@@ -957,9 +957,16 @@ int dpr_hybrid_update(int64_t n, int32_t sh_degree, const float *xyz, const floa
     return DPR_OK;
 }
 
-size_t dpr_hull_ws_bytes(int64_t n, int32_t n_cams) {
-    if (n < 0 || n > (int64_t)0x7FFFFFFF || n_cams < 1 || n_cams > kHullMaxCams) return 0;
-    return (size_t)hull_layout((uint64_t)n, n_cams).bytes;
+size_t dpr_hull_ws_bytes(int64_t n, int32_t n_cams, const dpr_camera *cams) {
+    if (n < 0 || n > (int64_t)0x7FFFFFFF || n_cams < 1 || n_cams > kHullMaxCams || !cams) return 0;
+    std::vector<HullCam> tab((size_t)n_cams);
+    for (int32_t i = 0; i < n_cams; ++i) {
+        if (cams[i].width < 1 || cams[i].width > kLimitDim || cams[i].height < 1 || cams[i].height > kLimitDim)
+            return 0;
+        tab[(size_t)i].width = cams[i].width;
+        tab[(size_t)i].height = cams[i].height;
+    }
+    return (size_t)hull_layout((uint64_t)n, n_cams, tab.data()).bytes;
 }
 
 int dpr_hull_sample(int32_t n_cams, const dpr_camera *cams, const dpr_mask *masks, const float *lo, const float *hi,
@@ -975,7 +982,7 @@ int dpr_hull_sample(int32_t n_cams, const dpr_camera *cams, const dpr_mask *mask
     std::vector<HullCam> tab;
     int rc = hull_table(n_cams, cams, masks, tab);
     if (rc) return rc;
-    const HullLayout L = hull_layout((uint64_t)n, n_cams);
+    const HullLayout L = hull_layout((uint64_t)n, n_cams, tab.data());
     if (!ws || ws_bytes < L.bytes) return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)L.bytes);
     if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
     HullJob job = {};
@@ -1001,7 +1008,7 @@ int dpr_consistency(int64_t n, const float *xyz, int32_t n_cams, const dpr_camer
     std::vector<HullCam> tab;
     int rc = hull_table(n_cams, cams, masks, tab);
     if (rc) return rc;
-    const HullLayout L = hull_layout((uint64_t)n, n_cams);
+    const HullLayout L = hull_layout((uint64_t)n, n_cams, tab.data());
     if (!ws || ws_bytes < L.bytes) return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)L.bytes);
     if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
     HullJob job = {};
@@ -1029,7 +1036,7 @@ int dpr_consistency_filter(int64_t n, int32_t sh_degree, const float *xyz, const
     std::vector<HullCam> tab;
     int rc = hull_table(n_cams, cams, masks, tab);
     if (rc) return rc;
-    const HullLayout L = hull_layout((uint64_t)n, n_cams);
+    const HullLayout L = hull_layout((uint64_t)n, n_cams, tab.data());
     if (!ws || ws_bytes < L.bytes) return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)L.bytes);
     if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
     HullJob job = {};

@@ -277,13 +277,16 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t 
 
 // Visual hull / consistency check (hull.hip).
 constexpr int32_t kHullMaxCams = 4096;
-struct HullCam {                 // 80 bytes, one per camera, in the workspace
+struct HullCam {                 // 96 bytes, one per camera, in the workspace
     float R[9], t[3], fx, fy, cx, cy;
     int32_t width, height;
     const uint8_t *mask;         // device, width x height, foreground where non-zero
+    const uint32_t *bits;        // the mask packed one bit per pixel (row-major), in the workspace
+    uint64_t word_off;           // first packed word of this camera
 };
 struct HullLayout {
-    uint64_t cams, bits, counts, offsets, part, total, bytes;
+    uint64_t cams, packed, bits, counts, offsets, part, total, bytes;
+    uint64_t words;              // packed mask words over all cameras
 };
 struct HullJob {
     int32_t n_cams;
@@ -301,7 +304,8 @@ struct HullJob {
     bool sync;                   // wait for the kept count
 };
 uint64_t hull_blocks(uint64_t n);
-HullLayout hull_layout(uint64_t n, int32_t n_cams);
+// cams: host table (width, height used)
+HullLayout hull_layout(uint64_t n, int32_t n_cams, const HullCam *cams);
 hipError_t launch_hull(const HullJob &job, uint8_t *ws, uint64_t *kept_host, hipStream_t st);
 
 // Eq. (8) loss over a batch of images (loss.hip).

@@ -9,6 +9,9 @@
 // The pixel decision is taken in float32 with the operations documented in
 // include/dpr.h, each rounded once, so it is reproducible bit for bit.
 //
+// The masks are first packed to one bit per pixel in the workspace (sixteen
+// 800x800 masks take 1.25 MB instead of 10 MB, so every XCD's L2 holds them
+// all: the lookups of random candidates are L2 hits).
 // Two passes over blocks of 1024 items (4 per thread): the first decides CC
 // (the 4 items of a thread walk the cameras together so that 4 mask gathers
 // are in flight; a wave leaves the camera loop once none of its items is still
@@ -17,6 +20,8 @@
 // items at offset + rank (popcounts of the bits before them), which keeps the
 // input order.  Camera and mask descriptors sit in one table in the
 // workspace and are read through uniform (scalar) loads.
+#include <vector>
+
 #include "dpr_internal.h"
 
 #pragma clang fp contract(off)
@@ -88,7 +93,27 @@ __device__ __forceinline__ bool inside(const HullCam &c, const float p[3]) {
     const float px = fmaf(c.fx, X[0] / X[2], c.cx);
     const float py = fmaf(c.fy, X[1] / X[2], c.cy);
     if (!(px >= 0.f && px < (float)c.width && py >= 0.f && py < (float)c.height)) return false;
-    return c.mask[(int64_t)(int32_t)py * c.width + (int32_t)px] != 0;
+    const uint64_t idx = (uint64_t)(int32_t)py * (uint32_t)c.width + (uint32_t)(int32_t)px;
+    return (c.bits[idx >> 5] >> (idx & 31u)) & 1u;
+}
+
+// Packed word w of all cameras: bit b = 1 iff mask byte 32 w' + b != 0 (w' the
+// word within its camera, bytes past the mask read as 0).
+__global__ __launch_bounds__(kHullThreads) void k_pack_masks(const HullCam *cams, int32_t n_cams, uint64_t words,
+                                                             uint32_t *packed) {
+    const uint64_t w = (uint64_t)blockIdx.x * kHullThreads + threadIdx.x;
+    if (w >= words) return;
+    int32_t lo = 0, hi = n_cams - 1;                // last camera with word_off <= w
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (cams[mid].word_off <= w) lo = mid; else hi = mid - 1;
+    }
+    const HullCam &c = cams[lo];
+    const uint64_t npix = (uint64_t)c.width * (uint32_t)c.height;
+    const uint64_t p0 = (w - c.word_off) * 32;
+    uint32_t v = 0;
+    for (uint32_t b = 0; b < 32 && p0 + b < npix; ++b) v |= (c.mask[p0 + b] != 0 ? 1u : 0u) << b;
+    packed[w] = v;
 }
 
 __global__ __launch_bounds__(kHullThreads) void k_hull_flags(HullArgs a) {
@@ -183,9 +208,11 @@ __global__ __launch_bounds__(kHullThreads) void k_hull_scatter(HullArgs a, HullO
     }
 }
 
-HullLayout hull_layout(uint64_t n, int32_t n_cams) {
+HullLayout hull_layout(uint64_t n, int32_t n_cams, const HullCam *cams) {
     const uint64_t nb = hull_blocks(n);
     HullLayout h;
+    h.words = 0;
+    for (int32_t i = 0; i < n_cams; ++i) h.words += ((uint64_t)cams[i].width * (uint32_t)cams[i].height + 31) / 32;
     uint64_t off = 0;
     auto add = [&](uint64_t bytes) {
         const uint64_t at = off;
@@ -193,6 +220,7 @@ HullLayout hull_layout(uint64_t n, int32_t n_cams) {
         return at;
     };
     h.cams = add(sizeof(HullCam) * (uint64_t)n_cams);
+    h.packed = add(4 * h.words);
     h.bits = add(4 * kHullWords * nb);
     h.counts = add(4 * (nb + 1));
     h.offsets = add(4 * (nb + 1));                 // the scan also writes the total after the last entry
@@ -203,8 +231,17 @@ HullLayout hull_layout(uint64_t n, int32_t n_cams) {
 }
 
 hipError_t launch_hull(const HullJob &job, uint8_t *ws, uint64_t *kept_host, hipStream_t st) {
-    const HullLayout L = hull_layout(job.n, job.n_cams);
+    const HullLayout L = hull_layout(job.n, job.n_cams, job.cams);
     *kept_host = 0;
+    // the table with each camera's packed words
+    std::vector<HullCam> tab(job.cams, job.cams + job.n_cams);
+    uint32_t *packed = reinterpret_cast<uint32_t *>(ws + L.packed);
+    uint64_t woff = 0;
+    for (HullCam &c : tab) {
+        c.word_off = woff;
+        c.bits = packed + woff;
+        woff += ((uint64_t)c.width * (uint32_t)c.height + 31) / 32;
+    }
     HullArgs a;
     a.cams = reinterpret_cast<const HullCam *>(ws + L.cams);
     a.n_cams = job.n_cams;
@@ -219,12 +256,16 @@ hipError_t launch_hull(const HullJob &job, uint8_t *ws, uint64_t *kept_host, hip
     a.bits = reinterpret_cast<uint32_t *>(ws + L.bits);
     a.counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     a.keep = job.keep;
-    hipError_t e = upload_async(ws + L.cams, job.cams, sizeof(HullCam) * (size_t)job.n_cams, st);
+    hipError_t e = upload_async(ws + L.cams, tab.data(), sizeof(HullCam) * (size_t)job.n_cams, st);
     if (e != hipSuccess || job.n == 0) return e;
+    hipLaunchKernelGGL(k_pack_masks, dim3((uint32_t)((L.words + kHullThreads - 1) / kHullThreads)),
+                       dim3(kHullThreads), 0, st, a.cams, job.n_cams, L.words, packed);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const uint64_t nb = hull_blocks(job.n);
     hipLaunchKernelGGL(k_hull_flags, dim3((uint32_t)nb), dim3(kHullThreads), 0, st, a);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || (!job.out_xyz && !job.sync)) return e;     // the predicate alone needs no scan
     uint64_t *total = reinterpret_cast<uint64_t *>(ws + L.total);
     uint32_t *offsets = reinterpret_cast<uint32_t *>(ws + L.offsets);
     e = launch_scan(a.counts, offsets, nb, reinterpret_cast<uint64_t *>(ws + L.part), total, st);

@@ -24,8 +24,8 @@ def _tables(cams: Sequence, masks: Sequence[torch.Tensor]):
     return c, mk
 
 
-def _ws(lib, n: int, n_cams: int, dev) -> torch.Tensor:
-    nbytes = lib.dpr_hull_ws_bytes(int(n), int(n_cams))
+def _ws(lib, n: int, c, dev) -> torch.Tensor:
+    nbytes = lib.dpr_hull_ws_bytes(int(n), len(c), c)
     if nbytes == 0:
         check(_abi.DPR_ERR_INVALID_ARG)
     return torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
@@ -43,7 +43,7 @@ def hull_sample(cams: Sequence, masks: Sequence[torch.Tensor], lo, hi, seed: int
     out = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
     lo_c = (ctypes.c_float * 3)(*[float(v) for v in lo])
     hi_c = (ctypes.c_float * 3)(*[float(v) for v in hi])
-    ws = _ws(lib, n, len(cams), dev)
+    ws = _ws(lib, n, c, dev)
     cnt = ctypes.c_int64(0)
     check(lib.dpr_hull_sample(len(cams), c, mk, lo_c, hi_c, int(seed), int(n), out.data_ptr(), cap,
                               ctypes.byref(cnt), ws.data_ptr(), int(ws.numel()), _stream_handle(stream)))
@@ -61,7 +61,7 @@ def consistency(xyz: torch.Tensor, cams: Sequence, masks: Sequence[torch.Tensor]
     c, mk = _tables(cams, masks)
     n = int(xyz.shape[0])
     keep = torch.empty(max(n, 1), dtype=torch.uint8, device=xyz.device)
-    ws = _ws(lib, n, len(cams), xyz.device)
+    ws = _ws(lib, n, c, xyz.device)
     check(lib.dpr_consistency(n, xyz.data_ptr(), len(cams), c, mk, keep.data_ptr(), ws.data_ptr(), int(ws.numel()),
                               _stream_handle(stream)))
     return keep[:n]
@@ -80,7 +80,7 @@ def consistency_filter(scene: SceneTensors, cams: Sequence, masks: Sequence[torc
                        torch.empty((max(n, 1),) + tuple(scene.sh.shape[1:]), dtype=torch.float32, device=dev),
                        torch.empty((max(n, 1),), dtype=torch.float32, device=dev),
                        torch.empty((max(n, 1),), dtype=torch.float32, device=dev))
-    ws = _ws(lib, n, len(cams), dev)
+    ws = _ws(lib, n, c, dev)
     cnt = ctypes.c_int64(0)
     check(lib.dpr_consistency_filter(n, scene.sh_degree, scene.xyz.data_ptr(), scene.sh.data_ptr(),
                                      scene.opacity.data_ptr(), scene.radius.data_ptr(), len(cams), c, mk,

@@ -57,14 +57,14 @@ T *poisoned(uint64_t bytes) {
 }
 
 // The workspace of hull_layout, with the padding after each region poisoned.
-uint8_t *workspace(uint64_t n, int32_t n_cams) {
-    const dpr::HullLayout L = dpr::hull_layout(n, n_cams);
+uint8_t *workspace(uint64_t n, int32_t n_cams, const dpr::HullCam *tab) {
+    const dpr::HullLayout L = dpr::hull_layout(n, n_cams, tab);
     uint8_t *w = poisoned<uint8_t>(L.bytes);
     const uint64_t nb = dpr::hull_blocks(n);
-    const uint64_t starts[] = {L.cams, L.bits, L.counts, L.offsets, L.part, L.total, L.bytes};
-    const uint64_t sizes[] = {sizeof(dpr::HullCam) * (uint64_t)n_cams, 4ull * 32 * nb, 4 * (nb + 1), 4 * (nb + 1),
-                              8 * (dpr::scan_partials(nb + 1) + 2), 8};
-    for (int r = 0; r < 6; ++r)
+    const uint64_t starts[] = {L.cams, L.packed, L.bits, L.counts, L.offsets, L.part, L.total, L.bytes};
+    const uint64_t sizes[] = {sizeof(dpr::HullCam) * (uint64_t)n_cams, 4 * L.words, 4ull * 32 * nb, 4 * (nb + 1),
+                              4 * (nb + 1), 8 * (dpr::scan_partials(nb + 1) + 2), 8};
+    for (int r = 0; r < 7; ++r)
         if (starts[r] + sizes[r] < starts[r + 1])
             ASAN_POISON_MEMORY_REGION(w + starts[r] + sizes[r], starts[r + 1] - starts[r] - sizes[r]);
     return w;
@@ -114,16 +114,16 @@ int main(int argc, char **argv) {
         job.capacity = std::strtoull(argv[5], nullptr, 10);
         for (int d = 0; d < 3; ++d) { job.lo[d] = b[d]; job.hi[d] = b[3 + d]; }
         job.out_xyz = static_cast<float *>(keep_ptr(poisoned<float>(12 * job.capacity)));
-        uint8_t *ws = workspace(job.n, n_cams);
+        uint8_t *ws = workspace(job.n, n_cams, tab.data());
         if (dpr::launch_hull(job, ws, &kept, nullptr) != hipSuccess) return 3;
         write_raw(dir + "/out_xyz.bin", job.out_xyz, 12 * std::min<uint64_t>(kept, job.capacity));
-        ASAN_UNPOISON_MEMORY_REGION(ws, dpr::hull_layout(job.n, n_cams).bytes);
+        ASAN_UNPOISON_MEMORY_REGION(ws, dpr::hull_layout(job.n, n_cams, tab.data()).bytes);
         std::free(ws);
     } else {
         const std::vector<uint8_t> xyz_b = read_bytes(dir + "/xyz.bin");
         job.n = xyz_b.size() / 12;
         job.xyz = static_cast<const float *>(keep_ptr(exact<float>(xyz_b)));
-        uint8_t *ws = workspace(job.n, n_cams);
+        uint8_t *ws = workspace(job.n, n_cams, tab.data());
         if (mode == "keep") {
             job.keep = static_cast<uint8_t *>(keep_ptr(poisoned<uint8_t>(job.n)));
             job.sync = false;
@@ -145,7 +145,7 @@ int main(int argc, char **argv) {
             write_raw(dir + "/out_op.bin", job.out_opacity, 4 * kept);
             write_raw(dir + "/out_rad.bin", job.out_radius, 4 * kept);
         }
-        ASAN_UNPOISON_MEMORY_REGION(ws, dpr::hull_layout(job.n, n_cams).bytes);
+        ASAN_UNPOISON_MEMORY_REGION(ws, dpr::hull_layout(job.n, n_cams, tab.data()).bytes);
         std::free(ws);
     }
     FILE *cf = std::fopen((dir + "/count.txt").c_str(), "w");

@@ -278,11 +278,18 @@ def test_loss_invalid_arguments_rejected(abi, case, expect):
 
 def test_hull_workspace_sizes(abi):
     lib = abi.load()
-    assert lib.dpr_hull_ws_bytes(0, 1) > 0
-    assert lib.dpr_hull_ws_bytes(5000, 16) >= 80 * 16 + 4 * 32 * 5
-    assert lib.dpr_hull_ws_bytes(-1, 1) == 0
-    assert lib.dpr_hull_ws_bytes(10, 0) == 0
-    assert lib.dpr_hull_ws_bytes(10, 5000) == 0
+    cam = abi.Camera()
+    cam.width, cam.height = 800, 600
+    cams = (abi.Camera * 16)(*([cam] * 16))
+    assert lib.dpr_hull_ws_bytes(0, 1, cams) > 0
+    # camera table, masks packed to bits, one bitmask word per 32 items
+    assert lib.dpr_hull_ws_bytes(5000, 16, cams) >= 96 * 16 + 16 * 800 * 600 // 8 + 4 * 32 * 5
+    assert lib.dpr_hull_ws_bytes(-1, 1, cams) == 0
+    assert lib.dpr_hull_ws_bytes(10, 0, cams) == 0
+    assert lib.dpr_hull_ws_bytes(10, 5000, cams) == 0
+    assert lib.dpr_hull_ws_bytes(10, 1, None) == 0
+    cam.width = 0
+    assert lib.dpr_hull_ws_bytes(10, 1, (abi.Camera * 1)(cam)) == 0
 
 
 @pytest.mark.parametrize("case,expect", [("n_cams", 1), ("mask_size", 1), ("null_mask", 1), ("box", 1), ("nan_box", 1),

@@ -48,7 +48,9 @@ def test_sample_matches_oracle(hull, n, capacity):
 
 
 def test_sample_mixed_sizes_and_noisy_masks(hull):
-    cams = workloads.disc_views(3, size=64) + workloads.disc_views(2, size=40, seed=1)
+    # 37 x 29 = 1073 pixels: the last packed word of that mask is partial
+    cams = workloads.disc_views(3, size=64) + workloads.disc_views(2, size=40, seed=1) + \
+        [workloads.look_at_camera(np.array([0.3, -2.9, 0.5]), 37, 29)]
     masks = _noisy_masks(cams, 3, 0.9)
     seed = (7 << 40) | 99
     got, kept = hull.hull_sample(cams, _dev_masks(masks), LO, HI, seed, 20000)

@@ -53,7 +53,9 @@ def test_sample(exe, tmp_path, n, capacity):
 
 
 def test_sample_mixed_sizes_and_noisy_masks(exe, tmp_path):
-    cams = workloads.disc_views(3, size=64) + workloads.disc_views(2, size=40, seed=1)
+    # 37 x 29 = 1073 pixels: the last packed word of that mask is partial
+    cams = workloads.disc_views(3, size=64) + workloads.disc_views(2, size=40, seed=1) + \
+        [workloads.look_at_camera(np.array([0.3, -2.9, 0.5]), 37, 29)]
     masks = _noisy_masks(cams, 3, 0.9)
     seed = (7 << 40) | 99
     run(exe, tmp_path, "sample", dict(_tables(cams, masks), box=BOX), seed, 20000, 20000)
