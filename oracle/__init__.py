@@ -21,7 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "hybrid.c"), os.path.join(_HERE, "hull.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "hybrid.c"), os.path.join(_HERE, "hull.c"), os.path.join(_HERE, "chamfer.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -97,6 +97,14 @@ def lib():
         L.hull_consistent.restype = ctypes.c_int
         L.hull_sample.argtypes = [i32, P, P, P, P, P, ctypes.c_uint64, i64, P, i64]
         L.hull_sample.restype = i64
+        L.chamfer_nn.argtypes = [i64, P, i64, P, P, P]
+        L.chamfer_nn.restype = ctypes.c_int
+        L.chamfer_forward_backward.argtypes = [i64, P, i64, P, P, P]
+        L.chamfer_forward_backward.restype = ctypes.c_int
+        L.chamfer_topk_sh.argtypes = [i64, P, P, i64, P, i32, i32, P, P]
+        L.chamfer_topk_sh.restype = ctypes.c_int
+        L.adam_step.argtypes = [i64, P, P, P, P, i32, f64, f64, f64, f64]
+        L.adam_step.restype = ctypes.c_int
         for f in (L.oracle_sh_basis, L.oracle_project, L.oracle_depth_order, L.oracle_render,
                   L.oracle_backward, L.oracle_max_threads):
             f.restype = ctypes.c_int
@@ -445,3 +453,50 @@ def consistency_filter(cloud, cams, masks):
     c = cloud.astype(np.float32)
     keep = hull_consistent(c.xyz, cams, masks)
     return keep, Cloud(c.xyz[keep], c.sh[keep], c.opacity[keep], c.radius[keep])
+
+
+# ---------------------------------------------------------------------------
+# video warm start: Chamfer distance (Eq. 9), top-k SH transfer, Adam (oracle/chamfer.c)
+# ---------------------------------------------------------------------------
+
+def chamfer_nn(a, b):
+    """Nearest point of b for every point of a: (index int64 [na], float32 d2 [na])."""
+    a = _f32(a).reshape(-1, 3); b = _f32(b).reshape(-1, 3)
+    nn = np.zeros(a.shape[0], np.int64)
+    d2 = np.zeros(a.shape[0], np.float32)
+    if lib().chamfer_nn(a.shape[0], _p(a), b.shape[0], _p(b), _p(nn), _p(d2)) != 0:
+        raise ValueError("bad input")
+    return nn, d2
+
+
+def chamfer(s1, s2):
+    """(CD of Eq. 9, FP64; gradient with respect to s2 positions, FP64 [n2, 3])."""
+    a = _f32(s1).reshape(-1, 3); b = _f32(s2).reshape(-1, 3)
+    cd = np.zeros(1, np.float64)
+    g = np.zeros((b.shape[0], 3), np.float64)
+    if lib().chamfer_forward_backward(a.shape[0], _p(a), b.shape[0], _p(b), _p(cd), _p(g)) != 0:
+        raise ValueError("bad input")
+    return float(cd[0]), g
+
+
+def topk_sh(s1, sh1, s2, K: int):
+    """Mean SH of each s2 point's K nearest s1 points: (FP64 [n2, C, 3], indices [n2, K], -1 past |s1|)."""
+    a = _f32(s1).reshape(-1, 3); b = _f32(s2).reshape(-1, 3)
+    h = _f32(sh1)
+    n2 = b.shape[0]
+    out = np.zeros((n2,) + h.shape[1:], np.float64)
+    idx = np.zeros((n2, K), np.int64)
+    k3 = int(np.prod(h.shape[1:]))
+    if lib().chamfer_topk_sh(a.shape[0], _p(a), _p(h), n2, _p(b), k3, int(K), _p(out), _p(idx)) != 0:
+        raise ValueError("bad input")
+    return out, idx
+
+
+def adam_step(p, g, m, v, t: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """One Adam step in FP64, in place on p, m, v (float64 arrays)."""
+    for x in (p, g, m, v):
+        if x.dtype != np.float64 or not x.flags.c_contiguous:
+            raise ValueError("contiguous float64 arrays required")
+    if lib().adam_step(p.size, _p(p), _p(g), _p(m), _p(v), int(t), float(lr), float(b1), float(b2),
+                       float(eps)) != 0:
+        raise ValueError("bad input")
