@@ -348,6 +348,45 @@ int dpr_consistency_filter(int64_t n, int32_t sh_degree, const float *xyz, const
                            float *out_xyz, float *out_sh, float *out_opacity, float *out_radius, int64_t *out_count,
                            void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Video warm start (Sec. 3.4 "Video Synthesis"): the Chamfer distance of
+ * Eq. (9) between the learned cloud S1 of one frame and the initial cloud S2
+ * of the next, its gradient with respect to the positions of S2, an Adam step
+ * on those positions, and the transfer to every S2 point of the mean SH
+ * coefficients of its k nearest S1 points.
+ * Squared distances in float32, each operation rounded once:
+ * d2(x, y) = ((x0 - y0)^2 + (x1 - y1)^2) + (x2 - y2)^2; a nearest neighbour is
+ * the point of smallest d2, ties to the lower index.  Brute force: the work
+ * grows as n1 * n2 (meant for clouds of one frame, up to about 10^6 points).
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of the device workspace of dpr_chamfer (0 on bad sizes). */
+size_t dpr_chamfer_ws_bytes(int64_t n1, int64_t n2);
+
+/* For clouds s1[n1][3], s2[n2][3] (device float32, 1 <= n < 2^31):
+ *   *cd = (1/n1) sum_x d2(x, nn(x)) + (1/n2) sum_y d2(y, nn(y))   (Eq. 9; device
+ *         double, FP64 sums; NULL to skip),
+ *   grad2[j] = dCD/dy_j = (2/n2)(y_j - nn(y_j)) + (2/n1) sum_{x: nn(x) = y_j}
+ *         (y_j - x)   (device float[n2][3], FP64 then rounded; NULL to skip),
+ *   nn12[i], nn21[j]: nearest indices (device int32; NULL to skip).
+ * Asynchronous on `stream`. */
+int dpr_chamfer(int64_t n1, const float *s1, int64_t n2, const float *s2, double *cd, float *grad2, int32_t *nn12,
+                int32_t *nn21, void *ws, size_t ws_bytes, void *stream);
+
+/* out_sh2[j] = mean of sh1 over the k = min(K, n1) points of s1 with the
+ * smallest (d2(y_j, x), index), FP64 sums in that order (1 <= K <= 32;
+ * sh1/out_sh2: device float[n][(sh_degree + 1)^2][3]); idx[j][K] (device
+ * int32, -1 past k; NULL to skip).  Asynchronous on `stream`. */
+int dpr_topk_sh(int64_t n1, const float *s1, const float *sh1, int64_t n2, const float *s2, int32_t sh_degree,
+                int32_t K, float *out_sh2, int32_t *idx, void *stream);
+
+/* One Adam step (Kingma and Ba, ICLR 2015) on n values in float32, in place
+ * on p, m, v (device), step t >= 1 with bias correction:
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).  Asynchronous. */
+int dpr_adam_step(int64_t n, float *p, const float *g, float *m, float *v, int32_t t, float lr, float beta1,
+                  float beta2, float eps, void *stream);
+
 /* Releases a plan (host memory and HIP events only).  NULL is ignored. */
 void dpr_plan_free(dpr_plan *plan);
 

@@ -25,7 +25,8 @@ EXPORTED = ["dpr_version", "dpr_last_error", "dpr_plan_ws_bytes", "dpr_plan_forw
             "dpr_render_backward", "dpr_plan_free", "dpr_plan_get_info", "dpr_stage_times",
             "dpr_render_forward_1", "dpr_loss_ws_bytes", "dpr_loss_l2_tv", "dpr_knn_ws_bytes", "dpr_knn",
             "dpr_hybrid_ws_bytes", "dpr_voxel_reduce", "dpr_hybrid_update", "dpr_hull_ws_bytes", "dpr_hull_sample",
-            "dpr_consistency", "dpr_consistency_filter"]
+            "dpr_consistency", "dpr_consistency_filter", "dpr_chamfer_ws_bytes", "dpr_chamfer", "dpr_topk_sh",
+            "dpr_adam_step"]
 
 
 class Camera(ctypes.Structure):
@@ -118,6 +119,11 @@ def load(path: str = LIB_PATH):
     L.dpr_consistency_filter.argtypes = [c_i64, c_i32, c_p, c_p, c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, I64P,
                                          c_p, c_sz, c_p]
     L.dpr_consistency_filter.restype = c_i32
+    L.dpr_chamfer_ws_bytes.argtypes, L.dpr_chamfer_ws_bytes.restype = [c_i64, c_i64], c_sz
+    L.dpr_chamfer.argtypes, L.dpr_chamfer.restype = [c_i64, c_p, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p], c_i32
+    L.dpr_topk_sh.argtypes, L.dpr_topk_sh.restype = [c_i64, c_p, c_p, c_i64, c_p, c_i32, c_i32, c_p, c_p, c_p], c_i32
+    L.dpr_adam_step.argtypes = [c_i64, c_p, c_p, c_p, c_p, c_i32, c_f, c_f, c_f, c_f, c_p]
+    L.dpr_adam_step.restype = c_i32
     _lib = L
     return L
 

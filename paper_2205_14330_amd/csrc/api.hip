@@ -1056,4 +1056,51 @@ int dpr_consistency_filter(int64_t n, int32_t sh_degree, const float *xyz, const
     return DPR_OK;
 }
 
+size_t dpr_chamfer_ws_bytes(int64_t n1, int64_t n2) {
+    if (n1 < 1 || n2 < 1 || n1 > (int64_t)0x7FFFFFFF || n2 > (int64_t)0x7FFFFFFF) return 0;
+    return (size_t)chamfer_layout((uint64_t)n1, (uint64_t)n2).bytes;
+}
+
+int dpr_chamfer(int64_t n1, const float *s1, int64_t n2, const float *s2, double *cd, float *grad2, int32_t *nn12,
+                int32_t *nn21, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (n1 < 1 || n2 < 1 || n1 > (int64_t)0x7FFFFFFF || n2 > (int64_t)0x7FFFFFFF)
+        return fail(DPR_ERR_INVALID_ARG, "point counts must be in [1, 2^31 - 1]");
+    if (!s1 || !s2) return fail(DPR_ERR_INVALID_ARG, "s1 or s2 is NULL");
+    const ChamferLayout L = chamfer_layout((uint64_t)n1, (uint64_t)n2);
+    if (!ws || ws_bytes < L.bytes) return fail(DPR_ERR_WORKSPACE, "workspace needs %llu bytes", (unsigned long long)L.bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    HIP_TRY(launch_chamfer((uint32_t)n1, s1, (uint32_t)n2, s2, cd, grad2, nn12, nn21, static_cast<uint8_t *>(ws),
+                           static_cast<hipStream_t>(stream)));
+    return DPR_OK;
+}
+
+int dpr_topk_sh(int64_t n1, const float *s1, const float *sh1, int64_t n2, const float *s2, int32_t sh_degree,
+                int32_t K, float *out_sh2, int32_t *idx, void *stream) {
+    g_err.clear();
+    if (n1 < 1 || n2 < 0 || n1 > (int64_t)0x7FFFFFFF || n2 > (int64_t)0x7FFFFFFF)
+        return fail(DPR_ERR_INVALID_ARG, "point counts must be n1 in [1, 2^31 - 1], n2 in [0, 2^31 - 1]");
+    if (sh_degree < 0 || sh_degree > 3) return fail(DPR_ERR_INVALID_ARG, "sh_degree must be in [0, 3]");
+    if (K < 1 || K > kTopkMax) return fail(DPR_ERR_INVALID_ARG, "K must be in [1, %d]", kTopkMax);
+    if (!s1 || !sh1 || (n2 > 0 && (!s2 || !out_sh2))) return fail(DPR_ERR_INVALID_ARG, "NULL array");
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    HIP_TRY(launch_topk_sh((uint32_t)n1, s1, sh1, (uint32_t)n2, s2, 3 * (sh_degree + 1) * (sh_degree + 1), K, out_sh2,
+                           idx, static_cast<hipStream_t>(stream)));
+    return DPR_OK;
+}
+
+int dpr_adam_step(int64_t n, float *p, const float *g, float *m, float *v, int32_t t, float lr, float beta1,
+                  float beta2, float eps, void *stream) {
+    g_err.clear();
+    if (n < 0 || n > (int64_t)0xFFFFFFFF) return fail(DPR_ERR_INVALID_ARG, "n must be in [0, 2^32 - 1]");
+    if (t < 1) return fail(DPR_ERR_INVALID_ARG, "t must be >= 1");
+    if (!(lr >= 0.f) || !std::isfinite(lr) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+        !(eps > 0.f) || !std::isfinite(eps))
+        return fail(DPR_ERR_INVALID_ARG, "need lr >= 0, 0 <= beta1, beta2 < 1, eps > 0 (all finite)");
+    if (n > 0 && (!p || !g || !m || !v)) return fail(DPR_ERR_INVALID_ARG, "NULL array");
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    HIP_TRY(launch_adam((uint32_t)n, p, g, m, v, t, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream)));
+    return DPR_OK;
+}
+
 }  // extern "C"

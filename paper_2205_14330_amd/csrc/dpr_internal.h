@@ -308,6 +308,19 @@ uint64_t hull_blocks(uint64_t n);
 HullLayout hull_layout(uint64_t n, int32_t n_cams, const HullCam *cams);
 hipError_t launch_hull(const HullJob &job, uint8_t *ws, uint64_t *kept_host, hipStream_t st);
 
+// Video warm start: Chamfer distance, top-k SH transfer, Adam (chamfer.hip).
+constexpr int kTopkMax = 32;
+struct ChamferLayout {
+    uint64_t key12, key21, acc, cnt, part1, part2, bytes;
+};
+ChamferLayout chamfer_layout(uint64_t n1, uint64_t n2);
+hipError_t launch_chamfer(uint32_t n1, const float *s1, uint32_t n2, const float *s2, double *cd, float *grad2,
+                          int32_t *nn12, int32_t *nn21, uint8_t *ws, hipStream_t st);
+hipError_t launch_topk_sh(uint32_t n1, const float *s1, const float *sh1, uint32_t n2, const float *s2, int k3, int K,
+                          float *out_sh, int32_t *idx, hipStream_t st);
+hipError_t launch_adam(uint32_t n, float *p, const float *g, float *m, float *v, int t, float lr, float b1, float b2,
+                       float eps, hipStream_t st);
+
 // Eq. (8) loss over a batch of images (loss.hip).
 struct LossImage {
     const float *render, *target;

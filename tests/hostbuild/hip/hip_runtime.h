@@ -1,5 +1,5 @@
 // Host stand-in for the part of the HIP runtime and device library that the
-// hybrid-update and visual-hull kernels use, so that those kernels compile with g++ and run on
+// hybrid-update, visual-hull and warm-start kernels use, so that those kernels compile with g++ and run on
 // CPU threads under AddressSanitizer.  Test infrastructure only: it checks the
 // kernels' indexing and host sequencing, not GPU code generation.
 //
@@ -104,21 +104,24 @@ class Pool {
         for (auto &th : threads_) th.join();
     }
     void run(dim3 grid, dim3 block, const std::function<void()> &body) {
-        if (block.x == 0 || block.x > kMaxBlock || block.y != 1 || block.z != 1 || grid.y != 1 || grid.z != 1) {
+        if (block.x == 0 || block.x > kMaxBlock || block.y != 1 || block.z != 1 || grid.z != 1) {
             std::fprintf(stderr, "host launch: unsupported shape grid %u block %u\n", grid.x, block.x);
             std::abort();
         }
         gridDim.x = grid.x;
+        gridDim.y = grid.y;
         blockDim.x = block.x;
         body_ = &body;
-        for (uint32_t b = 0; b < grid.x; ++b) {
-            blk_.bar = std::make_unique<std::barrier<>>(block.x);
-            for (uint32_t w = 0; w < (block.x + 63) / 64; ++w)
-                blk_.wave[w] = std::make_unique<std::barrier<>>(std::min<uint32_t>(64, block.x - 64 * w));
-            block_ = b;
-            start_.arrive_and_wait();
-            end_.arrive_and_wait();
-        }
+        for (uint32_t by = 0; by < grid.y; ++by)
+            for (uint32_t b = 0; b < grid.x; ++b) {
+                blk_.bar = std::make_unique<std::barrier<>>(block.x);
+                for (uint32_t w = 0; w < (block.x + 63) / 64; ++w)
+                    blk_.wave[w] = std::make_unique<std::barrier<>>(std::min<uint32_t>(64, block.x - 64 * w));
+                block_ = b;
+                block_y_ = by;
+                start_.arrive_and_wait();
+                end_.arrive_and_wait();
+            }
     }
     Block &block() { return blk_; }
 
@@ -130,6 +133,7 @@ class Pool {
             if (t < blockDim.x) {
                 threadIdx.x = t;
                 blockIdx.x = block_;
+                blockIdx.y = block_y_;
                 (*body_)();
                 // an exited thread no longer takes part in barriers, and a
                 // ballot reads its predicate as 0
@@ -143,7 +147,7 @@ class Pool {
     std::vector<std::thread> threads_;
     std::barrier<> start_, end_;
     const std::function<void()> *body_ = nullptr;
-    uint32_t block_ = 0;
+    uint32_t block_ = 0, block_y_ = 0;
     Block blk_;
     bool quit_ = false;
 };
@@ -194,6 +198,26 @@ inline uint64_t __ballot(int pred) {
     b.wave[t / 64]->arrive_and_wait();
     return m;
 }
+
+// Device atomics on host memory (the threads of a block run concurrently).
+inline unsigned long long atomicMin(unsigned long long *p, unsigned long long v) {
+    unsigned long long old = __atomic_load_n(p, __ATOMIC_RELAXED);
+    while (v < old && !__atomic_compare_exchange_n(p, &old, v, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+    }
+    return old;
+}
+inline double atomicAdd(double *p, double v) {
+    uint64_t *w = reinterpret_cast<uint64_t *>(p);
+    uint64_t old = __atomic_load_n(w, __ATOMIC_RELAXED), upd;
+    double o;
+    do {
+        std::memcpy(&o, &old, 8);
+        const double n = o + v;
+        std::memcpy(&upd, &n, 8);
+    } while (!__atomic_compare_exchange_n(w, &old, upd, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED));
+    return o;
+}
+inline uint32_t atomicAdd(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
 
 inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
 inline int __popc(uint32_t x) { return __builtin_popcount(x); }

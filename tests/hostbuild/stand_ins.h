@@ -1,6 +1,6 @@
 // Sequential host stand-ins for the library routines that the kernels under
-// test call but that live in other sources (flat scan, radix sort, small-table
-// upload).  Each keeps its routine's contract: it touches exactly the scratch
+// test call but that live in other sources (flat scan, radix sort, fill,
+// small-table upload).  Each keeps its routine's contract: it touches exactly the scratch
 // words the library's version uses, and the sort leaves its result in the
 // buffer the library's would.  Test infrastructure only.
 #pragma once
@@ -51,6 +51,11 @@ hipError_t launch_radix_sort(uint32_t n, int bits, uint32_t *keys, uint32_t *val
         ko[i] = kv[i].first;
         vo[i] = kv[i].second;
     }
+    return hipSuccess;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t) {
+    for (uint64_t i = 0; i < n; ++i) p[i] = value;
     return hipSuccess;
 }
 

@@ -338,3 +338,51 @@ def test_hull_invalid_arguments_rejected(abi, case, expect):
         keep = FAKE + 32768
         rc2 = lib.dpr_consistency(100, FAKE, n_cams, cams, masks, keep, ws, nb, None)
         assert rc2 == expect
+
+
+@pytest.mark.parametrize("case", ["n1", "n2", "null_s1", "workspace", "topk_K", "topk_deg", "topk_null",
+                                  "adam_t", "adam_beta", "adam_eps", "adam_null"])
+def test_warm_start_invalid_arguments_rejected(abi, case):
+    """Every check of the warm-start entry points runs on the host before
+    anything is launched."""
+    lib = abi.load()
+    s1, s2, ws = FAKE, FAKE + 65536, FAKE + 131072
+    if case in ("n1", "n2", "null_s1", "workspace"):
+        n1, n2, nb = 100, 80, 1 << 30
+        if case == "n1":
+            n1 = 0
+        elif case == "n2":
+            n2 = -3
+        elif case == "null_s1":
+            s1 = None
+        else:
+            nb = 16
+        rc = lib.dpr_chamfer(n1, s1, n2, s2, None, None, None, None, ws, nb, None)
+        assert rc == (2 if case == "workspace" else 1), lib.dpr_last_error()
+    elif case.startswith("topk"):
+        K, deg, out = 4, 2, FAKE + 262144
+        if case == "topk_K":
+            K = 33
+        elif case == "topk_deg":
+            deg = 4
+        else:
+            out = None
+        assert lib.dpr_topk_sh(100, s1, FAKE + 8192, 80, s2, deg, K, out, None, None) == 1
+    else:
+        t, b1, eps, p = 1, 0.9, 1e-8, FAKE
+        if case == "adam_t":
+            t = 0
+        elif case == "adam_beta":
+            b1 = 1.0
+        elif case == "adam_eps":
+            eps = 0.0
+        else:
+            p = None
+        assert lib.dpr_adam_step(10, p, FAKE, FAKE, FAKE, t, 1e-3, b1, 0.999, eps, None) == 1
+    assert lib.dpr_last_error()
+
+
+def test_chamfer_workspace_sizes(abi):
+    lib = abi.load()
+    assert lib.dpr_chamfer_ws_bytes(1000, 2000) >= 8 * 3000 + 24 * 2000 + 4 * 2000
+    assert lib.dpr_chamfer_ws_bytes(0, 5) == 0 and lib.dpr_chamfer_ws_bytes(5, 0) == 0
