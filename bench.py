@@ -29,7 +29,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpix/s fwd & fwd+bwd (300k pts, 800x800) at 1e-4 err; served p50/p99 latency"
 PEAK_HBM = 8.0e12                 # B/s
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # non-packed FP32 VALU lane-ops/s (39.3 T)
+# FP32 VALU lane-ops/s: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz = 78.6 T, the published
+# 157.3 TFLOP/s FP32 vector rate with an FMA counted as one lane-op.  Plain (non-packed) FP32
+# instructions with VGPR operands issue a wave64 every two clocks per SIMD, so this rate needs no
+# packed instructions.
+PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 FWD_OPS_PER_BLEND = 20            # lane-ops per blended (pixel, splat), forward composite
 BWD_OPS_PER_BLEND = 50            # lane-ops per blended (pixel, splat), backward composite
 

@@ -22,8 +22,8 @@
 // colour blended behind (B = I_final - I_checkpoint at a segment end), and
 // folding each (pixel, splat) contribution into 7 per-lane partial sums.  A
 // chunk of 64 records is gathered one per lane, written to LDS and read back
-// as broadcasts.  The sums are reduced across each group of 4 lanes with DPP,
-// the 16 group sums of up to 8 splats are staged in LDS, and each flush
+// as broadcasts.  The sums are reduced across each group of 4 lanes with
+// quad-permute swizzles (LDS pipe, so the VALU only adds), the 16 group sums of up to 8 splats are staged in LDS, and each flush
 // completes 56 sums and adds them to the per-item gradient records with one
 // 64-lane float atomic.
 #include "dpr_internal.h"
@@ -32,6 +32,18 @@ namespace dpr {
 
 constexpr int kCompLanes = 64;
 constexpr int kQuad = 4;          // pixels per lane
+
+// Keeps a wave-uniform value in a VGPR.  A VALU instruction that reads an SGPR
+// issues at about half the rate of one whose operands are VGPRs, inline
+// constants or literals (measured on gfx950: ~4 against ~2 clocks per wave64
+// add), so the loop-invariant thresholds of the inner loops are copied to
+// VGPRs once.  The empty asm hides the value's uniformity from the compiler,
+// which would otherwise fold it back into SGPR operands.
+template <typename V>
+__device__ __forceinline__ V in_vgpr(V x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
 
 struct TileCtx {
     uint32_t start, end;       // list range in pairs[]
@@ -56,9 +68,12 @@ __device__ __forceinline__ TileCtx tile_ctx(const CompositeArgs &a, uint32_t til
 }
 
 // alpha = min(alpha_max, 2^e); the clamp (and only it) blocks the gradient to e.
-__device__ __forceinline__ float splat_alpha(float e, float alpha_max) {
-    return fminf(__builtin_amdgcn_exp2f(e), alpha_max);
-}
+// The exponent never exceeds the record's w (its quadratic form is >= 0), so a
+// splat whose peak 2^w stays below alpha_max clamps no pixel; w_noclamp puts
+// that test a margin of 2^-1e-5 (about 58 float ulps) inside alpha_max, far
+// above the error of exp2 and log2, and the compositing loops apply the clamp
+// only on the rare path where w exceeds it.
+__device__ __forceinline__ float no_clamp_w(float alpha_max) { return __log2f(alpha_max) - 1e-5f; }
 
 // Record k of the pair list, or an inert record past the end.
 __device__ __forceinline__ void load_rec(const CompositeArgs &a, uint32_t k, uint32_t end, float4 &r0, float4 &r1,
@@ -101,16 +116,20 @@ constexpr int kFwdChunk = 2 * kFwdThreads;
 // the tile's backward work items (tile, s) for s < ceil(max stop / kBwdSeg).
 static_assert(kBwdSeg % kFwdChunk == 0, "backward segments are whole forward chunks");
 
-// CAP: a pixel also stops after blending th.max_splats splats (then it is live
-// while T >= t_min and fewer than max_splats splats were blended).
-template <bool PERSISTENT, bool CAP>
+// COUNT: the kernel counts each pixel's blended splats, for the per-pixel
+// statistics and for the cap th.max_splats: a pixel also stops after blending
+// that many (then it is live while T >= t_min and fewer than max_splats splats
+// were blended).  Without a cap the count never reaches cap = 2^32 - 1.
+template <bool PERSISTENT, bool COUNT>
 __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     constexpr int PX = kFwdPx, kThreads = kFwdThreads, kChunk = kFwdChunk;
     __shared__ float4 s_r0[kChunk], s_r1[kChunk];
     __shared__ uint32_t s_next, s_max[2], s_work;
-    const float neg_lambda = -a.th.lambda;
-    const float alpha_max = a.th.alpha_max, t_min = a.th.t_min;
-    const uint32_t cap = a.th.max_splats;
+    const float neg_lambda = in_vgpr(-a.th.lambda);
+    const float alpha_max = a.th.alpha_max;
+    const float w_noclamp = in_vgpr(no_clamp_w(alpha_max));
+    const float t_min = in_vgpr(a.th.t_min);
+    const uint32_t cap = in_vgpr(a.th.max_splats > 0 ? a.th.max_splats : 0xFFFFFFFFu);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_remap(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
         const int v = find_segment(a.tile_start, a.n_views, tile);
@@ -169,14 +188,18 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             for (int j0 = 0; j0 < cnt; j0 += 16) {
                 bool any_live = false;
 #pragma unroll
-                for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!CAP || nblend[p] < cap));
+                for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!COUNT || nblend[p] < cap));
                 if (__ballot(any_live) == 0ull) break;
                 const int jn = min(j0 + 16, cnt);
-                for (int j = j0; j < jn; ++j) {
-                    const float4 r0 = s_r0[j];
+                // record j sits at byte 16 j of s_r0 and of s_r1; the offset is kept
+                // in a VGPR (see in_vgpr) and addresses both LDS reads
+                int roff = in_vgpr(16 * j0);
+                for (int j = j0; j < jn; ++j, roff = in_vgpr(roff + 16)) {
+                    const float4 r0 = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_r0) + roff);
+                    const char *r1p = reinterpret_cast<const char *>(s_r1) + roff;
                     SplatRec s;
                     s.px = r0.x; s.py = r0.y; s.a = r0.z; s.b = r0.w;
-                    s.w = s_r1[j].x;
+                    s.w = *reinterpret_cast<const float *>(r1p);
                     float e[PX];
                     bool hit[PX];
                     bool any = false;
@@ -184,32 +207,40 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                     for (int p = 0; p < PX; ++p) {
                         float dx, dy, q;
                         e[p] = splat_exponent(s, ux[p], uy[p], dx, dy, q);
-                        hit[p] = T[p] >= t_min && (!CAP || nblend[p] < cap) && e[p] >= neg_lambda;
+                        hit[p] = (T[p] >= t_min) & (!COUNT || nblend[p] < cap) & (e[p] >= neg_lambda);
                         any = any || hit[p];
                     }
                     if (__ballot(any) != 0ull) {
-                        const float4 r1 = s_r1[j];
+                        const float4 r1 = *reinterpret_cast<const float4 *>(r1p);
                         s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
                         // branch-free over the lane's pixels: alpha = 0 leaves a
                         // pixel that does not blend this splat exactly unchanged
                         const uint32_t pos1 = base - start + (uint32_t)j + 1;
+                        float alpha[PX];
+#pragma unroll
+                        for (int p = 0; p < PX; ++p) alpha[p] = hit[p] ? __builtin_amdgcn_exp2f(e[p]) : 0.f;
+                        if (__builtin_expect(s.w > w_noclamp, 0)) {
+                            const float am = in_vgpr(alpha_max);     // read here so the compares stay here
+#pragma unroll
+                            for (int p = 0; p < PX; ++p)
+                                if (alpha[p] > am) alpha[p] = am;
+                        }
 #pragma unroll
                         for (int p = 0; p < PX; ++p) {
-                            const float alpha = hit[p] ? splat_alpha(e[p], alpha_max) : 0.f;
-                            const float Ta = T[p] * alpha;
+                            const float Ta = T[p] * alpha[p];
                             I0[p] = fmaf(Ta, s.cr, I0[p]);
                             I1[p] = fmaf(Ta, s.cg, I1[p]);
                             I2[p] = fmaf(Ta, s.cb, I2[p]);
-                            nblend[p] += hit[p] ? 1u : 0u;
+                            if (COUNT) nblend[p] += hit[p] ? 1u : 0u;
                             T[p] = T[p] - Ta;                       // T (1 - alpha)
-                            if (hit[p] && (T[p] < t_min || (CAP && nblend[p] == cap))) nlast[p] = pos1;
+                            if (hit[p] & ((T[p] < t_min) | (COUNT && nblend[p] == cap))) nlast[p] = pos1;
                         }
                     }
                 }
             }
             bool any_live = false;
 #pragma unroll
-            for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!CAP || nblend[p] < cap));
+            for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!COUNT || nblend[p] < cap));
             if (__syncthreads_count(any_live) == 0) break;
         }
         uint32_t mymax = 0;
@@ -223,7 +254,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                 float *img = vd.image + 3 * lpix;
                 img[0] = I0[p]; img[1] = I1[p]; img[2] = I2[p];
                 if (vd.trans) vd.trans[lpix] = T[p];
-                if (a.stats) a.stats[pix] = nblend[p];
+                if (COUNT && a.stats) a.stats[pix] = nblend[p];
             }
             if (a.nlast) {
                 a.nlast[pix] = nlast[p];
@@ -253,16 +284,29 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-template <int CTRL>
-__device__ __forceinline__ float dpp_add(float v) {
-    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+// The value of the lane given by a quad-permute pattern.  ds_swizzle in quad
+// mode (offset bit 15 set; two bits per destination lane of the quad) runs on
+// the LDS pipe, so only the adds of a reduction issue on the VALU; a
+// DPP-modified add costs about twice a plain one there.
+template <int PATTERN>
+__device__ __forceinline__ float swizzle(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x8000 | PATTERN));
 }
 
-// Sum over each group of 4 consecutive lanes (valid in all 4 lanes).
-__device__ __forceinline__ float quad_sum(float v) {
-    v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
-    v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
-    return v;
+// Sums over each group of 4 consecutive lanes (valid in all 4 lanes) of N
+// values; each level's swizzles are issued together so that one wait covers
+// them.
+template <int N>
+__device__ __forceinline__ void quad_sums(float (&v)[N]) {
+    float t[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = swizzle<0xB1>(v[i]);     // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + t[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = swizzle<0x4E>(v[i]);     // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = v[i] + t[i];
 }
 
 // Staging of per-splat partial sums: slot k holds, for one splat, the 16
@@ -298,9 +342,9 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     __shared__ uint32_t s_gid[kSlots];
     __shared__ float4 s_rec[2 * kCompLanes];       // the current chunk: record j at [2j], [2j + 1]
     const CompositeArgs &a = b.c;
-    const float neg_lambda = -a.th.lambda;
+    const float neg_lambda = in_vgpr(-a.th.lambda);
     const float alpha_max = a.th.alpha_max;
-    const float w_noclamp = __log2f(alpha_max) - 1e-5f;
+    const float w_noclamp = in_vgpr(no_clamp_w(alpha_max));
     const int lane = threadIdx.x;
     float *const my_part = s_part + (lane >> 2) * kQuadStride;
     const uint32_t nwork = *b.work_count;
@@ -366,12 +410,21 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 const bool more = cbeg > sbeg;
                 if (more) load_rec(a, cbeg - kCompLanes + lane, lend, n0, n1, nid);
                 const int cnt = (int)min((uint32_t)kCompLanes, lend - cbeg);
-                for (int j = cnt - 1; j >= 0; --j) {
-                    const float4 f0 = s_rec[2 * j];
+                // Record j sits at byte 32 j of s_rec, and pixel p blended it iff its
+                // list position cbeg - start + j is below nl[p], i.e. iff 32 j < lim[p].
+                // The byte offset is kept in a VGPR (see in_vgpr): it addresses the
+                // LDS reads and takes part in the compares without SGPR operands.
+                int lim[kQuad];
+                const int rel = (int)(cbeg - c.start);
+#pragma unroll
+                for (int p = 0; p < kQuad; ++p) lim[p] = 32 * min(max((int)nl[p] - rel, 0), kCompLanes);
+                int roff = in_vgpr(32 * (cnt - 1));
+                for (int j = cnt - 1; j >= 0; --j, roff = in_vgpr(roff - 32)) {
+                    const char *rec = reinterpret_cast<const char *>(s_rec) + roff;
+                    const float4 f0 = *reinterpret_cast<const float4 *>(rec);
                     SplatRec s;
                     s.px = f0.x; s.py = f0.y; s.a = f0.z; s.b = f0.w;
-                    s.w = s_rec[2 * j + 1].x;
-                    const uint32_t pos = cbeg - c.start + (uint32_t)j;
+                    s.w = *reinterpret_cast<const float *>(rec + 16);
                     float gw[kQuad], Ta[kQuad], e[kQuad], g[kQuad], alpha[kQuad], qs[kQuad];
                     float dx0 = 0.f, dy0 = 0.f;
                     bool hit[kQuad];
@@ -381,15 +434,14 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         float dx, dy;
                         e[p] = splat_exponent(s, ux[p], uy[p], dx, dy, qs[p]);
                         if (p == 0) { dx0 = dx; dy0 = dy; }
-                        hit[p] = pos < nl[p] && e[p] >= neg_lambda;
+                        hit[p] = (roff < lim[p]) & (e[p] >= neg_lambda);
                         any = any || hit[p];
                     }
                     // a splat that no pixel of the tile blended changes nothing below
                     // (alpha = 0 for every pixel makes every update an exact no-op)
                     if (__ballot(any) == 0ull) continue;
-                    const float4 f1 = s_rec[2 * j + 1];
+                    const float4 f1 = *reinterpret_cast<const float4 *>(rec + 16);
                     s.cr = f1.y; s.cg = f1.z; s.cb = f1.w;
-                    bool any_clamped = false;
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
                         g[p] = __builtin_amdgcn_exp2f(e[p]);
@@ -398,19 +450,16 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         alpha[p] = hit[p] ? g[p] : 0.f;
                     }
                     // the alpha_max clamp, which also blocks the gradient to e, is rare:
-                    // it is applied on a path of its own, before and after the update.
                     // e <= w (q >= 0), so a splat whose peak 2^w stays below alpha_max
-                    // (with a margin far above the error of exp2) clamps no pixel.
-                    bool wave_clamped = false;
-                    if (__builtin_expect(s.w > w_noclamp, 0)) {
-#pragma unroll
-                        for (int p = 0; p < kQuad; ++p) any_clamped = any_clamped || (hit[p] && g[p] > alpha_max);
-                        wave_clamped = __ballot(any_clamped) != 0ull;
-                    }
-                    if (wave_clamped) {
+                    // (with a margin far above the error of exp2) clamps no pixel.  It is
+                    // applied on a path of its own before and after the update; the
+                    // threshold is read inside each branch so that the compares stay there.
+                    const bool near_max = __builtin_expect(s.w > w_noclamp, 0);
+                    if (near_max) {
+                        const float am = in_vgpr(alpha_max);
 #pragma unroll
                         for (int p = 0; p < kQuad; ++p)
-                            if (hit[p] && g[p] > alpha_max) alpha[p] = alpha_max;
+                            if (alpha[p] > am) alpha[p] = am;    // only a blending pixel has alpha > 0
                     }
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
@@ -422,10 +471,11 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         D[p] = fmaf(Ta[p], gc, D[p]);
                         gw[p] = dA * alpha[p];                           // dL/de / ln 2
                     }
-                    if (wave_clamped) {
+                    if (near_max) {
+                        const float am = in_vgpr(alpha_max);
 #pragma unroll
                         for (int p = 0; p < kQuad; ++p)
-                            if (hit[p] && g[p] > alpha_max) gw[p] = 0.f;
+                            if (hit[p] && g[p] > am) gw[p] = 0.f;
                     }
                     {
                         // quad pixel p sits at (+(p & 1), +(p >> 1)) from pixel 0, so its
@@ -444,11 +494,12 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                             v7 = fmaf(Ta[p], gI2[p], v7);
                         }
                         {   // the 4 lanes of a group hold bitwise-equal sums and store them
-                            // to the same words, which keeps the DPP adds unconditional
+                            // to the same words, which keeps the reduction unconditional
+                            float v[7] = {v0, v1, v2, v4, v5, v6, v7};
+                            quad_sums(v);
                             float *dst = my_part + nslots * kSlotStride;
-                            dst[0] = quad_sum(v0); dst[1] = quad_sum(v1); dst[2] = quad_sum(v2);
-                            dst[4] = quad_sum(v4); dst[5] = quad_sum(v5); dst[6] = quad_sum(v6);
-                            dst[7] = quad_sum(v7);
+                            dst[0] = v[0]; dst[1] = v[1]; dst[2] = v[2];
+                            dst[4] = v[3]; dst[5] = v[4]; dst[6] = v[5]; dst[7] = v[6];
                         }
                         if (lane == j) s_gid[nslots] = id;
                         if (++nslots == kSlots) {
@@ -481,19 +532,20 @@ static uint32_t persistent_grid(uint32_t tiles, uint32_t per_cu) {
     return tiles < g ? tiles : g;
 }
 
-template <bool CAP>
+template <bool COUNT>
 static void launch_fwd(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (persistent) {
-        hipLaunchKernelGGL((k_composite<true, CAP>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0,
+        hipLaunchKernelGGL((k_composite<true, COUNT>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0,
                            st, a);
     } else {
-        hipLaunchKernelGGL((k_composite<false, CAP>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
+        hipLaunchKernelGGL((k_composite<false, COUNT>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
     }
 }
 
 hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (a.total_tiles == 0) return hipSuccess;
-    if (a.th.max_splats > 0) launch_fwd<true>(a, persistent, st);
+    // the blend count is kept only where the cap or the statistics need it
+    if (a.th.max_splats > 0 || (a.write_views && a.stats)) launch_fwd<true>(a, persistent, st);
     else launch_fwd<false>(a, persistent, st);
     return hipGetLastError();
 }
