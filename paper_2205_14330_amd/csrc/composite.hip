@@ -123,7 +123,8 @@ static_assert(kBwdSeg % kFwdChunk == 0, "backward segments are whole forward chu
 template <bool PERSISTENT, bool COUNT>
 __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     constexpr int PX = kFwdPx, kThreads = kFwdThreads, kChunk = kFwdChunk;
-    __shared__ float4 s_r0[kChunk], s_r1[kChunk];
+    // two padding records: the read-ahead reaches index kChunk + 1
+    __shared__ float4 s_r0[kChunk + 2], s_r1[kChunk + 2];
     __shared__ uint32_t s_next, s_max[2], s_work;
     const float neg_lambda = in_vgpr(-a.th.lambda);
     const float alpha_max = a.th.alpha_max;
@@ -191,15 +192,17 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                 for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!COUNT || nblend[p] < cap));
                 if (__ballot(any_live) == 0ull) break;
                 const int jn = min(j0 + 16, cnt);
-                // record j sits at byte 16 j of s_r0 and of s_r1; the offset is kept
-                // in a VGPR (see in_vgpr) and addresses both LDS reads
-                int roff = in_vgpr(16 * j0);
-                for (int j = j0; j < jn; ++j, roff = in_vgpr(roff + 16)) {
-                    const float4 r0 = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_r0) + roff);
-                    const char *r1p = reinterpret_cast<const char *>(s_r1) + roff;
+                // Record j sits at byte 16 j of s_r0 and of s_r1; the offset is kept
+                // in a VGPR (see in_vgpr) and addresses both LDS reads.  The loop is
+                // unrolled by two over the register sets A and B: the next record is
+                // read while the current one is processed, so the LDS latency
+                // overlaps the arithmetic.  The whole record is read ahead (a later
+                // read of the colour would have to wait for the read-ahead as well).
+                const char *b0 = reinterpret_cast<const char *>(s_r0), *b1 = reinterpret_cast<const char *>(s_r1);
+                auto blend = [&](const float4 &r0, const float4 &r1, int j) {
                     SplatRec s;
                     s.px = r0.x; s.py = r0.y; s.a = r0.z; s.b = r0.w;
-                    s.w = *reinterpret_cast<const float *>(r1p);
+                    s.w = r1.x;
                     float e[PX];
                     bool hit[PX];
                     bool any = false;
@@ -210,32 +213,44 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                         hit[p] = (T[p] >= t_min) & (!COUNT || nblend[p] < cap) & (e[p] >= neg_lambda);
                         any = any || hit[p];
                     }
-                    if (__ballot(any) != 0ull) {
-                        const float4 r1 = *reinterpret_cast<const float4 *>(r1p);
-                        s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
-                        // branch-free over the lane's pixels: alpha = 0 leaves a
-                        // pixel that does not blend this splat exactly unchanged
-                        const uint32_t pos1 = base - start + (uint32_t)j + 1;
-                        float alpha[PX];
+                    if (__ballot(any) == 0ull) return;
+                    s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
+                    // branch-free over the lane's pixels: alpha = 0 leaves a pixel
+                    // that does not blend this splat exactly unchanged
+                    const uint32_t pos1 = base - start + (uint32_t)j + 1;
+                    float alpha[PX];
 #pragma unroll
-                        for (int p = 0; p < PX; ++p) alpha[p] = hit[p] ? __builtin_amdgcn_exp2f(e[p]) : 0.f;
-                        if (__builtin_expect(s.w > w_noclamp, 0)) {
-                            const float am = in_vgpr(alpha_max);     // read here so the compares stay here
+                    for (int p = 0; p < PX; ++p) alpha[p] = hit[p] ? __builtin_amdgcn_exp2f(e[p]) : 0.f;
+                    if (__builtin_expect(s.w > w_noclamp, 0)) {
+                        const float am = in_vgpr(alpha_max);         // read here so the compares stay here
 #pragma unroll
-                            for (int p = 0; p < PX; ++p)
-                                if (alpha[p] > am) alpha[p] = am;
-                        }
-#pragma unroll
-                        for (int p = 0; p < PX; ++p) {
-                            const float Ta = T[p] * alpha[p];
-                            I0[p] = fmaf(Ta, s.cr, I0[p]);
-                            I1[p] = fmaf(Ta, s.cg, I1[p]);
-                            I2[p] = fmaf(Ta, s.cb, I2[p]);
-                            if (COUNT) nblend[p] += hit[p] ? 1u : 0u;
-                            T[p] = T[p] - Ta;                       // T (1 - alpha)
-                            if (hit[p] & ((T[p] < t_min) | (COUNT && nblend[p] == cap))) nlast[p] = pos1;
-                        }
+                        for (int p = 0; p < PX; ++p)
+                            if (alpha[p] > am) alpha[p] = am;
                     }
+#pragma unroll
+                    for (int p = 0; p < PX; ++p) {
+                        const float Ta = T[p] * alpha[p];
+                        I0[p] = fmaf(Ta, s.cr, I0[p]);
+                        I1[p] = fmaf(Ta, s.cg, I1[p]);
+                        I2[p] = fmaf(Ta, s.cb, I2[p]);
+                        if (COUNT) nblend[p] += hit[p] ? 1u : 0u;
+                        T[p] = T[p] - Ta;                           // T (1 - alpha)
+                        if (hit[p] & ((T[p] < t_min) | (COUNT && nblend[p] == cap))) nlast[p] = pos1;
+                    }
+                };
+                int roff = in_vgpr(16 * j0);
+                float4 a0 = *reinterpret_cast<const float4 *>(b0 + roff);
+                float4 a1 = *reinterpret_cast<const float4 *>(b1 + roff);
+                for (int j = j0; j < jn; j += 2) {
+                    roff = in_vgpr(roff + 16);                      // record j + 1 (at most index kChunk)
+                    const float4 c0 = *reinterpret_cast<const float4 *>(b0 + roff);
+                    const float4 c1 = *reinterpret_cast<const float4 *>(b1 + roff);
+                    blend(a0, a1, j);
+                    if (j + 1 >= jn) break;
+                    roff = in_vgpr(roff + 16);                      // record j + 2 (at most index kChunk + 1)
+                    a0 = *reinterpret_cast<const float4 *>(b0 + roff);
+                    a1 = *reinterpret_cast<const float4 *>(b1 + roff);
+                    blend(c0, c1, j + 1);
                 }
             }
             bool any_live = false;
@@ -340,7 +355,10 @@ __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t 
 __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     __shared__ float s_part[kSlots * kSlotStride];
     __shared__ uint32_t s_gid[kSlots];
-    __shared__ float4 s_rec[2 * kCompLanes];       // the current chunk: record j at [2j], [2j + 1]
+    // the current chunk: record j at s_rec[2j], s_rec[2j + 1]; two padding records
+    // in front, which the read-ahead of records -1 and -2 reaches
+    __shared__ float4 s_rec_store[2 * kCompLanes + 4];
+    float4 *const s_rec = s_rec_store + 4;
     const CompositeArgs &a = b.c;
     const float neg_lambda = in_vgpr(-a.th.lambda);
     const float alpha_max = a.th.alpha_max;
@@ -401,6 +419,12 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
             float4 n0, n1;
             uint32_t nid;
             load_rec(a, cbeg + lane, lend, n0, n1, nid);
+            // Pixel p blended the record at list position cbeg - start + j iff that
+            // position is below nl[p], i.e. iff 32 j < lim[p] = 32 (nl[p] - (cbeg -
+            // start)) for the current chunk; lim grows by 32 * 64 per chunk back.
+            int lim[kQuad];
+#pragma unroll
+            for (int p = 0; p < kQuad; ++p) lim[p] = 32 * ((int)nl[p] - (int)(cbeg - c.start));
             while (true) {
                 const uint32_t id = nid;
                 __syncthreads();                 // the previous chunk's broadcasts are done
@@ -410,21 +434,11 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 const bool more = cbeg > sbeg;
                 if (more) load_rec(a, cbeg - kCompLanes + lane, lend, n0, n1, nid);
                 const int cnt = (int)min((uint32_t)kCompLanes, lend - cbeg);
-                // Record j sits at byte 32 j of s_rec, and pixel p blended it iff its
-                // list position cbeg - start + j is below nl[p], i.e. iff 32 j < lim[p].
-                // The byte offset is kept in a VGPR (see in_vgpr): it addresses the
-                // LDS reads and takes part in the compares without SGPR operands.
-                int lim[kQuad];
-                const int rel = (int)(cbeg - c.start);
-#pragma unroll
-                for (int p = 0; p < kQuad; ++p) lim[p] = 32 * min(max((int)nl[p] - rel, 0), kCompLanes);
-                int roff = in_vgpr(32 * (cnt - 1));
-                for (int j = cnt - 1; j >= 0; --j, roff = in_vgpr(roff - 32)) {
-                    const char *rec = reinterpret_cast<const char *>(s_rec) + roff;
-                    const float4 f0 = *reinterpret_cast<const float4 *>(rec);
+                // one (pixel, splat) record of the walk: record j at byte offset ro
+                auto splat = [&](const float4 &f0, const float4 &f1, int ro, int j) {
                     SplatRec s;
                     s.px = f0.x; s.py = f0.y; s.a = f0.z; s.b = f0.w;
-                    s.w = *reinterpret_cast<const float *>(rec + 16);
+                    s.w = f1.x;
                     float gw[kQuad], Ta[kQuad], e[kQuad], g[kQuad], alpha[kQuad], qs[kQuad];
                     float dx0 = 0.f, dy0 = 0.f;
                     bool hit[kQuad];
@@ -434,13 +448,12 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         float dx, dy;
                         e[p] = splat_exponent(s, ux[p], uy[p], dx, dy, qs[p]);
                         if (p == 0) { dx0 = dx; dy0 = dy; }
-                        hit[p] = (roff < lim[p]) & (e[p] >= neg_lambda);
+                        hit[p] = (ro < lim[p]) & (e[p] >= neg_lambda);
                         any = any || hit[p];
                     }
                     // a splat that no pixel of the tile blended changes nothing below
                     // (alpha = 0 for every pixel makes every update an exact no-op)
-                    if (__ballot(any) == 0ull) continue;
-                    const float4 f1 = *reinterpret_cast<const float4 *>(rec + 16);
+                    if (__ballot(any) == 0ull) return;
                     s.cr = f1.y; s.cg = f1.z; s.cb = f1.w;
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
@@ -477,39 +490,62 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         for (int p = 0; p < kQuad; ++p)
                             if (hit[p] && g[p] > am) gw[p] = 0.f;
                     }
-                    {
-                        // quad pixel p sits at (+(p & 1), +(p >> 1)) from pixel 0, so its
-                        // dx is dx0 - (p & 1) and its dy is dy0 - (p >> 1)
-                        const float gx = gw[1] + gw[3], gz = gw[0] + gw[2];
-                        const float v4 = gx + gz;
-                        const float v0 = fmaf(dx0, v4, -gx);
-                        const float v1 = fmaf(dy0, v4, -(gw[2] + gw[3]));
-                        float v2 = gw[0] * qs[0];
-                        float v5 = Ta[0] * gI0[0], v6 = Ta[0] * gI1[0], v7 = Ta[0] * gI2[0];
+                    // quad pixel p sits at (+(p & 1), +(p >> 1)) from pixel 0, so its
+                    // dx is dx0 - (p & 1) and its dy is dy0 - (p >> 1)
+                    const float gx = gw[1] + gw[3], gz = gw[0] + gw[2];
+                    const float v4 = gx + gz;
+                    const float v0 = fmaf(dx0, v4, -gx);
+                    const float v1 = fmaf(dy0, v4, -(gw[2] + gw[3]));
+                    float v2 = gw[0] * qs[0];
+                    float v5 = Ta[0] * gI0[0], v6 = Ta[0] * gI1[0], v7 = Ta[0] * gI2[0];
 #pragma unroll
-                        for (int p = 1; p < kQuad; ++p) {
-                            v2 = fmaf(gw[p], qs[p], v2);
-                            v5 = fmaf(Ta[p], gI0[p], v5);
-                            v6 = fmaf(Ta[p], gI1[p], v6);
-                            v7 = fmaf(Ta[p], gI2[p], v7);
-                        }
-                        {   // the 4 lanes of a group hold bitwise-equal sums and store them
-                            // to the same words, which keeps the reduction unconditional
-                            float v[7] = {v0, v1, v2, v4, v5, v6, v7};
-                            quad_sums(v);
-                            float *dst = my_part + nslots * kSlotStride;
-                            dst[0] = v[0]; dst[1] = v[1]; dst[2] = v[2];
-                            dst[4] = v[3]; dst[5] = v[4]; dst[6] = v[5]; dst[7] = v[6];
-                        }
-                        if (lane == j) s_gid[nslots] = id;
-                        if (++nslots == kSlots) {
-                            __syncthreads();     // staged sums are written before other lanes read them
-                            flush_slots(s_part, s_gid, kSlots, b.grad, lane);
-                            __syncthreads();     // and read before the slots are written again
-                            nslots = 0;
-                        }
+                    for (int p = 1; p < kQuad; ++p) {
+                        v2 = fmaf(gw[p], qs[p], v2);
+                        v5 = fmaf(Ta[p], gI0[p], v5);
+                        v6 = fmaf(Ta[p], gI1[p], v6);
+                        v7 = fmaf(Ta[p], gI2[p], v7);
                     }
+                    {   // the 4 lanes of a group hold bitwise-equal sums and store them
+                        // to the same words, which keeps the reduction unconditional
+                        float v[7] = {v0, v1, v2, v4, v5, v6, v7};
+                        quad_sums(v);
+                        float *dst = my_part + nslots * kSlotStride;
+                        dst[0] = v[0]; dst[1] = v[1]; dst[2] = v[2];
+                        dst[4] = v[3]; dst[5] = v[4]; dst[6] = v[5]; dst[7] = v[6];
+                    }
+                    if (lane == j) s_gid[nslots] = id;
+                    if (++nslots == kSlots) {
+                        __syncthreads();     // staged sums are written before other lanes read them
+                        flush_slots(s_part, s_gid, kSlots, b.grad, lane);
+                        __syncthreads();     // and read before the slots are written again
+                        nslots = 0;
+                    }
+                };
+                // Record j sits at byte 32 j of s_rec; the offset is kept in a VGPR (see
+                // in_vgpr): it addresses the LDS reads and takes part in the position
+                // test without SGPR operands.  The walk is unrolled by two over the
+                // register sets A and B: the record before the current one is read while
+                // the current one is processed, so the LDS latency overlaps the
+                // arithmetic.
+                const char *rb = reinterpret_cast<const char *>(s_rec);
+                int roff = in_vgpr(32 * (cnt - 1));
+                float4 a0 = *reinterpret_cast<const float4 *>(rb + roff);
+                float4 a1 = *reinterpret_cast<const float4 *>(rb + roff + 16);
+                for (int j = cnt - 1; j >= 0; j -= 2) {
+                    const int ra = roff;
+                    roff = in_vgpr(roff - 32);                  // record j - 1 (at least index -1)
+                    const float4 c0 = *reinterpret_cast<const float4 *>(rb + roff);
+                    const float4 c1 = *reinterpret_cast<const float4 *>(rb + roff + 16);
+                    splat(a0, a1, ra, j);
+                    if (j == 0) break;
+                    const int rc = roff;
+                    roff = in_vgpr(roff - 32);                  // record j - 2 (at least index -2)
+                    a0 = *reinterpret_cast<const float4 *>(rb + roff);
+                    a1 = *reinterpret_cast<const float4 *>(rb + roff + 16);
+                    splat(c0, c1, rc, j - 1);
                 }
+#pragma unroll
+                for (int p = 0; p < kQuad; ++p) lim[p] += 32 * kCompLanes;   // the previous chunk
                 if (!more) break;
                 cbeg -= kCompLanes;
             }
