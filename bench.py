@@ -36,6 +36,7 @@ PEAK_HBM = 8.0e12                 # B/s
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 FWD_OPS_PER_BLEND = 20            # lane-ops per blended (pixel, splat), forward composite
 BWD_OPS_PER_BLEND = 50            # lane-ops per blended (pixel, splat), backward composite
+EMIT_BYTES_PER_ITEM = 32          # bytes tile emission reads per depth-sorted item
 
 
 def log(*a):
@@ -47,6 +48,8 @@ def load_traffic(kernel: str, workload: str):
     profiles/traffic_<workload>.json, if it was taken on the current kernel
     sources; else None."""
     from paper_2205_14330_amd.profiling import kernel_source_hash
+    if workload is None:
+        return None
     p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(p):
         return None
@@ -212,18 +215,21 @@ def main():
     stage_ms = {s: 0.0 for s in dpr.STAGES}
     blend_acc = torch.zeros((), dtype=torch.int64, device=dev)
     pair_acc = [0]
+    item_acc = [0]
 
     def collect(p):
         for s_, v in p.stage_times().items():
             if v > 0:
                 stage_ms[s_] += v
         pair_acc[0] += p.info().pairs
+        item_acc[0] += p.info().items
 
     def reset():
         for s_ in stage_ms:
             stage_ms[s_] = 0.0
         blend_acc.zero_()
         pair_acc[0] = 0
+        item_acc[0] = 0
 
     # stage breakdown: every stage timed.  Each timed stage records two HIP
     # events on the stream, which stretch the step, so this loop is short and
@@ -239,6 +245,7 @@ def main():
     t_fb = timed(dpr.RenderParams(timing=True, timing_stages=(dom,), **base), True, args.steps,
                  args.warmup, collect, reset)
     pairs = pair_acc[0]
+    items = item_acc[0]
     K = args.steps
     # blended (pixel, splat) pairs of the timed steps, from the forward's
     # per-pixel counters in a pass of their own over the same views (the
@@ -263,20 +270,32 @@ def main():
         mpix_r = round(pix_step * K / t_r / 1e6, 2)
         log(f"fwd: {mpix_f} Mpix/s; fwd+bwd recompute: {mpix_r} Mpix/s")
 
-    # roofline of the dominant kernel (per launch = per step)
+    # roofline of the dominant kernel (per launch = per step); the committed PMC
+    # traffic summary covers the default workload only
     comp = {"composite_fwd": FWD_OPS_PER_BLEND, "composite_bwd": BWD_OPS_PER_BLEND}
+    traffic_wl = None if paper else "surface300k_4x800"
     if dom in comp:
         ops = comp[dom] * blends / K
         t_launch = stage_ms[dom] / K / 1e3
         achieved = ops / t_launch / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
                 "unit": "Tlane-op/s", "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4),
-                "traffic": load_traffic(dom, "surface300k_4x800"),
+                "traffic": load_traffic(dom, traffic_wl),
                 "per_unit": f"{comp[dom]} lane-ops per blended (pixel, splat)",
                 "units_per_launch": blends / K, "launch_ms": round(t_launch * 1e3, 4)}
+    elif dom == "emit":
+        # 4 B written per (tile, splat) pair; per depth-sorted item 32 B read
+        # (its index 4, tile rectangle 8, exponent record 20)
+        nbytes = (4.0 * pairs + EMIT_BYTES_PER_ITEM * items) / K
+        t_launch = stage_ms[dom] / K / 1e3
+        achieved = nbytes / t_launch / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": round(achieved * 1e9 / PEAK_HBM, 4), "traffic": load_traffic("tile_emit", traffic_wl),
+                "per_unit": f"4 B per (tile, splat) pair + {EMIT_BYTES_PER_ITEM} B per item",
+                "units_per_launch": {"pairs": pairs / K, "items": items / K}, "launch_ms": round(t_launch * 1e3, 4)}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": None, "traffic": load_traffic(dom, "surface300k_4x800")}
+                "frac": None, "traffic": load_traffic(dom, traffic_wl)}
 
     # the loss kernel alone (Eq. 8, one launch for the step's views): HBM-bound,
     # 36 algorithmic bytes per pixel (render and target read, gradient written)
@@ -480,7 +499,8 @@ def bench_warmstart(args):
                                "jittered by N(0, 0.01^2)", "points": n},
         "topk_sh_ms": round(t_topk * 1e3, 4), "adam_ms": round(t_adam * 1e3, 4),
         "warm_start_100_steps_ms": round(t_ws * 1e3, 2), "cd_before": cd0, "cd_after": cd1,
-        "roofline": {"kernel": "nn (both directions)", "bound": "alu", "achieved": round(achieved, 3),
+        "roofline": {"kernel": "dpr_chamfer call (k_nn in both directions and its reductions)", "bound": "alu",
+                     "achieved": round(achieved, 3),
                      "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
                      "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": None,
                      "per_unit": f"{NN_OPS_PER_PAIR} lane-ops per pair distance", "units_per_launch": pairs},

@@ -9,8 +9,14 @@ pmc_traffic():   HBM bytes per launch from two ``--pmc FETCH_SIZE`` and
                  largest ``copyBuffer`` dispatch), so the result is in bytes
                  actually moved.
 
+steady_stats():  per-kernel statistics from the ``*_kernel_trace.csv`` of the
+                 same run, over the launches from the first backward
+                 compositing launch on (set-up work such as rendering the
+                 training targets comes before it), with the blend-count
+                 forward variant named apart.
+
 Usage:
-  python -m paper_2205_14330_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>"
+  python -m paper_2205_14330_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>" [<kernel_trace.csv>]
   python -m paper_2205_14330_amd.profiling traffic <fetch.csv> <write.csv> <copy MiB> <out.json> "<command>"
 """
 from __future__ import annotations
@@ -38,6 +44,8 @@ KERNELS = {
     "dpr::k_col_down": "col_down",
     "dpr::k_tile_emit": "tile_emit",
     "dpr::k_composite_bwd": "composite_bwd",
+    "dpr::k_composite<false, true>": "composite_fwd_count",   # forward keeping blend counts
+    "dpr::k_composite<true, true>": "composite_fwd_count",
     "dpr::k_composite<": "composite_fwd",       # forward, and the backward's recompute pass
     "dpr::k_point_bwd": "point_bwd",
     "dpr::k_fill_u32": "fill",
@@ -77,14 +85,43 @@ def kernel_stats(stats_csv: str):
     return agg
 
 
-def write_stats_txt(stats_csv: str, out_txt: str, command: str):
-    agg = kernel_stats(stats_csv)
+def steady_stats(trace_csv: str):
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    first = next((int(r["Start_Timestamp"]) for r in rows if short_name(r["Kernel_Name"]) == "composite_bwd"), None)
+    agg = collections.OrderedDict()
+    for r in rows:
+        t0 = int(r["Start_Timestamp"])
+        if first is not None and t0 < first:
+            continue
+        d = float(int(r["End_Timestamp"]) - t0)
+        e = agg.setdefault(short_name(r["Kernel_Name"]), {"calls": 0, "total_ns": 0.0, "min_ns": float("inf"),
+                                                          "max_ns": 0.0})
+        e["calls"] += 1
+        e["total_ns"] += d
+        e["min_ns"] = min(e["min_ns"], d)
+        e["max_ns"] = max(e["max_ns"], d)
+    for e in agg.values():
+        e["avg_ns"] = e["total_ns"] / max(e["calls"], 1)
+    return collections.OrderedDict(sorted(agg.items(), key=lambda kv: -kv[1]["total_ns"]))
+
+
+def _table(agg):
     tot = sum(e["total_ns"] for e in agg.values())
-    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", f"# kernel sources: {kernel_source_hash()}",
-             "", f"{'kernel':48s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
+    lines = [f"{'kernel':48s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
     for n, e in agg.items():
         lines.append(f"{n:48s} {e['calls']:6d} {e['avg_ns'] / 1e3:10.2f} {e['min_ns'] / 1e3:10.2f} "
                      f"{e['max_ns'] / 1e3:10.2f} {100 * e['total_ns'] / tot:6.1f}")
+    return lines
+
+
+def write_stats_txt(stats_csv: str, out_txt: str, command: str, trace_csv: str = None):
+    agg = kernel_stats(stats_csv)
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", f"# kernel sources: {kernel_source_hash()}",
+             "", "## all launches of the run (--stats)"] + _table(agg)
+    if trace_csv:
+        lines += ["", "## launches from the first backward compositing launch on (--kernel-trace)"]
+        lines += _table(steady_stats(trace_csv))
     open(out_txt, "w").write("\n".join(lines) + "\n")
     return agg
 
@@ -117,7 +154,7 @@ def pmc_traffic(fetch_csv: str, write_csv: str, copy_mib: float):
 
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
-        agg = write_stats_txt(argv[1], argv[2], argv[3])
+        agg = write_stats_txt(argv[1], argv[2], argv[3], argv[4] if len(argv) >= 5 else None)
         print(json.dumps({k: round(v["avg_ns"] / 1e3, 2) for k, v in agg.items()}))
     elif len(argv) >= 6 and argv[0] == "traffic":
         res, fs, ws = pmc_traffic(argv[1], argv[2], float(argv[3]))

@@ -86,4 +86,13 @@ def test_small_budget_limits_batches(env):
     torch.cuda.synchronize()
     assert len(done) == 24 and all(r.error is None for r in done)
     assert srv.peak_in_use <= 2 * one                # the budget holds (exact bytes after planning)
-    assert max(srv.batches) <= 3                     # and keeps batches small
+    # and keeps batches small: a batch's requests, at their admission estimates,
+    # fit the budget (a single request always may).  How many that is depends on
+    # which requests are pending when a slot frees, i.e. on timing.
+    by_batch = {}
+    for r in done:
+        by_batch.setdefault(r.batch, []).append(r)
+    assert len(by_batch) == len(srv.batches) and max(srv.batches) < 24
+    for reqs in by_batch.values():
+        est = sum(ex.request_bytes(Request(0, r.scene, r.camera, 0.0)) for r in reqs)
+        assert len(reqs) == 1 or est <= 2 * one
