@@ -163,26 +163,44 @@ struct EmitItem {
     float px, py, a, b, thr;
 };
 
-__device__ __forceinline__ float rl(float v, uint32_t j) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+// The items of a batch of 64 are staged in LDS, one per lane, and each is read
+// back as an LDS broadcast: its fields then sit in VGPRs, and the arithmetic of
+// the tile test issues at the VGPR-operand rate (an SGPR operand, as left by a
+// readlane, costs about twice as much per instruction).
+struct EmitStage {
+    float4 shape;      // px, py, a, b
+    float4 misc;       // thr, 1 / w, g (bits), x0 | y0 << 16 (bits)
+    uint2 wn;          // w, n
+};
+
+__device__ __forceinline__ void stage_item(EmitStage &st, uint32_t g, uint32_t ra, uint32_t rb, const float4 &shape,
+                                           float thr) {
+    const uint32_t x0 = ra & 0xFFFFu, y0 = ra >> 16;
+    const uint32_t x1 = rb & 0xFFFFu, y1 = rb >> 16;
+    const uint32_t w = x1 > x0 ? x1 - x0 : 0u;
+    const uint32_t h = y1 > y0 ? y1 - y0 : 0u;
+    st.shape = shape;
+    st.misc = make_float4(thr, w ? __builtin_amdgcn_rcpf((float)w) : 0.f, __uint_as_float(g), __uint_as_float(ra));
+    st.wn = make_uint2(w, w * h);
 }
 
-__device__ __forceinline__ EmitItem emit_item(uint32_t g, uint32_t ra, uint32_t rb, const float4 &shape, float thr,
-                                              uint32_t j) {
+__device__ __forceinline__ EmitItem emit_item(const EmitStage *stage, uint32_t j) {
+    const EmitStage &st = stage[j];
+    const float4 shape = st.shape, misc = st.misc;
+    const uint2 wn = st.wn;
     EmitItem it;
-    it.px = rl(shape.x, j);
-    it.py = rl(shape.y, j);
-    it.a = rl(shape.z, j);
-    it.b = rl(shape.w, j);
-    it.thr = rl(thr, j);
-    it.g = g;
+    it.px = shape.x;
+    it.py = shape.y;
+    it.a = shape.z;
+    it.b = shape.w;
+    it.thr = misc.x;
+    it.inv_w = misc.y;
+    it.g = __float_as_uint(misc.z);
+    const uint32_t ra = __float_as_uint(misc.w);
     it.x0 = ra & 0xFFFFu;
     it.y0 = ra >> 16;
-    const uint32_t x1 = rb & 0xFFFFu, y1 = rb >> 16;
-    it.w = x1 > it.x0 ? x1 - it.x0 : 0u;
-    const uint32_t h = y1 > it.y0 ? y1 - it.y0 : 0u;
-    it.n = it.w * h;
-    it.inv_w = it.w ? __builtin_amdgcn_rcpf((float)it.w) : 0.f;
+    it.w = wn.x;
+    it.n = wn.y;
     return it;
 }
 
@@ -208,6 +226,7 @@ __global__ __launch_bounds__(kEmitLanes) void k_tile_emit(Tables tb, const uint3
                                                            const uint32_t *tile_base, uint32_t *pairs,
                                                            uint32_t band_tiles) {
     extern __shared__ uint32_t s_pos[];    // [band_tiles]
+    __shared__ EmitStage s_stage[kEmitLanes];
     const ChunkInfo ci = chunk_info(tb);
     const uint32_t lane = threadIdx.x;
     const uint32_t tx = (uint32_t)ci.tiles_x;
@@ -229,14 +248,15 @@ __global__ __launch_bounds__(kEmitLanes) void k_tile_emit(Tables tb, const uint3
                 shape = reinterpret_cast<const float4 *>(rec + g)[0];
                 thr = reinterpret_cast<const float4 *>(rec + g)[1].x + lambda;
             }
+            __syncthreads();                 // the previous batch's broadcasts are done (one wave: cheap)
+            stage_item(s_stage[lane], g, rc.x, rc.y, shape, thr);
+            __syncthreads();
             const uint32_t nb = min((uint32_t)kEmitLanes, ci.end - s0);
             uint32_t j = 0;
             for (; j + 4 <= nb; j += 4) {
                 EmitItem it[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    it[q] = emit_item(__builtin_amdgcn_readlane(g, j + q), __builtin_amdgcn_readlane(rc.x, j + q),
-                                      __builtin_amdgcn_readlane(rc.y, j + q), shape, thr, j + q);
+                for (int q = 0; q < 4; ++q) it[q] = emit_item(s_stage, j + q);
                 const uint32_t nmax = max(max(it[0].n, it[1].n), max(it[2].n, it[3].n));
                 if (nmax <= (uint32_t)kEmitLanes) {
                     uint32_t t[4], p[4];
@@ -265,11 +285,7 @@ __global__ __launch_bounds__(kEmitLanes) void k_tile_emit(Tables tb, const uint3
                     for (int q = 0; q < 4; ++q) emit_one(it[q], lane, tx, band, bend, s_pos, pairs);
                 }
             }
-            for (; j < nb; ++j) {
-                const EmitItem it = emit_item(__builtin_amdgcn_readlane(g, j), __builtin_amdgcn_readlane(rc.x, j),
-                                              __builtin_amdgcn_readlane(rc.y, j), shape, thr, j);
-                emit_one(it, lane, tx, band, bend, s_pos, pairs);
-            }
+            for (; j < nb; ++j) emit_one(emit_item(s_stage, j), lane, tx, band, bend, s_pos, pairs);
         }
         __syncthreads();
     }

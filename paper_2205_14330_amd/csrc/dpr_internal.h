@@ -134,8 +134,10 @@ __device__ __forceinline__ float splat_exponent(const SplatRec &s, float ux, flo
 __device__ __forceinline__ bool splat_touches_tile(float px, float py, float a, float b, float thr, uint32_t tx,
                                                    uint32_t ty) {
     const float x0 = (float)(tx * kTile) + 0.5f, y0 = (float)(ty * kTile) + 0.5f;
-    const float cx = fminf(fmaxf(px, x0), x0 + (float)(kTile - 1));
-    const float cy = fminf(fmaxf(py, y0), y0 + (float)(kTile - 1));
+    // the tile's pixel centre nearest to the splat centre: px clamped to
+    // [x0, x0 + 15] (med3 returns that same value, in one instruction)
+    const float cx = __builtin_amdgcn_fmed3f(px, x0, x0 + (float)(kTile - 1));
+    const float cy = __builtin_amdgcn_fmed3f(py, y0, y0 + (float)(kTile - 1));
     const float dx = cx - px, dy = cy - py;
     return a * dx * dx + b * dy * dy <= thr * (1.0f + 1.0f / 1024.0f) + 1.0e-6f;
 }

@@ -66,6 +66,12 @@ inline float __fadd_rn(float a, float b) { return a + b; }
 inline float __fsub_rn(float a, float b) { return a - b; }
 inline float __fmul_rn(float a, float b) { return a * b; }
 inline float __fdiv_rn(float a, float b) { return a / b; }
+// median of three (v_med3_f32 for finite operands)
+inline float __builtin_amdgcn_fmed3f(float a, float b, float c) {
+    const float lo = a < b ? a : b, hi = a < b ? b : a;
+    const float m = hi < c ? hi : c;
+    return lo < m ? m : lo;
+}
 inline float __fmaf_rn(float a, float b, float c) { return std::fma(a, b, c); }
 inline uint32_t __float_as_uint(float f) {
     uint32_t u;
