@@ -5,9 +5,8 @@
 // half w, two horizontally adjacent pixels per lane.  The tile's
 // depth-ordered list is consumed in chunks of 256 splat records gathered into
 // LDS (the next chunk is prefetched into registers while the current one is
-// processed) and read back as LDS broadcasts: the 20 bytes of the exponent
-// first, the colour only if some pixel of the wave blends.  The blend is
-// branch-free per pixel.  A pixel stops after the first blended splat that
+// processed) and read back as LDS broadcasts, each 32-byte record one record
+// ahead of its use.  The blend is branch-free per pixel.  A pixel stops after the first blended splat that
 // leaves T < t_min; a wave leaves the chunk once its 128 pixels have stopped,
 // and the workgroup leaves the list once all 256 have.
 //
@@ -22,10 +21,12 @@
 // colour blended behind (B = I_final - I_checkpoint at a segment end), and
 // folding each (pixel, splat) contribution into 7 per-lane partial sums.  A
 // chunk of 64 records is gathered one per lane, written to LDS and read back
-// as broadcasts.  The sums are reduced across each group of 4 lanes with
-// quad-permute swizzles (LDS pipe, so the VALU only adds), the 16 group sums of up to 8 splats are staged in LDS, and each flush
-// completes 56 sums and adds them to the per-item gradient records with one
-// 64-lane float atomic.
+// as broadcasts, one record ahead of its use.  T is recovered with one
+// reciprocal per lane and splat, of the product of the quad's four (1 - alpha).
+// The sums are reduced across each group of 4 lanes with quad-permute
+// swizzles (LDS pipe, so the VALU only adds), the 16 group sums of up to 8
+// splats are staged in LDS, and each flush completes 56 sums and adds them to
+// the per-item gradient records with one 64-lane float atomic.
 #include "dpr_internal.h"
 
 namespace dpr {
@@ -474,9 +475,22 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         for (int p = 0; p < kQuad; ++p)
                             if (alpha[p] > am) alpha[p] = am;    // only a blending pixel has alpha > 0
                     }
+                    // 1 / (1 - alpha) of the four pixels from one reciprocal of their
+                    // product (each factor >= 1 - alpha_max, so the product neither
+                    // underflows nor overflows): r = 1 / (o0 o1 o2 o3), 1 / o0 = r o1 o2 o3 ...
+                    float inv[kQuad];
+                    {
+                        const float o0 = 1.0f - alpha[0], o1 = 1.0f - alpha[1];
+                        const float o2 = 1.0f - alpha[2], o3 = 1.0f - alpha[3];
+                        const float p01 = o0 * o1, p23 = o2 * o3;
+                        const float r = __builtin_amdgcn_rcpf(p01 * p23);
+                        const float r01 = r * p23, r23 = r * p01;
+                        inv[0] = r01 * o1; inv[1] = r01 * o0;
+                        inv[2] = r23 * o3; inv[3] = r23 * o2;
+                    }
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
-                        const float iom = __builtin_amdgcn_rcpf(1.0f - alpha[p]);
+                        const float iom = inv[p];
                         T[p] = T[p] * iom;                       // T in front of this splat
                         Ta[p] = T[p] * alpha[p];
                         const float gc = fmaf(gI0[p], s.cr, fmaf(gI1[p], s.cg, gI2[p] * s.cb));
