@@ -10,6 +10,10 @@ IMG_TOL = 1e-4          # max-abs per pixel/channel, image and transmittance
 GRAD_RTOL = 1e-3        # per element, relative to max(|g*|, 1e-2 ||g*||_inf)
 GRAD_L2 = 1e-3          # ||g - g*||_2 / ||g*||_2
 
+# (name, worst element error as a fraction of its bound, rel-L2 as a fraction of
+# GRAD_L2) of every gradient comparison of the session, for the margin summary
+GRAD_MARGINS = []
+
 
 def torch_mod():
     import torch
@@ -66,6 +70,7 @@ def compare_grads(g, ref, name=""):
     bound = GRAD_RTOL * np.maximum(np.abs(r), 1e-2 * gmax)
     bad = np.abs(g - r) > bound
     l2 = np.linalg.norm(g - r) / np.linalg.norm(r)
+    GRAD_MARGINS.append((name, float(np.max(np.abs(g - r) / bound)), float(l2 / GRAD_L2)))
     assert not bad.any(), (f"{name}: {bad.sum()} of {r.size} elements off; worst "
                            f"{np.max(np.abs(g - r) / bound):.3g}x the bound; rel-L2 {l2:.3e}")
     assert l2 <= GRAD_L2, f"{name}: rel-L2 {l2:.3e}"
