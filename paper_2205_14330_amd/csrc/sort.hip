@@ -130,9 +130,55 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, 
     }
 }
 
+// Downsweep for a scan of few blocks: each block adds up the partials of the
+// blocks before it itself (at most kScanFewBlocks values), and the last block
+// writes the total, so no separate scan of the partials is launched.
+constexpr uint64_t kScanFewBlocks = 512;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down_few(const uint32_t *in, uint32_t *out, uint64_t n,
+                                                                const uint64_t *part, uint64_t *total64) {
+    __shared__ uint32_t s_wave[kScanThreads / 64];
+    __shared__ uint64_t s_pre[kScanThreads / 64];
+    uint64_t pre = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kScanThreads) pre += part[b];
+    pre = wave_sum_u64(pre);
+    if (__lane_id() == 0) s_pre[threadIdx.x >> 6] = pre;
+    __syncthreads();
+    uint64_t block_base = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) block_base += s_pre[w];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItemsPerThread;
+    uint32_t v[kScanItemsPerThread];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItemsPerThread; ++j) {
+        const uint64_t idx = base + j;
+        v[j] = idx < n ? in[idx] : 0u;
+        sum += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan_u32(sum, s_wave, &total) + (uint32_t)block_base;
+#pragma unroll
+    for (int j = 0; j < kScanItemsPerThread; ++j) {
+        const uint64_t idx = base + j;
+        if (idx < n) out[idx] = run;
+        run += v[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        const uint64_t t = block_base + total;
+        *total64 = t;
+        out[n] = (uint32_t)t;
+    }
+}
+
 hipError_t launch_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint64_t *part,
                        uint64_t *total64, hipStream_t st) {
     const uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb > 0 && nb <= kScanFewBlocks) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, part);
+        hipLaunchKernelGGL(k_scan_down_few, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, out, n, part, total64);
+        return hipGetLastError();
+    }
     if (nb > 0) {
         hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(kScanThreads), 0, st, in, n, part);
     }
