@@ -27,7 +27,6 @@ constexpr int kNnThreads = 256;
 constexpr int kNnQueries = 2;                          // queries per thread
 constexpr int kNnTile = 1024;                          // candidate points per LDS tile
 constexpr int kNnRange = 4096;                         // candidate points per block
-constexpr int kTopkThreads = 64;
 
 __device__ __forceinline__ float d2f(float ax, float ay, float az, float bx, float by, float bz) {
     const float a = ax - bx, b = ay - by, c = az - bz;
@@ -201,66 +200,108 @@ hipError_t launch_chamfer(uint32_t n1, const float *s1, uint32_t n2, const float
     return hipGetLastError();
 }
 
-// Top-k: thread = query y of S2; best[] = its K smallest keys over S1, ascending.
-__global__ __launch_bounds__(kTopkThreads) void k_topk_sh(const float *s1, const float *sh1, uint32_t n1,
-                                                          const float *s2, uint32_t n2, int k3, int K,
-                                                          float *out_sh, int32_t *idx) {
+// Top-k: a group of kTopkLanes consecutive lanes per query y of S2.  Lane s of
+// the group scans the candidates t = s mod kTopkLanes of every LDS tile of S1
+// and keeps the KM smallest keys (d2 bits << 32 | index, ascending) it met;
+// the group's lists are then merged by exchanging them between partner lanes
+// (xor 1, 2, 4).  The keys are distinct and totally ordered, so the K smallest
+// are found exactly, whatever the split.
+constexpr int kTopkLanes = 8;
+constexpr int kTopkBlock = 256;                          // 32 queries per block
+
+template <int KM>
+__device__ __forceinline__ void topk_insert(unsigned long long (&best)[KM], int K, unsigned long long x,
+                                            unsigned long long &worst) {
+    if (x >= worst) return;
+    // keep the smaller key in each place, carry the larger one on
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        if (k < K) {
+            const unsigned long long lo = best[k] < x ? best[k] : x;
+            x = best[k] < x ? x : best[k];
+            best[k] = lo;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k == K - 1) worst = best[k];
+}
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+template <int KM>
+__global__ __launch_bounds__(kTopkBlock) void k_topk_sh(const float *s1, const float *sh1, uint32_t n1,
+                                                        const float *s2, uint32_t n2, int k3, int K,
+                                                        float *out_sh, int32_t *idx) {
     __shared__ float s_x[kNnTile], s_y[kNnTile], s_z[kNnTile];
-    const uint32_t j = blockIdx.x * kTopkThreads + threadIdx.x;
+    const uint32_t sub = threadIdx.x % (uint32_t)kTopkLanes;
+    const uint32_t j = blockIdx.x * (uint32_t)(kTopkBlock / kTopkLanes) + threadIdx.x / (uint32_t)kTopkLanes;
     const uint32_t jj = j < n2 ? j : 0;
     const float qx = s2[3 * (size_t)jj], qy = s2[3 * (size_t)jj + 1], qz = s2[3 * (size_t)jj + 2];
-    unsigned long long best[kTopkMax];
+    unsigned long long best[KM];
 #pragma unroll
-    for (int k = 0; k < kTopkMax; ++k) best[k] = ~0ull;
+    for (int k = 0; k < KM; ++k) best[k] = ~0ull;
     unsigned long long worst = ~0ull;
     for (uint32_t t0 = 0; t0 < n1; t0 += kNnTile) {
         const uint32_t tn = min((uint32_t)kNnTile, n1 - t0);
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < tn; t += kTopkThreads) {
+        for (uint32_t t = threadIdx.x; t < tn; t += kTopkBlock) {
             s_x[t] = s1[3 * (size_t)(t0 + t)];
             s_y[t] = s1[3 * (size_t)(t0 + t) + 1];
             s_z[t] = s1[3 * (size_t)(t0 + t) + 2];
         }
         __syncthreads();
-        for (uint32_t t = 0; t < tn; ++t) {
+        for (uint32_t t = sub; t < tn; t += kTopkLanes) {
             const float d = d2f(qx, qy, qz, s_x[t], s_y[t], s_z[t]);
-            unsigned long long x = ((unsigned long long)__float_as_uint(d) << 32) | (t0 + t);
-            if (x >= worst) continue;
-            // insert: keep the smaller key in each place, carry the larger one on
-#pragma unroll
-            for (int k = 0; k < kTopkMax; ++k) {
-                if (k < K) {
-                    const unsigned long long lo = best[k] < x ? best[k] : x;
-                    x = best[k] < x ? x : best[k];
-                    best[k] = lo;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kTopkMax; ++k)
-                if (k == K - 1) worst = best[k];
+            topk_insert(best, K, ((unsigned long long)__float_as_uint(d) << 32) | (t0 + t), worst);
         }
     }
-    if (j >= n2) return;
+    // merge the group's lists: after the exchange with lane ^ m every lane of a
+    // pair holds the K smallest of both (all lanes take part in the shuffles)
+#pragma unroll
+    for (int m = 1; m < kTopkLanes; m <<= 1) {
+        unsigned long long other[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) other[k] = shfl_xor_u64(best[k], m);
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+            if (k < K) topk_insert(best, K, other[k], worst);
+    }
+    if (j >= n2 || sub != 0) return;
     const int kk = (int)min((uint32_t)K, n1);
     if (idx) {
 #pragma unroll
-        for (int k = 0; k < kTopkMax; ++k)
+        for (int k = 0; k < KM; ++k)
             if (k < K) idx[(size_t)j * K + k] = k < kk ? (int32_t)(uint32_t)(best[k] & 0xFFFFFFFFull) : -1;
     }
     for (int a = 0; a < k3; ++a) {
-        double s = 0.0;
+        double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < kTopkMax; ++k)
-            if (k < kk) s += (double)sh1[(size_t)k3 * (uint32_t)(best[k] & 0xFFFFFFFFull) + a];
-        out_sh[(size_t)k3 * j + a] = (float)(s / (double)kk);
+        for (int k = 0; k < KM; ++k)
+            if (k < kk) acc += (double)sh1[(size_t)k3 * (uint32_t)(best[k] & 0xFFFFFFFFull) + a];
+        out_sh[(size_t)k3 * j + a] = (float)(acc / (double)kk);
     }
 }
 
 hipError_t launch_topk_sh(uint32_t n1, const float *s1, const float *sh1, uint32_t n2, const float *s2, int k3, int K,
                           float *out_sh, int32_t *idx, hipStream_t st) {
     if (n2 == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_topk_sh, dim3((n2 + kTopkThreads - 1) / kTopkThreads), dim3(kTopkThreads), 0, st, s1, sh1,
-                       n1, s2, n2, k3, K, out_sh, idx);
+    if (K < 1 || K > kTopkMax) return hipErrorInvalidValue;
+    const dim3 grid((n2 + kTopkBlock / kTopkLanes - 1) / (kTopkBlock / kTopkLanes));
+    if (K <= 4) {
+        hipLaunchKernelGGL(k_topk_sh<4>, grid, dim3(kTopkBlock), 0, st, s1, sh1, n1, s2, n2, k3, K, out_sh, idx);
+    } else if (K <= 8) {
+        hipLaunchKernelGGL(k_topk_sh<8>, grid, dim3(kTopkBlock), 0, st, s1, sh1, n1, s2, n2, k3, K, out_sh, idx);
+    } else if (K <= 16) {
+        hipLaunchKernelGGL(k_topk_sh<16>, grid, dim3(kTopkBlock), 0, st, s1, sh1, n1, s2, n2, k3, K, out_sh, idx);
+    } else {
+        hipLaunchKernelGGL(k_topk_sh<kTopkMax>, grid, dim3(kTopkBlock), 0, st, s1, sh1, n1, s2, n2, k3, K, out_sh,
+                           idx);
+    }
     return hipGetLastError();
 }
 
