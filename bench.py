@@ -251,12 +251,23 @@ def main():
     # per-pixel counters in a pass of their own over the same views (the
     # forward is bitwise deterministic, so the counts are those of the timed
     # launches; counting inside the timed loop would add a reduction per step)
+    overheads = None
     for k in range(args.warmup, args.warmup + K):
         p = dpr.Plan([scene], [(0, c) for c in step_views[k]], dpr.RenderParams(stats=True, **base),
                      workspace=wss[k % 2])
         p.forward()
         inf = p.info()
-        blend_acc.add_(p.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32).sum())
+        nu = p.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32)
+        blend_acc.add_(nu.sum())
+        if k == args.warmup + K - 1:
+            # the overheads of the last step: blended splats per pixel n(u), tile list lengths
+            rng = p.plan_ws[inf.range_off: inf.range_off + 4 * (inf.tiles + 1)].view(torch.int32).long()
+            lens = (rng[1:] - rng[:-1]).float()
+            nuf = nu.float()
+            overheads = {"pairs": int(inf.pairs), "n_u_mean": round(float(nuf.mean()), 1),
+                         "n_u_p99": float(torch.quantile(nuf[:: max(1, nuf.numel() // 1000000)], 0.99)),
+                         "n_u_max": int(nu.max()), "list_len_mean": round(float(lens.mean()), 1),
+                         "list_len_max": int(lens.max())}
         p.free()
     blends = int(blend_acc.item())
     mpix_fb = pix_step * K / t_fb / 1e6
@@ -356,7 +367,7 @@ def main():
         "fwd_mpix_s": mpix_f, "fwd_bwd_mpix_s": round(mpix_fb, 2),
         "fwd_bwd_recompute_mpix_s": mpix_r,
         "stage_ms_per_step": {s_: round(v, 4) for s_, v in breakdown.items()},
-        "pairs_per_step": pairs / K, "blended_per_step": blends / K,
+        "pairs_per_step": pairs / K, "blended_per_step": blends / K, "step_overheads": overheads,
         "roofline": roof, "loss_kernel": loss_kernel, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(out), flush=True)
