@@ -55,7 +55,8 @@ def test_chamfer(exe, tmp_path, n1, n2, dup):
     check_chamfer(tmp_path, s1, s2)
 
 
-@pytest.mark.parametrize("n1,n2,K", [(2000, 300, 1), (2000, 300, 5), (1500, 129, 32), (3, 50, 8)])
+@pytest.mark.parametrize("n1,n2,K", [(2000, 300, 1), (2000, 300, 5), (1500, 160, 12), (1500, 129, 32), (3, 50, 8),
+                                       (7, 40, 16)])
 def test_topk(exe, tmp_path, n1, n2, K):
     s1, s2 = _clouds(n1, n2, K, dup=True)
     sh1 = workloads.point_attributes(n1, 2, K)[0]

@@ -53,7 +53,8 @@ def test_chamfer_matches_oracle(cf, n1, n2, dup):
     np.testing.assert_allclose(out["grad2"].cpu().numpy(), rg, rtol=1e-6, atol=1e-7 * np.abs(rg).max())
 
 
-@pytest.mark.parametrize("n1,n2,K", [(2000, 300, 1), (2000, 300, 5), (1500, 129, 32), (3, 50, 8), (6000, 1000, 4)])
+@pytest.mark.parametrize("n1,n2,K", [(2000, 300, 1), (2000, 300, 5), (1500, 160, 12), (1500, 129, 32), (3, 50, 8),
+                                       (7, 40, 16), (6000, 1000, 4)])
 def test_topk_sh_matches_oracle(cf, n1, n2, K):
     s1, s2 = _clouds(n1, n2, K, dup=True)
     sh1 = workloads.point_attributes(n1, 2, K)[0]
