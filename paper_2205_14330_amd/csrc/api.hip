@@ -64,7 +64,7 @@ struct Sizes {
 
 struct PlanLayout {
     Region views, scenes, u32tab, rec, keys, vals, keys_alt, vals_alt, rect, hist, part, cnt, segs, tile_total,
-        tile_base;
+        tile_base, tile_order, bucket_cnt;
     uint64_t total = 0;
 };
 
@@ -89,6 +89,8 @@ PlanLayout plan_layout(const Sizes &s) {
     p.segs = L.add(4 * s.segs);
     p.tile_total = L.add(4 * s.tiles);
     p.tile_base = L.add(4 * (s.tiles + 1));
+    p.tile_order = L.add(4 * s.tiles);
+    p.bucket_cnt = L.add(4ull * kOrderBuckets * order_count_blocks(s.tiles));
     p.total = L.total;
     return p;
 }
@@ -308,6 +310,7 @@ CompositeArgs composite_args(const dpr_plan *p, const void *ws) {
     a.rec = reinterpret_cast<const SplatRec *>(p->pws + p->lay.rec.off);
     a.pairs = reinterpret_cast<const uint32_t *>(w + f.pairs.off);
     a.tile_base = reinterpret_cast<const uint32_t *>(p->pws + p->lay.tile_base.off);
+    a.tile_order = reinterpret_cast<const uint32_t *>(p->pws + p->lay.tile_order.off);
     a.write_views = 0;
     a.stats = nullptr;
     a.nlast = nullptr;
@@ -614,8 +617,11 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
     }
     {
         StageScope sc_(p, DPR_STAGE_TILE_SCAN, st);
-        STAGE_TRY(launch_tile_colscan(tb, cnt, segs, tile_total, st));
+        uint32_t *bucket_cnt = reinterpret_cast<uint32_t *>(w + lay.bucket_cnt.off);
+        STAGE_TRY(launch_tile_colscan(tb, cnt, segs, tile_total, bucket_cnt, st));
         STAGE_TRY(launch_scan(tile_total, tile_base, s.tiles, part, total64, st));
+        STAGE_TRY(launch_tile_order(tile_total, (uint32_t)s.tiles, bucket_cnt,
+                                    reinterpret_cast<uint32_t *>(w + lay.tile_order.off), st));
     }
     STAGE_TRY(hipMemcpyAsync(p->total_host, total64, 8, hipMemcpyDeviceToHost, st));
     STAGE_TRY(hipStreamSynchronize(st));

@@ -116,17 +116,68 @@ __global__ __launch_bounds__(kColThreads) void k_col_segsum(Tables tb, const uin
     segs[c.seg_off + (uint64_t)s * c.ntiles + c.t] = sum;
 }
 
-__global__ __launch_bounds__(kColThreads) void k_col_segscan(Tables tb, uint32_t *segs, uint32_t *tile_total) {
+// Also counts the block's tiles per order bucket (bucket_cnt[block][kOrderBuckets]).
+__global__ __launch_bounds__(kColThreads) void k_col_segscan(Tables tb, uint32_t *segs, uint32_t *tile_total,
+                                                             uint32_t *bucket_cnt) {
+    __shared__ uint32_t s_b[kOrderBuckets];
+    if (threadIdx.x < (uint32_t)kOrderBuckets) s_b[threadIdx.x] = 0;
+    __syncthreads();
     const ColCtx c = col_ctx(tb);
-    if (!c.ok) return;
-    uint32_t run = 0;
-    for (uint32_t s = 0; s < c.nseg; ++s) {
-        uint32_t *p = segs + c.seg_off + (uint64_t)s * c.ntiles + c.t;
-        const uint32_t v = *p;
-        *p = run;
-        run += v;
+    if (c.ok) {
+        uint32_t run = 0;
+        for (uint32_t s = 0; s < c.nseg; ++s) {
+            uint32_t *p = segs + c.seg_off + (uint64_t)s * c.ntiles + c.t;
+            const uint32_t v = *p;
+            *p = run;
+            run += v;
+        }
+        tile_total[c.gtile] = run;
+        atomicAdd(&s_b[order_bucket(run)], 1u);
     }
-    tile_total[c.gtile] = run;
+    __syncthreads();
+    if (threadIdx.x < (uint32_t)kOrderBuckets)
+        bucket_cnt[(uint64_t)blockIdx.x * kOrderBuckets + threadIdx.x] = s_b[threadIdx.x];
+}
+
+uint64_t order_count_blocks(uint64_t tiles) { return (tiles + kColThreads - 1) / kColThreads; }
+
+// Same blocks of kColThreads tiles as k_col_segscan.  Bucket b starts after
+// every tile of the longer buckets and after bucket b's tiles of the earlier
+// blocks; inside a block the tiles of a bucket take its slots by LDS atomics.
+__global__ __launch_bounds__(kColThreads) void k_tile_order(const uint32_t *len, uint32_t n, const uint32_t *bucket_cnt,
+                                                            uint32_t nblk, uint32_t *order) {
+    __shared__ uint32_t s_tot[kOrderBuckets], s_before[kOrderBuckets], s_base[kOrderBuckets];
+    const uint32_t tid = threadIdx.x;
+    if (tid < (uint32_t)kOrderBuckets) {
+        uint32_t tot = 0, before = 0;
+#pragma unroll 8
+        for (uint32_t i = 0; i < nblk; ++i) {
+            const uint32_t v = bucket_cnt[(uint64_t)i * kOrderBuckets + tid];
+            tot += v;
+            before += i < blockIdx.x ? v : 0u;
+        }
+        s_tot[tid] = tot;
+        s_before[tid] = before;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b < kOrderBuckets; ++b) {
+            s_base[b] = run + s_before[b];
+            run += s_tot[b];
+        }
+    }
+    __syncthreads();
+    const uint32_t t = blockIdx.x * kColThreads + tid;
+    if (t < n) order[atomicAdd(&s_base[order_bucket(len[t])], 1u)] = t;
+}
+
+hipError_t launch_tile_order(const uint32_t *len, uint32_t n, const uint32_t *bucket_cnt, uint32_t *order,
+                             hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const uint32_t nblk = (uint32_t)order_count_blocks(n);
+    hipLaunchKernelGGL(k_tile_order, dim3(nblk), dim3(kColThreads), 0, st, len, n, bucket_cnt, nblk, order);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kColThreads) void k_col_down(Tables tb, uint32_t *cnt, const uint32_t *segs) {
@@ -144,12 +195,12 @@ __global__ __launch_bounds__(kColThreads) void k_col_down(Tables tb, uint32_t *c
 }
 
 hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, uint32_t *tile_total,
-                               hipStream_t st) {
+                               uint32_t *bucket_cnt, hipStream_t st) {
     if (tb.total_tiles == 0) return hipSuccess;
     const uint32_t bx = (tb.total_tiles + kColThreads - 1) / kColThreads;
     const uint32_t ns = tb.max_view_segs > 0 ? tb.max_view_segs : 1;
     hipLaunchKernelGGL(k_col_segsum, dim3(bx, ns), dim3(kColThreads), 0, st, tb, cnt, segs);
-    hipLaunchKernelGGL(k_col_segscan, dim3(bx), dim3(kColThreads), 0, st, tb, segs, tile_total);
+    hipLaunchKernelGGL(k_col_segscan, dim3(bx), dim3(kColThreads), 0, st, tb, segs, tile_total, bucket_cnt);
     hipLaunchKernelGGL(k_col_down, dim3(bx, ns), dim3(kColThreads), 0, st, tb, cnt, segs);
     return hipGetLastError();
 }

@@ -133,7 +133,9 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     const float t_min = in_vgpr(a.th.t_min);
     const uint32_t cap = in_vgpr(a.th.max_splats > 0 ? a.th.max_splats : 0xFFFFFFFFu);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (uint32_t tile = PERSISTENT ? blockIdx.x : xcd_remap(blockIdx.x, a.total_tiles); tile < a.total_tiles;) {
+    // block (or popped) index -> tile: through the longest-first order when there is one
+    for (uint32_t idx = blockIdx.x; idx < a.total_tiles;) {
+        const uint32_t tile = a.tile_order ? a.tile_order[idx] : (PERSISTENT ? idx : xcd_remap(idx, a.total_tiles));
         const int v = find_segment(a.tile_start, a.n_views, tile);
         const ViewDesc &vd = a.views[v];
         const uint32_t lt = tile - vd.tile_off;
@@ -293,9 +295,10 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
         __syncthreads();
         if (tid == 0) s_next = atomicAdd(a.counters, 1u) + gridDim.x;
         __syncthreads();
-        tile = s_next;
+        idx = s_next;
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // backward

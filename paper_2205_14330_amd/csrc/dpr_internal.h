@@ -183,7 +183,7 @@ hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *
 // In place: cnt[c][t] -> sum of cnt[c'][t] over c' < c; tile_total[tile] = column sum.
 // segs: scratch of sum over views of tiles * segments u32.
 hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, uint32_t *tile_total,
-                               hipStream_t st);
+                               uint32_t *bucket_cnt, hipStream_t st);
 // tile_base = exclusive scan of tile_total (tiles + 1 entries).
 hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
                             const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
@@ -208,6 +208,7 @@ struct CompositeArgs {
     const SplatRec *rec;
     const uint32_t *pairs;
     const uint32_t *tile_base;  // [tiles + 1] first pair of each tile
+    const uint32_t *tile_order; // [tiles] the order in which the forward takes the tiles, or null
     int write_views;            // 1: write image / trans / stats of each view
     uint32_t *stats;            // per-pixel blended count (or null)
     // backward state (all null for a forward that no backward will follow)
@@ -219,6 +220,19 @@ struct CompositeArgs {
     Thresholds th;
 };
 hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st);
+// The forward takes the tiles longest pair list first: a tile's compositing
+// time grows with the list positions it visits, and the kernel's end is set by
+// the last long tile to start.  The length ranks that work only roughly (early
+// termination), so the order is by bucket: the bit length of the length,
+// longest first.  k_col_segscan counts each block's tiles per bucket; the
+// order kernel places them (the order of tiles within a bucket changes no
+// result).
+constexpr int kOrderBuckets = 33;            // bit lengths 32 .. 0
+__device__ __forceinline__ uint32_t order_bucket(uint32_t len) { return len ? (uint32_t)__clz(len) : 32u; }
+uint64_t order_count_blocks(uint64_t tiles);
+// order[] = the n tiles, longest list first, from the per-block bucket counts of k_col_segscan
+hipError_t launch_tile_order(const uint32_t *len, uint32_t n, const uint32_t *bucket_cnt, uint32_t *order,
+                             hipStream_t st);
 
 struct BackwardArgs {
     CompositeArgs c;

@@ -72,6 +72,8 @@ inline float __builtin_amdgcn_fmed3f(float a, float b, float c) {
     const float m = hi < c ? hi : c;
     return lo < m ? m : lo;
 }
+// leading zero bits of a 32-bit word (32 for zero)
+inline int __clz(unsigned x) { return x ? __builtin_clz(x) : 32; }
 inline float __fmaf_rn(float a, float b, float c) { return std::fma(a, b, c); }
 inline uint32_t __float_as_uint(float f) {
     uint32_t u;
