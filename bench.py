@@ -76,13 +76,14 @@ def cpu_baseline(scene, cams, targets_fn, max_splats=0, kernel_norm=0, lam=0.0):
         oracle.backward(scene, [cam], [gI], None, params=op, threads=cores)
         pix += cam.pixels
     dt = time.perf_counter() - t0
+    used = min(cores, oracle.max_threads())    # read before the one-thread run resets it
     # the same work on one thread, for the first view only (a quarter of the step)
     t1 = time.perf_counter()
     r = oracle.render(scene, cams[0], op, threads=1)
     _, gI = oracle.loss_l2_tv(r.image, targets_fn(0), lam)
     oracle.backward(scene, [cams[0]], [gI], None, params=op, threads=1)
     dt1 = time.perf_counter() - t1
-    return {"value": pix / dt / 1e6, "unit": "Mpix/s", "cores": min(cores, oracle.max_threads()), "kind": "oracle",
+    return {"value": pix / dt / 1e6, "unit": "Mpix/s", "cores": used, "kind": "oracle",
             "sample": f"one full step: {len(cams)} views x {cams[0].width}x{cams[0].height}, fwd+bwd, "
                       f"FP64, {dt:.1f} s",
             "one_thread": {"value": cams[0].pixels / dt1 / 1e6, "unit": "Mpix/s",

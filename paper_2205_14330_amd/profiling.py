@@ -42,6 +42,7 @@ KERNELS = {
     "dpr::k_col_segsum": "col_segsum",
     "dpr::k_col_segscan": "col_segscan",
     "dpr::k_col_down": "col_down",
+    "dpr::k_tile_order": "tile_order",
     "dpr::k_tile_emit": "tile_emit",
     "dpr::k_composite_bwd": "composite_bwd",
     "dpr::k_composite<false, true>": "composite_fwd_count",   # forward keeping blend counts
@@ -49,6 +50,9 @@ KERNELS = {
     "dpr::k_composite<": "composite_fwd",       # forward, and the backward's recompute pass
     "dpr::k_point_bwd": "point_bwd",
     "dpr::k_fill_u32": "fill",
+    "dpr::k_loss_sum": "loss_sum",
+    "dpr::k_loss": "loss",
+    "dpr::k_upload": "upload",
 }
 
 
