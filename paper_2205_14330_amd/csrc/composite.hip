@@ -211,8 +211,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                     bool any = false;
 #pragma unroll
                     for (int p = 0; p < PX; ++p) {
-                        float dx, dy, q;
-                        e[p] = splat_exponent(s, ux[p], uy[p], dx, dy, q);
+                        float dx, dy;
+                        e[p] = splat_exponent(s, ux[p], uy[p], dx, dy);
                         hit[p] = (T[p] >= t_min) & (!COUNT || nblend[p] < cap) & (e[p] >= neg_lambda);
                         any = any || hit[p];
                     }
@@ -443,14 +443,14 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                     SplatRec s;
                     s.px = f0.x; s.py = f0.y; s.a = f0.z; s.b = f0.w;
                     s.w = f1.x;
-                    float gw[kQuad], Ta[kQuad], e[kQuad], g[kQuad], alpha[kQuad], qs[kQuad];
+                    float gw[kQuad], Ta[kQuad], e[kQuad], g[kQuad], alpha[kQuad];
                     float dx0 = 0.f, dy0 = 0.f;
                     bool hit[kQuad];
                     bool any = false;
 #pragma unroll
                     for (int p = 0; p < kQuad; ++p) {
                         float dx, dy;
-                        e[p] = splat_exponent(s, ux[p], uy[p], dx, dy, qs[p]);
+                        e[p] = splat_exponent(s, ux[p], uy[p], dx, dy);
                         if (p == 0) { dx0 = dx; dy0 = dy; }
                         hit[p] = (ro < lim[p]) & (e[p] >= neg_lambda);
                         any = any || hit[p];
@@ -513,11 +513,13 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                     const float v4 = gx + gz;
                     const float v0 = fmaf(dx0, v4, -gx);
                     const float v1 = fmaf(dy0, v4, -(gw[2] + gw[3]));
-                    float v2 = gw[0] * qs[0];
+                    // sum of gw q with q = w - e: w sum(gw) - sum(gw e)
+                    float v2 = s.w * v4;
                     float v5 = Ta[0] * gI0[0], v6 = Ta[0] * gI1[0], v7 = Ta[0] * gI2[0];
 #pragma unroll
-                    for (int p = 1; p < kQuad; ++p) {
-                        v2 = fmaf(gw[p], qs[p], v2);
+                    for (int p = 0; p < kQuad; ++p) {
+                        v2 = fmaf(-gw[p], e[p], v2);
+                        if (p == 0) continue;
                         v5 = fmaf(Ta[p], gI0[p], v5);
                         v6 = fmaf(Ta[p], gI1[p], v6);
                         v7 = fmaf(Ta[p], gI2[p], v7);

@@ -116,14 +116,14 @@ __device__ __forceinline__ float depth_z(const float *R, const float *t, float x
 }
 
 // Exponent of the splat opacity: e = w - (a dx^2 + b dy^2); alpha = 2^e.
-// Written with explicit rounding so every kernel that re-evaluates a splat
-// (forward, recompute, backward) takes bit-identical decisions.
-__device__ __forceinline__ float splat_exponent(const SplatRec &s, float ux, float uy, float &dx, float &dy,
-                                                float &q) {
+// Evaluated as (w - b dy^2) - a dx^2 with two FMAs: the row term w - b dy^2 is
+// shared by the pixels of a row.  Written with explicit rounding so every
+// kernel that re-evaluates a splat (forward, recompute, backward) takes
+// bit-identical decisions.
+__device__ __forceinline__ float splat_exponent(const SplatRec &s, float ux, float uy, float &dx, float &dy) {
     dx = __fsub_rn(s.px, ux);
     dy = __fsub_rn(s.py, uy);
-    q = __fmaf_rn(s.a, __fmul_rn(dx, dx), __fmul_rn(s.b, __fmul_rn(dy, dy)));
-    return __fsub_rn(s.w, q);
+    return __fmaf_rn(-s.a, __fmul_rn(dx, dx), __fmaf_rn(-s.b, __fmul_rn(dy, dy), s.w));
 }
 
 // Conservative test of whether any pixel centre of tile (tx, ty) can pass the
