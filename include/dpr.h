@@ -156,7 +156,9 @@ typedef struct dpr_plan_info {
     int64_t range_off;       /* [tiles + 1] u32: tile t's list is pairs[range[t] .. range[t+1]) */
     /* byte offsets inside the forward workspace */
     int64_t pairs_off;       /* [pairs] u32 item ids, grouped by tile, depth order within */
-    int64_t nlast_off;       /* [pixels] u32 stop index (stored mode), -1 if absent       */
+    int64_t nlast_off;       /* [pixels] u32 blend end (stored mode), -1 if absent: one
+                                past the list position of the pixel's last blended splat,
+                                0 if it blended none                                      */
     int64_t stats_off;       /* [pixels] u32 blended splats per pixel, -1 if absent       */
     int32_t tile_size;       /* 16                                                        */
     int32_t chunk_items;     /* items per binning chunk                                   */
@@ -189,7 +191,7 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes,
 
 /* Bytes of the forward workspace, known after dpr_plan_forward: the per-tile
  * pair lists and, in stored mode, the state the backward reads (per pixel the
- * stop index and final (T, I); per tile a (T, I) checkpoint of every pixel each
+ * blend end and final (T, I); per tile a (T, I) checkpoint of every pixel each
  * 256 list positions; the backward's work items), up to 16 B per pair + 20 B
  * per pixel on top of the 4 B per pair of the lists. */
 size_t dpr_workspace_bytes(const dpr_plan *plan);
@@ -210,7 +212,7 @@ size_t dpr_backward_ws_bytes(const dpr_plan *plan);
  *   dL_dxyz[s]    [n][3]     } per scene, OVERWRITTEN with the sum over every
  *   dL_dsh[s]     [n][K][3]  } view of the scene; a NULL array pointer (or a NULL
  *   dL_dopacity[s][n]        } table) skips that output.
- * Candidate sets, depth order and stop index are held fixed (piecewise-constant
+ * Candidate sets, depth order and the splats each pixel blends are held fixed (piecewise-constant
  * structure); clamped alphas pass no gradient to o or the position.  The
  * forward state is not modified, so backward may be called more than once. */
 int dpr_render_backward(dpr_plan *plan, const void *ws, size_t ws_bytes,

@@ -16,7 +16,7 @@
 // checkpoint of every pixel's (T, I), so the segments of one long list are
 // processed independently and in parallel (the longest tiles no longer set
 // the kernel's duration).  A segment is walked in reverse from its end (or the
-// furthest stop index in it), recovering T_i = T_{i+1} / (1 - alpha_i)
+// furthest blend end in it), recovering T_i = T_{i+1} / (1 - alpha_i)
 // (alpha <= alpha_max < 1), carrying D = dL/dI . B + dL/dT T_final with B the
 // colour blended behind (B = I_final - I_checkpoint at a segment end), and
 // folding each (pixel, splat) contribution into 7 per-lane partial sums.  A
@@ -112,9 +112,13 @@ constexpr int kFwdChunk = 2 * kFwdThreads;
 // test is exactly the stop rule.  Pixels outside the image start at T = -1.
 //
 // With backward state requested (a.nlast non-null) the kernel also writes,
-// per pixel, the stop index and the final (T, I); at every list position
-// s * kBwdSeg it reaches, the (T, I) checkpoint of each pixel; and it appends
-// the tile's backward work items (tile, s) for s < ceil(max stop / kBwdSeg).
+// per pixel, its blend end (one past the list position of the last splat it
+// blended, 0 if none: no later splat changes the pixel) and the final (T, I);
+// at every list position s * kBwdSeg it reaches, the (T, I) checkpoint of
+// each pixel; and it appends the tile's backward work items (tile, s) for
+// s < ceil(max blend end / kBwdSeg).  Within a chunk a pixel keeps the LDS
+// offset of its last blended record, which is already in a VGPR; the list
+// position is formed once per chunk.
 static_assert(kBwdSeg % kFwdChunk == 0, "backward segments are whole forward chunks");
 
 // COUNT: the kernel counts each pixel's blended splats, for the per-pixel
@@ -146,6 +150,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
         const int x0 = (int)(tx * kTile) + lx, y0 = (int)(ty * kTile) + ly;
         float ux[PX], uy[PX], T[PX], I0[PX], I1[PX], I2[PX];
         uint32_t nlast[PX], nblend[PX];
+        int last[PX];                     // LDS byte offset of the last blended record of this chunk, or -1
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
             const int px = x0 + p, py = y0;
@@ -153,7 +158,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             uy[p] = (float)py + 0.5f;
             T[p] = (px < vd.width && py < vd.height) ? 1.f : -1.f;
             I0[p] = I1[p] = I2[p] = 0.f;
-            nlast[p] = end - start; nblend[p] = 0;
+            nlast[p] = 0; nblend[p] = 0; last[p] = -1;
         }
         float4 n0[2], n1[2];
 #pragma unroll
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                 // overlaps the arithmetic.  The whole record is read ahead (a later
                 // read of the colour would have to wait for the read-ahead as well).
                 const char *b0 = reinterpret_cast<const char *>(s_r0), *b1 = reinterpret_cast<const char *>(s_r1);
-                auto blend = [&](const float4 &r0, const float4 &r1, int j) {
+                auto blend = [&](const float4 &r0, const float4 &r1, int ro) {
                     SplatRec s;
                     s.px = r0.x; s.py = r0.y; s.a = r0.z; s.b = r0.w;
                     s.w = r1.x;
@@ -220,7 +225,6 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                     s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
                     // branch-free over the lane's pixels: alpha = 0 leaves a pixel
                     // that does not blend this splat exactly unchanged
-                    const uint32_t pos1 = base - start + (uint32_t)j + 1;
                     float alpha[PX];
 #pragma unroll
                     for (int p = 0; p < PX; ++p) alpha[p] = hit[p] ? __builtin_amdgcn_exp2f(e[p]) : 0.f;
@@ -238,24 +242,32 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                         I2[p] = fmaf(Ta, s.cb, I2[p]);
                         if (COUNT) nblend[p] += hit[p] ? 1u : 0u;
                         T[p] = T[p] - Ta;                           // T (1 - alpha)
-                        if (hit[p] & ((T[p] < t_min) | (COUNT && nblend[p] == cap))) nlast[p] = pos1;
+                        if (hit[p]) last[p] = ro;
                     }
                 };
                 int roff = in_vgpr(16 * j0);
                 float4 a0 = *reinterpret_cast<const float4 *>(b0 + roff);
                 float4 a1 = *reinterpret_cast<const float4 *>(b1 + roff);
                 for (int j = j0; j < jn; j += 2) {
+                    const int ra = roff;
                     roff = in_vgpr(roff + 16);                      // record j + 1 (at most index kChunk)
                     const float4 c0 = *reinterpret_cast<const float4 *>(b0 + roff);
                     const float4 c1 = *reinterpret_cast<const float4 *>(b1 + roff);
-                    blend(a0, a1, j);
+                    blend(a0, a1, ra);
                     if (j + 1 >= jn) break;
+                    const int rc = roff;
                     roff = in_vgpr(roff + 16);                      // record j + 2 (at most index kChunk + 1)
                     a0 = *reinterpret_cast<const float4 *>(b0 + roff);
                     a1 = *reinterpret_cast<const float4 *>(b1 + roff);
-                    blend(c0, c1, j + 1);
+                    blend(c0, c1, rc);
                 }
             }
+#pragma unroll
+            for (int p = 0; p < PX; ++p)
+                if (last[p] >= 0) {
+                    nlast[p] = base - start + (uint32_t)last[p] / 16u + 1u;
+                    last[p] = -1;
+                }
             bool any_live = false;
 #pragma unroll
             for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!COUNT || nblend[p] < cap));
@@ -281,7 +293,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             }
         }
         if (a.nlast) {
-            // the tile's backward work items: one per kBwdSeg positions below its largest stop index
+            // the tile's backward work items: one per kBwdSeg positions below its largest blend end
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) mymax = max(mymax, (uint32_t)__shfl_xor((int)mymax, d, 64));
             if (lane == 0) s_max[wave] = mymax;
@@ -399,7 +411,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 gI0[p] = gi[0]; gI1[p] = gi[1]; gI2[p] = gi[2];
                 const float gT = (b.dtrans && b.dtrans[c.v]) ? b.dtrans[c.v][lpix] : 0.f;
                 if (nl[p] > seg_end) {
-                    // live past this segment: B = I_final - (I after the first seg_end splats)
+                    // blends past this segment: B = I_final - (I after the first seg_end splats)
                     const float4 k = ck[(py - (c.y0 & ~(kTile - 1))) * kTile + (px - (c.x0 & ~(kTile - 1)))];
                     T[p] = k.x;
                     D[p] = fmaf(gI0[p], f.y - k.y, fmaf(gI1[p], f.z - k.z, fmaf(gI2[p], f.w - k.w, gT * f.x)));
