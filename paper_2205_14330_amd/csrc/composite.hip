@@ -72,8 +72,10 @@ __device__ __forceinline__ TileCtx tile_ctx(const CompositeArgs &a, uint32_t til
 // The exponent never exceeds the record's w (its quadratic form is >= 0), so a
 // splat whose peak 2^w stays below alpha_max clamps no pixel; w_noclamp puts
 // that test a margin of 2^-1e-5 (about 58 float ulps) inside alpha_max, far
-// above the error of exp2 and log2, and the compositing loops apply the clamp
-// only on the rare path where w exceeds it.
+// above the error of exp2 and log2.  The forward flags each staged chunk that
+// holds a record with w above it and applies the clamp to every record of a
+// flagged chunk only (a no-op for the others), so the common chunk pays no
+// per-record test; the backward tests w per record, on a path of its own.
 __device__ __forceinline__ float no_clamp_w(float alpha_max) { return __log2f(alpha_max) - 1e-5f; }
 
 // Record k of the pair list, or an inert record past the end.
@@ -125,7 +127,9 @@ static_assert(kBwdSeg % kFwdChunk == 0, "backward segments are whole forward chu
 // statistics and for the cap th.max_splats: a pixel also stops after blending
 // that many (then it is live while T >= t_min and fewer than max_splats splats
 // were blended).  Without a cap the count never reaches cap = 2^32 - 1.
-template <bool PERSISTENT, bool COUNT>
+// STATE: backward state is requested (a.nlast non-null); without it the
+// kernel keeps no blend ends.
+template <bool PERSISTENT, bool COUNT, bool STATE>
 __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     constexpr int PX = kFwdPx, kThreads = kFwdThreads, kChunk = kFwdChunk;
     // two padding records: the read-ahead reaches index kChunk + 1
@@ -172,18 +176,23 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             }
         }
         for (uint32_t base = start; base < end; base += kChunk) {
-            if (a.ckpt && base > start && (base - start) % (uint32_t)kBwdSeg == 0) {
+            if (STATE && a.ckpt && base > start && (base - start) % (uint32_t)kBwdSeg == 0) {
                 float4 *dst = a.ckpt + ckpt_slot(start, tile, (base - start) / (uint32_t)kBwdSeg) * kTilePix +
                               ly * kTile + lx;
 #pragma unroll
                 for (int p = 0; p < PX; ++p) dst[p] = make_float4(T[p], I0[p], I1[p], I2[p]);
             }
+            // the chunk flag: may any of its records reach the alpha_max clamp
+            // (records past the list end are never blended; a stale one only
+            // sets the flag needlessly)
+            bool near = false;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 s_r0[h * kThreads + tid] = n0[h];
                 s_r1[h * kThreads + tid] = n1[h];
+                near = near || n1[h].x > w_noclamp;
             }
-            __syncthreads();
+            const bool chunk_clamp = __syncthreads_or(near);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const uint32_t k = base + kChunk + h * kThreads + tid;
@@ -228,7 +237,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                     float alpha[PX];
 #pragma unroll
                     for (int p = 0; p < PX; ++p) alpha[p] = hit[p] ? __builtin_amdgcn_exp2f(e[p]) : 0.f;
-                    if (__builtin_expect(s.w > w_noclamp, 0)) {
+                    if (__builtin_expect(chunk_clamp, 0)) {
                         const float am = in_vgpr(alpha_max);         // read here so the compares stay here
 #pragma unroll
                         for (int p = 0; p < PX; ++p)
@@ -242,7 +251,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                         I2[p] = fmaf(Ta, s.cb, I2[p]);
                         if (COUNT) nblend[p] += hit[p] ? 1u : 0u;
                         T[p] = T[p] - Ta;                           // T (1 - alpha)
-                        if (hit[p]) last[p] = ro;
+                        if (STATE && hit[p]) last[p] = ro;
                     }
                 };
                 int roff = in_vgpr(16 * j0);
@@ -264,7 +273,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             }
 #pragma unroll
             for (int p = 0; p < PX; ++p)
-                if (last[p] >= 0) {
+                if (STATE && last[p] >= 0) {
                     nlast[p] = base - start + (uint32_t)last[p] / 16u + 1u;
                     last[p] = -1;
                 }
@@ -286,13 +295,13 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                 if (vd.trans) vd.trans[lpix] = T[p];
                 if (COUNT && a.stats) a.stats[pix] = nblend[p];
             }
-            if (a.nlast) {
+            if (STATE) {
                 a.nlast[pix] = nlast[p];
                 a.fin[pix] = make_float4(T[p], I0[p], I1[p], I2[p]);
                 mymax = max(mymax, nlast[p]);
             }
         }
-        if (a.nlast) {
+        if (STATE) {
             // the tile's backward work items: one per kBwdSeg positions below its largest blend end
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) mymax = max(mymax, (uint32_t)__shfl_xor((int)mymax, d, 64));
@@ -599,21 +608,24 @@ static uint32_t persistent_grid(uint32_t tiles, uint32_t per_cu) {
     return tiles < g ? tiles : g;
 }
 
-template <bool COUNT>
+template <bool COUNT, bool STATE>
 static void launch_fwd(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (persistent) {
-        hipLaunchKernelGGL((k_composite<true, COUNT>), dim3(persistent_grid(a.total_tiles, 8)), dim3(kFwdThreads), 0,
-                           st, a);
+        hipLaunchKernelGGL((k_composite<true, COUNT, STATE>), dim3(persistent_grid(a.total_tiles, 8)),
+                           dim3(kFwdThreads), 0, st, a);
     } else {
-        hipLaunchKernelGGL((k_composite<false, COUNT>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
+        hipLaunchKernelGGL((k_composite<false, COUNT, STATE>), dim3(a.total_tiles), dim3(kFwdThreads), 0, st, a);
     }
 }
 
 hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st) {
     if (a.total_tiles == 0) return hipSuccess;
-    // the blend count is kept only where the cap or the statistics need it
-    if (a.th.max_splats > 0 || (a.write_views && a.stats)) launch_fwd<true>(a, persistent, st);
-    else launch_fwd<false>(a, persistent, st);
+    // the blend count is kept only where the cap or the statistics need it,
+    // the blend ends only where a backward follows
+    const bool count = a.th.max_splats > 0 || (a.write_views && a.stats);
+    const bool state = a.nlast != nullptr;
+    if (count) state ? launch_fwd<true, true>(a, persistent, st) : launch_fwd<true, false>(a, persistent, st);
+    else state ? launch_fwd<false, true>(a, persistent, st) : launch_fwd<false, false>(a, persistent, st);
     return hipGetLastError();
 }
 
