@@ -444,12 +444,14 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
             float4 n0, n1;
             uint32_t nid;
             load_rec(a, cbeg + lane, lend, n0, n1, nid);
-            // Pixel p blended the record at list position cbeg - start + j iff that
-            // position is below nl[p], i.e. iff 32 j < lim[p] = 32 (nl[p] - (cbeg -
-            // start)) for the current chunk; lim grows by 32 * 64 per chunk back.
+            // Pixel p may have blended the record at list position cbeg - start + j
+            // only if that position is below nl[p], i.e. iff 32 (j - 1) < lim[p] =
+            // 32 (nl[p] - (cbeg - start) - 1) for the current chunk: the test takes
+            // the byte offset of record j - 1, which the walk already holds for its
+            // read-ahead.  lim grows by 32 * 64 per chunk back.
             int lim[kQuad];
 #pragma unroll
-            for (int p = 0; p < kQuad; ++p) lim[p] = 32 * ((int)nl[p] - (int)(cbeg - c.start));
+            for (int p = 0; p < kQuad; ++p) lim[p] = 32 * ((int)nl[p] - (int)(cbeg - c.start) - 1);
             while (true) {
                 const uint32_t id = nid;
                 __syncthreads();                 // the previous chunk's broadcasts are done
@@ -459,7 +461,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 const bool more = cbeg > sbeg;
                 if (more) load_rec(a, cbeg - kCompLanes + lane, lend, n0, n1, nid);
                 const int cnt = (int)min((uint32_t)kCompLanes, lend - cbeg);
-                // one (pixel, splat) record of the walk: record j at byte offset ro
+                // one (pixel, splat) record of the walk: record j, whose predecessor sits at byte offset ro
                 auto splat = [&](const float4 &f0, const float4 &f1, int ro, int j) {
                     SplatRec s;
                     s.px = f0.x; s.py = f0.y; s.a = f0.z; s.b = f0.w;
@@ -572,17 +574,15 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 float4 a0 = *reinterpret_cast<const float4 *>(rb + roff);
                 float4 a1 = *reinterpret_cast<const float4 *>(rb + roff + 16);
                 for (int j = cnt - 1; j >= 0; j -= 2) {
-                    const int ra = roff;
                     roff = in_vgpr(roff - 32);                  // record j - 1 (at least index -1)
                     const float4 c0 = *reinterpret_cast<const float4 *>(rb + roff);
                     const float4 c1 = *reinterpret_cast<const float4 *>(rb + roff + 16);
-                    splat(a0, a1, ra, j);
+                    splat(a0, a1, roff, j);
                     if (j == 0) break;
-                    const int rc = roff;
                     roff = in_vgpr(roff - 32);                  // record j - 2 (at least index -2)
                     a0 = *reinterpret_cast<const float4 *>(rb + roff);
                     a1 = *reinterpret_cast<const float4 *>(rb + roff + 16);
-                    splat(c0, c1, rc, j - 1);
+                    splat(c0, c1, roff, j - 1);
                 }
 #pragma unroll
                 for (int p = 0; p < kQuad; ++p) lim[p] += 32 * kCompLanes;   // the previous chunk
