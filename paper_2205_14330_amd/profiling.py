@@ -45,8 +45,8 @@ KERNELS = {
     "dpr::k_tile_order": "tile_order",
     "dpr::k_tile_emit": "tile_emit",
     "dpr::k_composite_bwd": "composite_bwd",
-    "dpr::k_composite<false, true>": "composite_fwd_count",   # forward keeping blend counts
-    "dpr::k_composite<true, true>": "composite_fwd_count",
+    "dpr::k_composite<false, true,": "composite_fwd_count",   # forward keeping blend counts
+    "dpr::k_composite<true, true,": "composite_fwd_count",
     "dpr::k_composite<": "composite_fwd",       # forward, and the backward's recompute pass
     "dpr::k_point_bwd": "point_bwd",
     "dpr::k_fill_u32": "fill",
