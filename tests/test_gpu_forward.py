@@ -238,6 +238,29 @@ def test_forward_is_deterministic_and_persistent_mode_matches(dpr):
         assert np.array_equal(to_np(a.trans[0]), to_np(p.trans[0]))
 
 
+def test_forward_variants_give_bitwise_identical_images(dpr):
+    """The forward kernel is built with and without backward state (stored vs
+    recompute mode) and with and without per-pixel counts, persistent or not;
+    every variant renders the same bits.  In the second scene every seventh
+    point has opacity 0.999 > alpha_max, so chunks holding one take the clamp
+    path; that scene is also checked against the oracle."""
+    sc, cam = _scene_cam(71, n=6000, size=(112, 80))
+    op = sc.opacity.copy()
+    op[::7] = np.float32(0.999)
+    hot = Scene(sc.xyz, sc.sh, op, sc.radius)
+    variants = (dict(bwd_mode="recompute"), dict(stats=True), dict(stats=True, bwd_mode="recompute"),
+                dict(persistent=True, bwd_mode="recompute"), dict(persistent=True, stats=True))
+    for scene in (sc, hot):
+        ref = gpu_plan([scene], [(0, cam)], dpr.RenderParams())
+        for kw in variants:
+            p = gpu_plan([scene], [(0, cam)], dpr.RenderParams(**kw))
+            assert np.array_equal(to_np(ref.images[0]), to_np(p.images[0])), kw
+            assert np.array_equal(to_np(ref.trans[0]), to_np(p.trans[0])), kw
+    plan = gpu_plan([hot], [(0, cam)], dpr.RenderParams())
+    compare_images(to_np(plan.images[0]), to_np(plan.trans[0]), oracle.render(hot, cam, oparams(dpr.RenderParams())),
+                   label="clamp-heavy")
+
+
 def test_sh_linearity_on_gpu(dpr):
     sc, cam = _scene_cam(68, n=3000)
     s2 = Scene(sc.xyz, (sc.sh * np.float32(2.0)).astype(np.float32), sc.opacity, sc.radius)
