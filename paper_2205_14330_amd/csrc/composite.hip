@@ -23,9 +23,9 @@
 // chunk of 64 records is gathered one per lane, written to LDS and read back
 // as broadcasts, one record ahead of its use.  T is recovered with one
 // reciprocal per lane and splat, of the product of the quad's four (1 - alpha).
-// The sums are reduced across each group of 4 lanes with quad-permute
-// swizzles (LDS pipe, so the VALU only adds), the 16 group sums of up to 8
-// splats are staged in LDS, and each flush completes 56 sums and adds them to
+// The sums are reduced across each pair of lanes with one quad-permute
+// swizzle (LDS pipe, so the VALU only adds), the 32 pair sums of up to 7
+// splats are staged in LDS, and each flush completes 49 sums and adds them to
 // the per-item gradient records with one 64-lane float atomic.
 #include "dpr_internal.h"
 
@@ -333,43 +333,42 @@ __device__ __forceinline__ float swizzle(float v) {
     return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x8000 | PATTERN));
 }
 
-// Sums over each group of 4 consecutive lanes (valid in all 4 lanes) of N
-// values; each level's swizzles are issued together so that one wait covers
-// them.
+// Sums over each pair of consecutive lanes (valid in both lanes) of N values;
+// the swizzles are issued together so that one wait covers them.
 template <int N>
-__device__ __forceinline__ void quad_sums(float (&v)[N]) {
+__device__ __forceinline__ void pair_sums(float (&v)[N]) {
     float t[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) t[i] = swizzle<0xB1>(v[i]);     // quad_perm [1,0,3,2]
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = v[i] + t[i];
-#pragma unroll
-    for (int i = 0; i < N; ++i) t[i] = swizzle<0x4E>(v[i]);     // quad_perm [2,3,0,1]
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = v[i] + t[i];
 }
 
-// Staging of per-splat partial sums: slot k holds, for one splat, the 16
-// lane-quad sums of each of the 8 quantities at [k][quad][quantity].  The quad
-// stride of 9 words keeps the 16 writers of one quantity on distinct banks; the
-// slot stride of 152 words (24 mod 32, 24 mod 64) keeps the 64 flush readers
-// (8 slots x 8 quantities) on distinct banks.
-constexpr int kSlots = 8;
-constexpr int kQuadStride = 9;
-constexpr int kSlotStride = 16 * kQuadStride + 8;
+// Staging of per-splat partial sums: slot k holds, for one splat, the 32
+// lane-pair sums of each of the 7 quantities at [k][pair][column].  The pair
+// stride of 7 words (odd) keeps the 32 writers of one column on distinct
+// banks; the slot stride of 264 words (8 mod 64) keeps the 49 flush readers
+// (7 slots x 7 columns) on distinct banks.  7 slots keep the kernel's LDS
+// within 16 waves per CU.
+constexpr int kSlots = 7;
+constexpr int kCols = 7;
+constexpr int kPairStride = kCols;
+constexpr int kSlotStride = 32 * kPairStride + 40;
+static_assert(kSlotStride % 64 == 8, "flush readers on distinct banks");
 
 // Completes the sums of the first nslots slots (lane L handles slot L/8,
-// quantity L%8) and adds them to the gradient records.
+// column L%8 < 7) and adds them to the gradient records.  Columns 0-2 are
+// quantities 0-2 and columns 3-6 quantities 4-7 (quantity 3 is unused).
 __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t *s_gid, int nslots, float *grad,
                                             int lane) {
-    const int q = lane & 7;
+    const int c = lane & 7;
     const int k = lane >> 3;
-    if (k < nslots && q != 3) {     // quantity 3 is unused
-        const float *src = s_part + k * kSlotStride + q;
+    if (k < nslots && c < kCols) {
+        const float *src = s_part + k * kSlotStride + c;
         float sum = src[0];
 #pragma unroll
-        for (int o = 1; o < 16; ++o) sum += src[o * kQuadStride];
-        atomicAdd(grad + 8 * (size_t)s_gid[k] + q, sum);
+        for (int o = 1; o < 32; ++o) sum += src[o * kPairStride];
+        atomicAdd(grad + 8 * (size_t)s_gid[k] + (c < 3 ? c : c + 1), sum);
     }
 }
 
@@ -389,7 +388,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     const float alpha_max = a.th.alpha_max;
     const float w_noclamp = in_vgpr(no_clamp_w(alpha_max));
     const int lane = threadIdx.x;
-    float *const my_part = s_part + (lane >> 2) * kQuadStride;
+    float *const my_part = s_part + (lane >> 1) * kPairStride;
     const uint32_t nwork = *b.work_count;
 
     for (uint32_t w = blockIdx.x; w < nwork;) {
@@ -547,13 +546,13 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         v6 = fmaf(Ta[p], gI1[p], v6);
                         v7 = fmaf(Ta[p], gI2[p], v7);
                     }
-                    {   // the 4 lanes of a group hold bitwise-equal sums and store them
+                    {   // the 2 lanes of a pair hold bitwise-equal sums and store them
                         // to the same words, which keeps the reduction unconditional
-                        float v[7] = {v0, v1, v2, v4, v5, v6, v7};
-                        quad_sums(v);
+                        float v[kCols] = {v0, v1, v2, v4, v5, v6, v7};
+                        pair_sums(v);
                         float *dst = my_part + nslots * kSlotStride;
-                        dst[0] = v[0]; dst[1] = v[1]; dst[2] = v[2];
-                        dst[4] = v[3]; dst[5] = v[4]; dst[6] = v[5]; dst[7] = v[6];
+#pragma unroll
+                        for (int i = 0; i < kCols; ++i) dst[i] = v[i];
                     }
                     if (lane == j) s_gid[nslots] = id;
                     if (++nslots == kSlots) {
