@@ -291,6 +291,32 @@ def test_stats_count_blended_splats(dpr):
     assert abs(int(st.sum()) - int(ref.ncontrib.sum())) <= 0.001 * ref.ncontrib.sum() + 5
 
 
+def test_blend_end_bounds_the_blends(dpr):
+    """Stored-mode backward state: a pixel's blend end (one past the list
+    position of the last splat it blended) is 0 exactly when it blended
+    nothing, is at least its number of blended splats, and stays within its
+    tile's list; also under the n = 3 cap."""
+    torch = __import__("torch")
+    W, H = 100, 70
+    sc, cam = _scene_cam(72, n=5000, size=(W, H))
+    for params in (dpr.RenderParams(stats=True), dpr.RenderParams(stats=True, max_splats=3)):
+        plan = gpu_plan([sc], [(0, cam)], params)
+        inf = plan.info()
+        st = to_np(plan.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32)).reshape(H, W)
+        nl = to_np(plan.ws[inf.nlast_off: inf.nlast_off + 4 * inf.pixels].view(torch.int32)).reshape(H, W)
+        tx, ty = (W + 15) // 16, (H + 15) // 16
+        rng_ = to_np(plan.plan_ws[inf.range_off: inf.range_off + 4 * (tx * ty + 1)].view(torch.int32))
+        tlen = np.diff(rng_.view(np.uint32).astype(np.int64))
+        ys, xs = np.mgrid[0:H, 0:W]
+        tl = tlen[(ys // 16) * tx + xs // 16]
+        assert (st > 0).mean() > 0.3
+        assert np.array_equal(st == 0, nl == 0)
+        assert np.all(nl >= st)
+        assert np.all(nl <= tl)
+        if params.max_splats:
+            assert st.max() == 3
+
+
 def test_timing_of_selected_stages(dpr):
     """With timing_stages only the named stages report a time; the image is the
     same as without timing."""
