@@ -381,3 +381,130 @@ def test_backward_matches_central_differences(seed, frame, deg):
             checked += 1
     assert kinked <= 0.05 * (checked + kinked)
     assert checked > 0
+
+
+def _clamp_pairs(xyz, op, rad, cam, alpha_max):
+    """(point, pixel) pairs where o G exceeds alpha_max, from a float64
+    projection of its own (Eq. 1, sigma = f r / Z).  Used only to find the
+    finite-difference pairs that cross the clamp (kinks)."""
+    R = np.asarray(cam.R, np.float64).reshape(3, 3)
+    X = xyz @ R.T + np.asarray(cam.t, np.float64)
+    px = cam.fx * X[:, 0] / X[:, 2] + cam.cx
+    py = cam.fy * X[:, 1] / X[:, 2] + cam.cy
+    sx = cam.fx * rad / X[:, 2]
+    sy = cam.fy * rad / X[:, 2]
+    ux = np.arange(cam.width) + 0.5
+    uy = np.arange(cam.height) + 0.5
+    q = ((px[:, None, None] - ux[None, None, :]) / sx[:, None, None]) ** 2 + \
+        ((py[:, None, None] - uy[None, :, None]) / sy[:, None, None]) ** 2
+    return op[:, None, None] * np.exp(-0.5 * q) > alpha_max
+
+
+@pytest.mark.parametrize("seed", [30, 31])
+def test_backward_with_clamped_splats_matches_central_differences(seed):
+    """Splats whose o G exceeds alpha_max at a pixel centre: there alpha is the
+    constant alpha_max, so the loss depends on such a splat's opacity and
+    position only through the other pixels it covers, yet its colour still
+    enters I and its (1 - alpha_max) still scales everything behind it.  Central
+    differences pin every branch of the backward that handles a clamped splat."""
+    sc, cam = _random_view(seed, n=24, deg=2)
+    params = oracle.Params()
+    base = oracle.project(sc, cam)
+    rng = np.random.default_rng(seed)
+    R = np.asarray(cam.R, np.float64).reshape(3, 3)
+    t = np.asarray(cam.t, np.float64)
+    extra = []
+    # six near-opaque splats on pixel centres, each just in front of or just
+    # behind one of the scene's splats, so that both orders occur
+    inside = base["valid"] & (base["px"] >= 1) & (base["px"] < cam.width - 1) & \
+        (base["py"] >= 1) & (base["py"] < cam.height - 1)
+    for j, i in enumerate(rng.choice(np.nonzero(inside)[0], 6, replace=False)):
+        ux = np.floor(base["px"][i]) + 0.5
+        uy = np.floor(base["py"][i]) + 0.5
+        Z = base["z"][i] + (-0.02 if j % 2 == 0 else 0.02)
+        Xc = np.array([(ux - cam.cx) * Z / cam.fx, (uy - cam.cy) * Z / cam.fy, Z])
+        extra.append(R.T @ (Xc - t))
+    m = len(extra)
+    xyz = np.concatenate([sc.xyz.astype(np.float64), np.array(extra)])
+    sh = np.concatenate([sc.sh.astype(np.float64), 0.3 * rng.standard_normal((m, 9, 3))])
+    op = np.concatenate([sc.opacity.astype(np.float64), np.full(m, 0.9999)])
+    rad = np.concatenate([sc.radius.astype(np.float64), np.full(m, 0.02)])
+    clamp0 = _clamp_pairs(xyz, op, rad, cam, params.alpha_max)
+    assert clamp0[-m:].any(axis=(1, 2)).all()            # every added splat is clamped somewhere
+    npix = cam.pixels
+    wI = rng.standard_normal((npix, 3))
+    wT = rng.standard_normal(npix)
+    g = oracle.backward_double(xyz, sh, op, rad, cam, wI, wT, params)
+
+    def structure():
+        r = oracle.render_double(xyz, sh, op, rad, cam, params)
+
+        class _S:
+            pass
+        q = _S()
+        q.xyz = xyz.astype(np.float32)
+        return r, oracle.depth_order(q, cam, params), _clamp_pairs(xyz, op, rad, cam, params.alpha_max)
+
+    checked = kinked = 0
+    checked_clamped = 0
+    for name, arr, h in (("xyz", xyz, 1e-6), ("sh", sh, 1e-3), ("opacity", op, 1e-6)):
+        grad = getattr(g, name)
+        gmax = np.abs(grad).max()
+        flat = arr.reshape(-1)
+        per_point = flat.size // xyz.shape[0]
+        for j in range(flat.size):
+            old = flat[j]
+            flat[j] = old + h
+            rp, op_, cp = structure()
+            flat[j] = old - h
+            rm, om_, cm = structure()
+            flat[j] = old
+            if not (np.array_equal(rp.ncontrib, rm.ncontrib) and np.array_equal(rp.stopped, rm.stopped)
+                    and np.array_equal(op_, om_) and np.array_equal(cp, cm)):
+                kinked += 1
+                continue
+            fd = (_loss(rp, wI.reshape(rp.image.shape), wT) - _loss(rm, wI.reshape(rm.image.shape), wT)) / (2 * h)
+            an = grad.reshape(-1)[j]
+            assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-2 * gmax) + 1e-12, (name, j, fd, an)
+            checked += 1
+            checked_clamped += j // per_point >= xyz.shape[0] - m
+    assert kinked <= 0.05 * (checked + kinked)
+    assert checked_clamped >= 0.9 * m * 31
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("which", ["ball100k_8x400", "surface300k_4x800"])
+def test_float32_depth_key_is_a_faithful_rounding_of_camera_z(which):
+    """Sec. 3.2 sorts by camera-space z.  The depth order decides in float32, on
+    the key fmaf(R20, x, fmaf(R21, y, fmaf(R22, z, t2))): three roundings, each
+    at most half an ulp32 of a partial sum bounded by
+    M = |t2| + |R22 z| + |R21 y| + |R20 x|, so |key - Z| <= e = 1.5 ulp32(M)
+    against Z computed in float64 from the same float32 inputs.  Checked here
+    point by point; the cull keeps exactly the points with Z > z_near; and a
+    point earlier in the key order is never farther than a later one by more
+    than the two points' bounds: the key order is the order of camera Z except
+    between points whose Z differ by less than that (near-ties)."""
+    if which == "ball100k_8x400":
+        scene, cams, _, _ = workloads.ball100k_8x400()
+    else:
+        scene, cams, _ = workloads.surface300k_4x800()
+    z_near = oracle.Params().z_near
+    xyz = scene.xyz.astype(np.float64)
+    swapped = 0
+    for cam in cams[:4]:
+        R = np.asarray(cam.R, np.float32).astype(np.float64).reshape(3, 3)
+        t = np.asarray(cam.t, np.float32).astype(np.float64)
+        Z = xyz @ R[2] + t[2]
+        M = np.abs(t[2]) + np.abs(xyz) @ np.abs(R[2])
+        e = 1.5 * np.spacing(M.astype(np.float32)).astype(np.float64)
+        zk = oracle.project(scene, cam)["zkey"].astype(np.float64)
+        assert (np.abs(zk - Z) <= e).all()
+        assert np.abs(zk - Z).max() > 0          # the key really is rounded
+        order = oracle.depth_order(scene, cam)
+        assert np.array_equal(np.sort(order), np.nonzero(Z > z_near)[0])
+        Zo = Z[order]
+        run_max = np.maximum.accumulate(Zo)
+        assert (run_max[:-1] - Zo[1:] <= e.max() + e[order][1:]).all()
+        exact = np.lexsort((order, Zo))           # float64 order, ties by index
+        swapped += int((order[exact] != order).sum())
+    print(f"{which}: {swapped} of {4 * len(xyz)} positions differ between the float32 and float64 orders")
