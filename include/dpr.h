@@ -214,7 +214,10 @@ size_t dpr_backward_ws_bytes(const dpr_plan *plan);
  *   dL_dopacity[s][n]        } table) skips that output.
  * Candidate sets, depth order and the splats each pixel blends are held fixed (piecewise-constant
  * structure); clamped alphas pass no gradient to o or the position.  The
- * forward state is not modified, so backward may be called more than once. */
+ * forward state is not modified, so backward may be called more than once.
+ * `ws` must be the very buffer given to this plan's dpr_render_forward (it holds
+ * the tile lists and, in stored mode, the backward state); any other pointer
+ * returns DPR_ERR_STATE before device work, as does a call before the forward. */
 int dpr_render_backward(dpr_plan *plan, const void *ws, size_t ws_bytes,
                         const float *const *dL_dimage, const float *const *dL_dtrans,
                         float *const *dL_dxyz, float *const *dL_dsh, float *const *dL_dopacity,

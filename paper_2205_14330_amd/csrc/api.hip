@@ -689,6 +689,11 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
     if (!p->forward_done) return fail(DPR_ERR_STATE, "dpr_render_backward before dpr_render_forward");
     const FwdLayout f = fwd_layout(p);
     if (!ws || ws_bytes < f.total) return fail(DPR_ERR_WORKSPACE, "forward workspace too small");
+    // the tile lists (and in stored mode the backward state) live in the
+    // workspace the forward wrote; any other buffer holds item ids and work
+    // items of some other plan
+    if (ws != p->fwd_ws)
+        return fail(DPR_ERR_STATE, "dpr_render_backward needs the workspace of this plan's dpr_render_forward");
     const BwdLayout bl = bwd_layout(p);
     if (!bwd_ws || bwd_ws_bytes < bl.total)
         return fail(DPR_ERR_WORKSPACE, "backward workspace needs %llu bytes, got %llu",

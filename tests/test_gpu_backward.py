@@ -269,3 +269,30 @@ def test_long_lists_split_into_backward_segments(dpr, mode):
         ref = oracle.render(sc, cam, oparams(params))
         compare_images(to_np(plan.images[v]), to_np(plan.trans[v]), ref, label=f"long lists {mode} view {v}")
     _check_scene(dpr, sc, cams, params, gI, gT, got[0], f"long lists {mode}")
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_backward_rejects_another_forward_workspace(dpr, mode):
+    """The backward reads the tile lists (and, stored, the backward state) from
+    the buffer this plan's forward wrote.  A different buffer of the same size
+    is refused on the host, before any device work, with DPR_ERR_STATE; the
+    right buffer still gives the oracle's gradients afterwards."""
+    import torch
+    from paper_2205_14330_amd import _abi
+    sc = workloads.small_scene(96, 800, extent=0.6)
+    rng = np.random.default_rng(96)
+    cams = [workloads.random_sphere_camera(rng, 32, 24)]
+    params = dpr.RenderParams(bwd_mode=mode)
+    gI, gT = _weights(96, cams)
+    plan = gpu_plan([sc], [(0, cams[0])], params)
+    gi = [torch.from_numpy(gI[0]).cuda()]
+    gt = [torch.from_numpy(gT[0]).cuda()]
+    mine = plan.ws
+    plan.ws = torch.zeros_like(mine)
+    with pytest.raises(_abi.DprError) as err:
+        plan.backward(gi, gt)
+    assert err.value.code == _abi.DPR_ERR_STATE
+    plan.ws = mine
+    out = plan.backward(gi, gt)
+    torch.cuda.synchronize()
+    _check_scene(dpr, sc, cams, params, gI, gT, [to_np(t) for t in out[0]], f"{mode} after refusal")
