@@ -9,6 +9,7 @@
 //   chamfer_host topk    DIR k3 K  DIR/{s1,sh1,s2}.bin -> DIR/{out_sh,idx}.bin
 //   chamfer_host adam    DIR t lr b1 b2 eps   DIR/{p,g,m,v}.bin -> same files, updated
 #include "chamfer.hip"
+#include "sort.hip"
 
 #include <sanitizer/asan_interface.h>
 

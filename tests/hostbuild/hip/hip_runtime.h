@@ -1,5 +1,6 @@
 // Host stand-in for the part of the HIP runtime and device library that the
-// hybrid-update, visual-hull and warm-start kernels use, so that those kernels compile with g++ and run on
+// hybrid-update, visual-hull and warm-start kernels and the library's scan
+// and radix sort use, so that those kernels compile with g++ and run on
 // CPU threads under AddressSanitizer.  Test infrastructure only: it checks the
 // kernels' indexing and host sequencing, not GPU code generation.
 //
@@ -187,6 +188,26 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
     b.slot[t] = bits;
     b.wave[t / 64]->arrive_and_wait();
     const uint64_t o = b.slot[(t & ~63u) | ((t & 63u) ^ (uint32_t)mask)];
+    b.wave[t / 64]->arrive_and_wait();
+    T r;
+    std::memcpy(&r, &o, sizeof(T));
+    return r;
+}
+
+inline int __lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Lane l receives lane l - delta's value; lanes below delta keep their own.
+template <class T>
+inline T __shfl_up(T v, unsigned delta, int width = 64) {
+    static_assert(sizeof(T) <= 8, "shuffle of a value wider than 8 bytes");
+    if (width != 64) std::abort();
+    hostrt::Block &b = hostrt::pool().block();
+    const uint32_t t = threadIdx.x;
+    uint64_t bits = 0;
+    std::memcpy(&bits, &v, sizeof(T));
+    b.slot[t] = bits;
+    b.wave[t / 64]->arrive_and_wait();
+    const uint64_t o = b.slot[(t & 63u) >= delta ? t - delta : t];
     b.wave[t / 64]->arrive_and_wait();
     T r;
     std::memcpy(&r, &o, sizeof(T));

@@ -2,8 +2,9 @@
 // initialisation, the appendix's consistency check) for checking their
 // indexing under AddressSanitizer; test infrastructure only.
 //
-// hull.hip compiles unchanged against the host stand-in of <hip/hip_runtime.h>;
-// the flat scan and the small-table upload come from stand_ins.h.  Inputs,
+// hull.hip and the library's scan (sort.hip) compile unchanged against the
+// host stand-in of <hip/hip_runtime.h>; the small-table upload comes from
+// stand_ins.h.  Inputs,
 // masks and outputs are allocations of exactly their size, and the padding
 // after each region of the workspace is poisoned, so an access past any array
 // is reported.
@@ -12,6 +13,7 @@
 //   hull_host keep   DIR                   + DIR/xyz.bin -> DIR/keep.bin
 //   hull_host filter DIR k3                + DIR/{xyz,sh,op,rad}.bin -> DIR/out_*.bin, DIR/count.txt
 #include "hull.hip"
+#include "sort.hip"
 
 #include <sanitizer/asan_interface.h>
 

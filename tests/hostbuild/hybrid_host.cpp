@@ -2,10 +2,8 @@
 // their indexing under AddressSanitizer; test infrastructure only.
 //
 // The kernels and host sequencing of hybrid.hip compile unchanged against the
-// host stand-in of <hip/hip_runtime.h>.  The library's flat scan and radix
-// sort are replaced by plain sequential versions that keep their contracts:
-// they touch exactly the scratch words the library's versions use, and the
-// sort leaves its result in the buffer the library's would.  Every scratch
+// host stand-in of <hip/hip_runtime.h>, and so do the library's flat scan and
+// radix sort (sort.hip), with their real launch sequence.  Every scratch
 // array is its own allocation of exactly the size the library reserves,
 // filled with 0xFF, so an unset index or an access past an array's end is
 // reported instead of landing in a neighbouring array.
@@ -14,6 +12,7 @@
 //   hybrid_host voxel  DIR N k3       DIR/{xyz,sh,op,rad}.bin -> DIR/out_*.bin, DIR/counts.txt
 //   hybrid_host hybrid DIR N K eps k3 same, counts = voxels kept points
 #include "hybrid.hip"
+#include "sort.hip"
 
 #include <string>
 

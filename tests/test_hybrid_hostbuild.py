@@ -5,8 +5,8 @@ The kernels and host sequencing of the HIP source compile unchanged with g++
 against a host stand-in of the HIP runtime (tests/hostbuild): the threads of
 a block run concurrently on host threads, every scratch array is its own
 allocation of exactly the size the library reserves, filled with 0xFF, and
-the library's flat scan and radix sort are replaced by sequential versions
-with the same contracts.  The outputs must equal the oracle's bit for bit.
+the library's own flat scan and radix sort (sort.hip) run with their real
+launch sequence.  The outputs must equal the oracle's bit for bit.
 
 This checks the kernels' indexing, the scratch sizes and the float32 decision
 arithmetic on the CPU; the GPU's own code generation is checked by the GPU
