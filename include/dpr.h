@@ -412,6 +412,30 @@ int dpr_render_forward_1(const dpr_scene *scene, const dpr_camera *cam, const dp
                          float *image, float *trans, void *ws, size_t ws_bytes,
                          size_t *ws_needed, void *stream);
 
+/* Bytes of the static device scratch of dpr_render_forward_1_noalloc (64 MiB). */
+#define DPR_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): dpr_render_forward_1 with
+ * its workspace in a static device array of DPR_NOALLOC_SCRATCH_BYTES instead
+ * of a caller buffer.  It calls no hipMalloc/hipFree and creates no events.
+ *   - Same arguments, results and kernels as dpr_render_forward_1 with
+ *     ws/ws_bytes/ws_needed dropped; the caller still owns scene, image, trans.
+ *   - bwd_mode is ignored (no backward state is kept: the plan ends with the
+ *     call); DPR_FLAG_TIMING is refused with DPR_ERR_INVALID_ARG.
+ *   - An input whose plan + forward workspace exceeds the scratch returns
+ *     DPR_ERR_WORKSPACE with the size it needs (the plan stage may have run).
+ *     About 300k points at 800x800 fit.
+ *   - The scratch is per device: the first call on a device, with that device
+ *     current, takes its address once; the device holds the array until the
+ *     process ends.  The current device must own `stream` and the pointers.
+ *   - Every call on one device uses the same array and nothing in it needs to
+ *     start zeroed (the call clears its own counters).  Calls that overlap on
+ *     one device (other threads or other streams) race on it: serialize them.
+ *   - Like dpr_render_forward_1 it waits once on `stream` (for the pair count). */
+int dpr_render_forward_1_noalloc(const dpr_scene *scene, const dpr_camera *cam, const dpr_params *params,
+                                 float *image, float *trans, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

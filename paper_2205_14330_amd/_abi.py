@@ -26,7 +26,7 @@ EXPORTED = ["dpr_version", "dpr_last_error", "dpr_plan_ws_bytes", "dpr_plan_forw
             "dpr_render_forward_1", "dpr_loss_ws_bytes", "dpr_loss_l2_tv", "dpr_knn_ws_bytes", "dpr_knn",
             "dpr_hybrid_ws_bytes", "dpr_voxel_reduce", "dpr_hybrid_update", "dpr_hull_ws_bytes", "dpr_hull_sample",
             "dpr_consistency", "dpr_consistency_filter", "dpr_chamfer_ws_bytes", "dpr_chamfer", "dpr_topk_sh",
-            "dpr_adam_step"]
+            "dpr_adam_step", "dpr_render_forward_1_noalloc"]
 
 
 class Camera(ctypes.Structure):
@@ -98,6 +98,9 @@ def load(path: str = LIB_PATH):
     L.dpr_render_forward_1.argtypes = [ctypes.POINTER(Scene), ctypes.POINTER(Camera), ctypes.POINTER(Params),
                                        c_p, c_p, c_p, c_sz, ctypes.POINTER(c_sz), c_p]
     L.dpr_render_forward_1.restype = c_i32
+    L.dpr_render_forward_1_noalloc.argtypes = [ctypes.POINTER(Scene), ctypes.POINTER(Camera),
+                                               ctypes.POINTER(Params), c_p, c_p, c_p]
+    L.dpr_render_forward_1_noalloc.restype = c_i32
     I32P = ctypes.POINTER(c_i32)
     L.dpr_loss_ws_bytes.argtypes, L.dpr_loss_ws_bytes.restype = [c_i32, I32P, I32P], c_sz
     L.dpr_loss_l2_tv.argtypes = [c_i32, PP, PP, I32P, I32P, c_f, PP, c_p, c_p, c_sz, c_p]

@@ -432,6 +432,16 @@ int check_hybrid_args(int64_t n, int32_t sh_degree, int32_t K) {
 
 }  // namespace
 
+int dpr::set_last_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
 extern "C" {
 
 int dpr_version(void) { return DPR_ABI_VERSION; }

@@ -350,4 +350,7 @@ hipError_t launch_loss(const LossImage *img, int n, float lambda, float *partial
 // Stream-ordered copy of a small host table (bytes % 4 == 0) through kernel arguments.
 hipError_t upload_async(void *dst, const void *src, size_t bytes, hipStream_t st);
 
+// Sets the thread's dpr_last_error message and returns `code`.
+int set_last_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
 }  // namespace dpr
