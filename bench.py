@@ -39,6 +39,23 @@ BWD_OPS_PER_BLEND = 50            # lane-ops per blended (pixel, splat), backwar
 EMIT_BYTES_PER_ITEM = 32          # bytes tile emission reads per depth-sorted item
 
 
+def load_profile(workload: str):
+    """Per-kernel rocprofv3 figures of the committed summary
+    profiles/kernels_<workload>.json (average duration of the step's launches,
+    VALU busy share) if taken on the current kernel sources; else None."""
+    from paper_2205_14330_amd.profiling import kernel_source_hash
+    if workload is None:
+        return None
+    p = os.path.join(ROOT, "profiles", f"kernels_{workload}.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("kernels")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -63,31 +80,127 @@ def load_traffic(kernel: str, workload: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, cams, targets_fn, max_splats=0, kernel_norm=0, lam=0.0):
-    """FP64 oracle on one full step (all views, forward, Eq. 8 loss, backward)."""
+TRAIN_STEPS = 100                 # Adam steps of the training trajectory (at least)
+# Adam learning rates: positions and SH as Sec. 3.3 sets them; the opacity
+# logit's rate is this benchmark's own (the paper learns no opacity)
+LR_XYZ, LR_SH, LR_LOGIT = 8e-4, 3e-3, 1e-2
+GRAD_RTOL = 1e-3                  # per element, relative to max(|g*|, 1e-2 ||g*||_inf)
+GRAD_L2 = 1e-3                    # ||g - g*||_2 / ||g*||_2
+IMG_TOL = 1e-4                    # max-abs per pixel and channel, image and transmittance
+
+
+class Trainer:
+    """Adam on the positions, SH coefficients and opacity logits of one scene
+    (o = sigmoid(l), so dL/dl = dL/do o (1 - o)).  The scene tensors are
+    updated in place on the current stream after each backward."""
+
+    def __init__(self, init):
+        import torch
+        from paper_2205_14330_amd import SceneTensors
+        self.init = init
+        self.scene = SceneTensors(init.xyz.clone(), init.sh.clone(), init.opacity.clone(), init.radius)
+        o = init.opacity.double()
+        self.logit0 = torch.log(o / (1.0 - o)).float()
+        self.logit = self.logit0.clone()
+        self.grads = (torch.empty_like(init.xyz), torch.empty_like(init.sh), torch.empty_like(init.opacity))
+        self.glogit = torch.empty_like(init.opacity)
+        self.params = (self.scene.xyz, self.scene.sh, self.logit)
+        self.m = [torch.zeros_like(x) for x in self.params]
+        self.v = [torch.zeros_like(x) for x in self.params]
+        self.t = 0
+
+    def reset(self):
+        self.scene.xyz.copy_(self.init.xyz)
+        self.scene.sh.copy_(self.init.sh)
+        self.scene.opacity.copy_(self.init.opacity)
+        self.logit.copy_(self.logit0)
+        for a in self.m + self.v:
+            a.zero_()
+        self.t = 0
+
+    def update(self):
+        import torch
+        from paper_2205_14330_amd.chamfer import adam_step
+        self.t += 1
+        gx, gs, go = self.grads
+        o = self.scene.opacity
+        torch.mul(go, o, out=self.glogit)
+        self.glogit.addcmul_(self.glogit, o, value=-1.0)          # go o (1 - o)
+        for p_, g_, m_, v_, lr in zip(self.params, (gx, gs, self.glogit), self.m, self.v, (LR_XYZ, LR_SH, LR_LOGIT)):
+            adam_step(p_, g_, m_, v_, self.t, lr)
+        torch.sigmoid(self.logit, out=o)
+
+    def numpy_scene(self):
+        import workloads
+        s = self.scene
+        return workloads.Scene(s.xyz.cpu().numpy(), s.sh.cpu().numpy(), s.opacity.cpu().numpy(),
+                               s.radius.cpu().numpy())
+
+
+def grad_margin(g, ref):
+    """(worst element error as a fraction of its bound, rel-L2) of a gradient
+    against the oracle's, bound |g - g*| <= 1e-3 max(|g*|, 1e-2 ||g*||_inf)."""
+    g = np.asarray(g, np.float64).reshape(-1)
+    r = np.asarray(ref, np.float64).reshape(-1)
+    gmax = np.abs(r).max()
+    bound = GRAD_RTOL * np.maximum(np.abs(r), 1e-2 * gmax)
+    return float(np.max(np.abs(g - r) / bound)), float(np.linalg.norm(g - r) / np.linalg.norm(r))
+
+
+def parity_weights(views, size):
+    """Seeded N(0, 1) weights w[v] [H][W][3]: the parity checks use the linear
+    loss L = sum w I, so dL/dI = w is the same input on both sides."""
+    rng = np.random.default_rng(np.random.SeedSequence(0, spawn_key=(3, 2)))
+    return [rng.standard_normal((size, size, 3)).astype(np.float32) for _ in range(views)]
+
+
+def gpu_step_outputs(dpr, scene, cams, weights, variant):
+    """One step's forward and, with dL/dI = weights, the backward in both
+    modes, on the current cloud (nothing is updated): the values the parity
+    check compares with the oracle."""
+    import torch
+    out = {}
+    w = [torch.from_numpy(x).cuda() for x in weights]
+    for mode in ("stored", "recompute"):
+        plan = dpr.Plan([scene], [(0, c) for c in cams], dpr.RenderParams(bwd_mode=mode, **variant))
+        plan.forward()
+        g = plan.backward(w, None)[0]
+        torch.cuda.synchronize()
+        if mode == "stored":
+            out["images"] = [t.cpu().numpy() for t in plan.images]
+            out["trans"] = [t.cpu().numpy() for t in plan.trans]
+        out[mode] = [t.cpu().numpy() for t in g]
+        plan.free()
+    return out
+
+
+def oracle_step(scene_np, cams, weights, max_splats, kernel_norm, threads):
+    """The FP64 oracle on one full step: forward of every view and the
+    backward with dL/dI = weights.  Returns (seconds, renders, gradients)."""
     import oracle
-    cores = len(os.sched_getaffinity(0))
     op = oracle.Params(max_splats=max_splats, kernel_norm=kernel_norm)
     t0 = time.perf_counter()
-    pix = 0
-    for v, cam in enumerate(cams):
-        r = oracle.render(scene, cam, op, threads=cores)
-        _, gI = oracle.loss_l2_tv(r.image, targets_fn(v), lam)
-        oracle.backward(scene, [cam], [gI], None, params=op, threads=cores)
-        pix += cam.pixels
-    dt = time.perf_counter() - t0
-    used = min(cores, oracle.max_threads())    # read before the one-thread run resets it
-    # the same work on one thread, for the first view only (a quarter of the step)
-    t1 = time.perf_counter()
-    r = oracle.render(scene, cams[0], op, threads=1)
-    _, gI = oracle.loss_l2_tv(r.image, targets_fn(0), lam)
-    oracle.backward(scene, [cams[0]], [gI], None, params=op, threads=1)
-    dt1 = time.perf_counter() - t1
-    return {"value": pix / dt / 1e6, "unit": "Mpix/s", "cores": used, "kind": "oracle",
-            "sample": f"one full step: {len(cams)} views x {cams[0].width}x{cams[0].height}, fwd+bwd, "
-                      f"FP64, {dt:.1f} s",
-            "one_thread": {"value": cams[0].pixels / dt1 / 1e6, "unit": "Mpix/s",
-                           "sample": f"view 0 of the step, fwd+bwd, FP64, {dt1:.1f} s"}}
+    renders = [oracle.render(scene_np, cam, op, threads=threads) for cam in cams]
+    g = oracle.backward(scene_np, cams, [w.astype(np.float64) for w in weights], None, params=op, threads=threads)
+    return time.perf_counter() - t0, renders, g
+
+
+def parity_report(gpu, renders, g):
+    img = max(float(np.abs(a.astype(np.float64) - r.image).max()) for a, r in zip(gpu["images"], renders))
+    tr = max(float(np.abs(a.astype(np.float64) - r.trans).max()) for a, r in zip(gpu["trans"], renders))
+    rep = {"img_max_err": img, "trans_max_err": tr, "grads": {}}
+    ok = img <= IMG_TOL and tr <= IMG_TOL
+    for mode in ("stored", "recompute"):
+        d = {}
+        for name, got, want in zip(("xyz", "sh", "opacity"), gpu[mode], (g.xyz, g.sh, g.opacity)):
+            worst, l2 = grad_margin(got, want)
+            d[name] = {"worst_over_bound": round(worst, 4), "rel_l2": float(f"{l2:.3e}")}
+            ok = ok and worst <= 1.0 and l2 <= GRAD_L2
+        rep["grads"][mode] = d
+    rep["grad_worst_over_bound"] = max(e["worst_over_bound"] for m in rep["grads"].values() for e in m.values())
+    rep["grad_rel_l2"] = max(e["rel_l2"] for m in rep["grads"].values() for e in m.values())
+    rep["pass"] = bool(ok)
+    return rep
 
 
 def main():
@@ -98,7 +211,10 @@ def main():
     ap.add_argument("--points", type=int, default=300_000)
     ap.add_argument("--size", type=int, default=800)
     ap.add_argument("--views", type=int, default=4)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=TRAIN_STEPS,
+                    help="length of the Adam trajectory (at least warmup + steps)")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (CPU baseline and the parity checks at both ends of the trajectory)")
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--main-only", action="store_true",
                     help="time only the forward + backward metric (skip the forward-only and recompute legs)")
@@ -108,9 +224,12 @@ def main():
                     default="train",
                     help="train: the default step; paper: the same step with the paper-literal renderer "
                          "(n = 15 splats per pixel, normalised Eq. 5) and the L2 + 0.01 TV loss")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
-                    help="length of the serving trace (train: short leg in the same JSON line; 0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the serving trace (train: a leg of the same JSON line; 0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--overload-rate", type=float, default=3000.0,
+                    help="train: rate of the short overload trace of the serving leg (0 = skip)")
+    ap.add_argument("--overload-seconds", type=float, default=2.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this renderer runs on one GPU; --gpus above 1 is not supported "
@@ -139,22 +258,25 @@ def main():
         print(json.dumps(out), flush=True)
         return
     V, S = args.views, args.size
+    W_, K = args.warmup, args.steps
+    n_traj = max(args.train_steps, W_ + K)
     scene_np, cams, gt_np = workloads.surface300k_4x800(n=args.points, size=S, views_per_step=V, steps=100)
-    scene = dpr.SceneTensors.from_numpy(scene_np, dev)
+    init = dpr.SceneTensors.from_numpy(scene_np, dev)
     gt = dpr.SceneTensors.from_numpy(gt_np, dev)
-    nsteps = args.warmup + args.steps
-    step_views = [cams[(k % 100) * V:(k % 100) * V + V] for k in range(nsteps)]
+    step_views = [cams[(k % 100) * V:(k % 100) * V + V] for k in range(n_traj)]
 
     # targets: renders of the ground-truth scene from each step's views (untimed)
     targets = []
-    for k in range(min(nsteps, 100)):
+    for k in range(min(n_traj, 100)):
         p = dpr.Plan([gt], [(0, c) for c in step_views[k]], dpr.RenderParams(bwd_mode="recompute"))
         p.forward()
         targets.append(torch.stack(p.images).clone())
         p.free()
     torch.cuda.synchronize()
-    log(f"setup done: {args.points} points, {V} x {S}x{S}, {nsteps} steps")
+    log(f"setup done: {args.points} points, {V} x {S}x{S}, trajectory of {n_traj} Adam steps, "
+        f"timed steps {W_}..{W_ + K - 1}")
 
+    trainer = Trainer(init)
     # two live plans at a time (one being inspected while the next runs), so two
     # workspaces, each reused every other step
     wss = [dpr.Workspace(dev), dpr.Workspace(dev)]
@@ -166,48 +288,53 @@ def main():
     grads = [torch.empty((S, S, 3), dtype=torch.float32, device=dev) for _ in range(V)]
     loss_ws = dpr.Workspace(dev)
 
-    def step(k, params, backward=True):
-        plan = dpr.Plan([scene], [(0, c) for c in step_views[k]], params, workspace=wss[k % 2])
+    def step(k, params, train=True):
+        """Step k of the trajectory: forward, Eq. (8) loss gradient, backward,
+        Adam update (train), or the forward alone."""
+        plan = dpr.Plan([trainer.scene], [(0, c) for c in step_views[k]], params, workspace=wss[k % 2])
         plan.forward()
-        if backward:
+        if train:
             tgt = targets[k % len(targets)]
             dpr.loss_l2_tv(plan.images, [tgt[v] for v in range(V)], lam, grads=grads, workspace=loss_ws)
-            plan.backward(grads, None)
+            plan.backward(grads, None, out=[trainer.grads])
+            trainer.update()
         return plan
 
-    def timed(params, backward, steps, warmup, collect=None, reset=None):
-        """Times `steps` steps after `warmup`.  At most two plans are alive, on
-        the two workspaces; a plan is inspected and freed once the next plan's
-        host sync has passed its work.  The warmup runs the same loop, inspection
+    def run(params, train, warmup, steps, after=0, collect=None, reset=None):
+        """From the step-0 cloud: `warmup` steps, then `steps` timed steps,
+        then `after` more untimed.  At most two plans are alive, on the two
+        workspaces; a plan is inspected and freed once the next plan's host
+        sync has passed its work.  The warmup runs the same loop, inspection
         included (its first calls load torch's kernels), then `reset` clears
         what the inspection accumulated."""
+        trainer.reset()
         prev = None
-        for k in range(warmup):
-            plan = step(k, params, backward)
+
+        def advance(k, inspect=True):
+            nonlocal prev
+            plan = step(k, params, train)
             if prev is not None:
-                if collect:
+                if collect and inspect:
                     collect(prev)
                 prev.free()
             prev = plan
+
+        for k in range(warmup):
+            advance(k)
         if prev is not None:
             if collect:
                 collect(prev)
             prev.free()
+            prev = None
         torch.cuda.synchronize()
         if reset:
             reset()
         n_alloc = torch.cuda.memory_stats().get("num_device_alloc", 0)
         host = []
         t0 = time.perf_counter()
-        prev = None
-        for k in range(steps):
+        for k in range(warmup, warmup + steps):
             ts = time.perf_counter()
-            plan = step(warmup + k, params, backward)
-            if prev is not None:
-                if collect:
-                    collect(prev)
-                prev.free()
-            prev = plan
+            advance(k)
             host.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -217,12 +344,17 @@ def main():
         if collect:
             collect(prev)
         prev.free()
+        prev = None
+        for k in range(warmup + steps, warmup + steps + after):
+            advance(k, inspect=False)
+        if prev is not None:
+            prev.free()
+        torch.cuda.synchronize()
         return dt
 
     pix_step = V * S * S
     base = dict(persistent=args.persistent, **variant)
     stage_ms = {s: 0.0 for s in dpr.STAGES}
-    blend_acc = torch.zeros((), dtype=torch.int64, device=dev)
     pair_acc = [0]
     item_acc = [0]
 
@@ -236,64 +368,73 @@ def main():
     def reset():
         for s_ in stage_ms:
             stage_ms[s_] = 0.0
-        blend_acc.zero_()
         pair_acc[0] = 0
         item_acc[0] = 0
+
+    # parity at step 0: the GPU's outputs on the initial cloud (compared with
+    # the oracle below, together with the CPU baseline)
+    weights = parity_weights(V, S)
+    trainer.reset()
+    gpu0 = gpu_step_outputs(dpr, trainer.scene, step_views[0], weights, variant)
 
     # stage breakdown: every stage timed.  Each timed stage records two HIP
     # events on the stream, which stretch the step, so this loop is short and
     # only names the dominant kernel and splits the step into stages.
-    KB = min(args.steps, 10)
-    timed(dpr.RenderParams(timing=True, **base), True, KB, args.warmup, collect, reset)
+    KB = min(K, 10)
+    run(dpr.RenderParams(timing=True, **base), True, W_, KB, collect=collect, reset=reset)
     breakdown = {s_: v / KB for s_, v in stage_ms.items()}
     dom = max(breakdown, key=lambda s_: breakdown[s_])
     log("stage ms/step (every stage timed): " + ", ".join(f"{s_}={v:.3f}" for s_, v in breakdown.items()))
 
-    # main metric: forward + backward (stored T), HIP events around the dominant
-    # kernel only (its live launch duration for the roofline)
-    t_fb = timed(dpr.RenderParams(timing=True, timing_stages=(dom,), **base), True, args.steps,
-                 args.warmup, collect, reset)
+    # main metric: the training trajectory, forward + backward (stored T) +
+    # Adam; HIP events around the dominant kernel only (its live launch
+    # duration for the roofline); the trajectory runs on to its last step
+    t_fb = run(dpr.RenderParams(timing=True, timing_stages=(dom,), **base), True, W_, K,
+               after=n_traj - W_ - K, collect=collect, reset=reset)
     pairs = pair_acc[0]
     items = item_acc[0]
-    K = args.steps
+    mpix_fb = pix_step * K / t_fb / 1e6
+    log(f"fwd+bwd+adam: {t_fb / K * 1e3:.3f} ms/step, {mpix_fb:.1f} Mpix/s; {dom} {stage_ms[dom] / K:.3f} ms/launch")
+    # parity at the last step: the trained cloud
+    final_np = trainer.numpy_scene()
+    k_last = n_traj - 1
+    gpu_last = gpu_step_outputs(dpr, trainer.scene, step_views[k_last], weights, variant)
+
     # blended (pixel, splat) pairs of the timed steps, from the forward's
-    # per-pixel counters in a pass of their own over the same views (the
-    # forward is bitwise deterministic, so the counts are those of the timed
-    # launches; counting inside the timed loop would add a reduction per step)
-    overheads = None
-    for k in range(args.warmup, args.warmup + K):
-        p = dpr.Plan([scene], [(0, c) for c in step_views[k]], dpr.RenderParams(stats=True, **base),
-                     workspace=wss[k % 2])
-        p.forward()
+    # per-pixel counters, in a replay of the same trajectory (the forward is
+    # bitwise deterministic; the replay's clouds differ from the timed run's
+    # only by the order of the backward's float atomics)
+    blend_acc = torch.zeros((), dtype=torch.int64, device=dev)
+    overheads = {}
+
+    def count(p):
         inf = p.info()
         nu = p.ws[inf.stats_off: inf.stats_off + 4 * inf.pixels].view(torch.int32)
         blend_acc.add_(nu.sum())
-        if k == args.warmup + K - 1:
-            # the overheads of the last step: blended splats per pixel n(u), tile list lengths
-            rng = p.plan_ws[inf.range_off: inf.range_off + 4 * (inf.tiles + 1)].view(torch.int32).long()
-            lens = (rng[1:] - rng[:-1]).float()
-            nuf = nu.float()
-            overheads = {"pairs": int(inf.pairs), "n_u_mean": round(float(nuf.mean()), 1),
-                         "n_u_p99": float(torch.quantile(nuf[:: max(1, nuf.numel() // 1000000)], 0.99)),
-                         "n_u_max": int(nu.max()), "list_len_mean": round(float(lens.mean()), 1),
-                         "list_len_max": int(lens.max())}
-        p.free()
+        rng = p.plan_ws[inf.range_off: inf.range_off + 4 * (inf.tiles + 1)].view(torch.int32).long()
+        lens = (rng[1:] - rng[:-1]).float()
+        nuf = nu.float()
+        overheads.update({"pairs": int(inf.pairs), "n_u_mean": round(float(nuf.mean()), 1),
+                          "n_u_p99": float(torch.quantile(nuf[:: max(1, nuf.numel() // 1000000)], 0.99)),
+                          "n_u_max": int(nu.max()), "list_len_mean": round(float(lens.mean()), 1),
+                          "list_len_max": int(lens.max())})
+
+    run(dpr.RenderParams(stats=True, **base), True, W_, K, collect=count, reset=lambda: blend_acc.zero_())
     blends = int(blend_acc.item())
-    mpix_fb = pix_step * K / t_fb / 1e6
-    log(f"fwd+bwd: {t_fb / K * 1e3:.3f} ms/step, {mpix_fb:.1f} Mpix/s; {dom} {stage_ms[dom] / K:.3f} ms/launch")
 
     mpix_f = mpix_r = None
     if not args.main_only:
-        t_f = timed(dpr.RenderParams(**base), False, K, args.warmup)
+        t_f = run(dpr.RenderParams(**base), False, W_, K)
         mpix_f = round(pix_step * K / t_f / 1e6, 2)
-        t_r = timed(dpr.RenderParams(bwd_mode="recompute", **base), True, K, args.warmup)
+        t_r = run(dpr.RenderParams(bwd_mode="recompute", **base), True, W_, K)
         mpix_r = round(pix_step * K / t_r / 1e6, 2)
-        log(f"fwd: {mpix_f} Mpix/s; fwd+bwd recompute: {mpix_r} Mpix/s")
+        log(f"fwd: {mpix_f} Mpix/s; fwd+bwd+adam recompute: {mpix_r} Mpix/s")
 
     # roofline of the dominant kernel (per launch = per step); the committed PMC
     # traffic summary covers the default workload only
     comp = {"composite_fwd": FWD_OPS_PER_BLEND, "composite_bwd": BWD_OPS_PER_BLEND}
     traffic_wl = None if paper else "surface300k_4x800"
+    prof = load_profile(traffic_wl)
     if dom in comp:
         ops = comp[dom] * blends / K
         t_launch = stage_ms[dom] / K / 1e3
@@ -306,16 +447,25 @@ def main():
     elif dom == "emit":
         # 4 B written per (tile, splat) pair; per depth-sorted item 32 B read
         # (its index 4, tile rectangle 8, exponent record 20)
-        nbytes = (4.0 * pairs + EMIT_BYTES_PER_ITEM * items) / K
+        ops = (4.0 * pairs + EMIT_BYTES_PER_ITEM * items) / K
         t_launch = stage_ms[dom] / K / 1e3
-        achieved = nbytes / t_launch / 1e9
+        achieved = ops / t_launch / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                 "frac": round(achieved * 1e9 / PEAK_HBM, 4), "traffic": load_traffic("tile_emit", traffic_wl),
                 "per_unit": f"4 B per (tile, splat) pair + {EMIT_BYTES_PER_ITEM} B per item",
                 "units_per_launch": {"pairs": pairs / K, "items": items / K}, "launch_ms": round(t_launch * 1e3, 4)}
     else:
+        ops = None
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                 "frac": None, "traffic": load_traffic(dom, traffic_wl)}
+    # the same work over the committed rocprofv3 average duration of the kernel
+    # (taken on the current kernel sources), beside the live HIP-event one
+    pk = (prof or {}).get({"emit": "tile_emit"}.get(dom, dom))
+    if ops is not None and pk:
+        scale = 1e12 if roof["unit"] == "Tlane-op/s" else 1e9
+        a = ops / (pk["avg_us"] * 1e-6) / scale
+        roof["rocprof"] = {"launch_ms": round(pk["avg_us"] / 1e3, 4), "achieved": round(a, 3),
+                           "frac": round(a / roof["peak"], 4), "valu_busy_pct": pk.get("valu_busy_pct")}
 
     # the loss kernel alone (Eq. 8, one launch for the step's views): HBM-bound,
     # 36 algorithmic bytes per pixel (render and target read, gradient written)
@@ -349,34 +499,61 @@ def main():
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
         del src, dst
 
-    cpu = None
+    cpu = parity = None
     if not args.no_cpu_baseline:
-        t_np = targets[0].cpu().numpy().astype(np.float64)
-        cpu = cpu_baseline(scene_np, step_views[0], lambda v: t_np[v], 15 if paper else 0, int(paper), lam)
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        ms, kn = (15, 1) if paper else (0, 0)
+        # the CPU baseline is the oracle on step 0 (all views, forward +
+        # backward); the same results are step 0's parity check
+        dt, renders, g = oracle_step(scene_np, step_views[0], weights, ms, kn, cores)
+        used = min(cores, oracle.max_threads())    # read before the one-thread run resets it
+        p0 = parity_report(gpu0, renders, g)
+        # the same work on one thread, for the first view only (a quarter of the step)
+        dt1, _, _ = oracle_step(scene_np, step_views[0][:1], weights[:1], ms, kn, 1)
+        cpu = {"value": pix_step / dt / 1e6, "unit": "Mpix/s", "cores": used, "kind": "oracle",
+               "sample": f"step 0 of the trajectory: {V} views x {S}x{S}, forward + backward, FP64, {dt:.1f} s",
+               "one_thread": {"value": S * S / dt1 / 1e6, "unit": "Mpix/s",
+                              "sample": f"view 0 of step 0, forward + backward, FP64, {dt1:.1f} s"}}
         log(f"cpu baseline: {cpu}")
+        _, renders, g = oracle_step(final_np, step_views[k_last], weights, ms, kn, cores)
+        pl = parity_report(gpu_last, renders, g)
+        parity = {"step_0": p0, f"step_{k_last + 1}": pl, "pass": bool(p0["pass"] and pl["pass"]),
+                  "what": f"all {V} views in full, image and T (max-abs <= {IMG_TOL}); gradients of xyz, SH and "
+                          f"opacity in both backward modes (per element <= {GRAD_RTOL} max(|g*|, 1e-2 |g*|inf), "
+                          f"rel-L2 <= {GRAD_L2}) of the linear loss sum(w I), w ~ N(0, 1) seeded; "
+                          f"step {k_last + 1} is the cloud after {k_last + 1} Adam steps, on that step's views"}
+        log(f"parity: step 0 {p0}; step {k_last + 1} {pl}")
+        if not parity["pass"]:
+            log("PARITY FAILED: the throughput figures of this run do not count")
 
     serving = None
     if args.serve_seconds > 0:
         del targets
         torch.cuda.empty_cache()
         serving = bench_serving(args.serve_seconds, args.serve_rate)
+        if args.overload_rate > 0:
+            serving["overload"] = bench_serving(args.overload_seconds, args.overload_rate)
 
     out = {
         "metric": METRIC if not paper else "Mpix/s fwd+bwd, paper-literal renderer (n = 15, normalised Eq. 5), "
                                            "L2 + 0.01 TV loss",
         "value": round(mpix_fb, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": K,
-        "warmup": args.warmup, "ms_per_step": round(t_fb / K * 1e3, 4), "higher_is_better": True,
+        "warmup": W_, "ms_per_step": round(t_fb / K * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "300k points (30% on a 20-bump surface), SH degree 2, 4 views x 800x800 "
-                               "per step, forward + backward (stored T), " +
+                               f"per step, training trajectory of {n_traj} Adam steps (xyz 8e-4, SH 3e-3, "
+                               "opacity logit 1e-2) timed over steps "
+                               f"{W_}..{W_ + K - 1}: forward + backward (stored T) + Adam, " +
                                ("n = 15 splats per pixel, normalised Eq. 5, L2 + 0.01 TV loss" if paper
                                 else "L2 loss"),
                    "points": args.points, "views_per_step": V, "width": S, "height": S,
-                   "persistent": bool(args.persistent)},
+                   "trajectory_steps": n_traj, "persistent": bool(args.persistent)},
         "fwd_mpix_s": mpix_f, "fwd_bwd_mpix_s": round(mpix_fb, 2),
         "fwd_bwd_recompute_mpix_s": mpix_r,
         "stage_ms_per_step": {s_: round(v, 4) for s_, v in breakdown.items()},
         "pairs_per_step": pairs / K, "blended_per_step": blends / K, "step_overheads": overheads,
+        "parity": parity,
         "roofline": roof, "loss_kernel": loss_kernel, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(out), flush=True)
@@ -608,6 +785,7 @@ def bench_serving(seconds: float, rate: float) -> dict:
         srv.run_trace(trace[:20], lambda i, tr: Request(i, tr.scene, tr.camera, 0.0))
     torch.cuda.synchronize()
     for name, slots, mv in (("continuous_batching", 2, 32), ("one_view_per_launch", 1, 1)):
+        log(f"serving {name}: {len(trace)} requests over {seconds:.0f} s at {rate:.0f} req/s")
         srv = Server(RendererExecutor(scenes, n_slots=slots), hbm_budget=budget, max_views=mv)
         t0 = time.perf_counter()
         done = srv.run_trace(trace, lambda i, tr: Request(i, tr.scene, tr.camera, 0.0))
@@ -616,6 +794,10 @@ def bench_serving(seconds: float, rate: float) -> dict:
         st = latency_stats(done, wall)
         st["mean_batch"] = round(float(np.mean(srv.batches)), 2)
         st["max_batch"] = int(max(srv.batches))
+        b = np.asarray(srv.batches)
+        st["batch_views"] = {"p50": float(np.percentile(b, 50)), "p90": float(np.percentile(b, 90)),
+                             "p99": float(np.percentile(b, 99)), "launches": int(b.size),
+                             "share_of_requests_in_batches_of_2_or_more": round(float(b[b >= 2].sum() / b.sum()), 3)}
         st["peak_hbm_bytes"] = int(srv.peak_in_use)
         res[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
         log(f"serving {name}: p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
