@@ -11,17 +11,15 @@ import pytest
 import oracle
 import workloads
 
-# Earlier versions of this path faulted the device: the end of the last voxel
-# was left unset when the last point in voxel order did not open a voxel
-# (k_voxel_average then read past the sorted index array), and fused
-# multiply-adds changed the float32 neighbour distances.  Both are fixed and
-# the fixed kernels are checked on the CPU, under AddressSanitizer and bit for
-# bit against the oracle, by test_hybrid_hostbuild.py; these GPU cases stay
-# skipped until the fixed path has run on a GPU.
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="held off the GPU: the fix of a device fault in this path (unset end of the "
-                                      "last voxel) has not yet run on a GPU; its CPU build passes "
-                                      "test_hybrid_hostbuild.py")]
+# Earlier versions of this path faulted the device: the flat radix sort's
+# histogram lacked the word the scan writes after its last entry, and the end
+# of the last voxel was left unset when the last point in voxel order did not
+# open a voxel (k_voxel_average then read past the sorted index array); fused
+# multiply-adds also changed the float32 neighbour distances.  All are fixed,
+# and the fixed kernels, with the library's own scan and radix sort, run clean
+# under AddressSanitizer and bit for bit against the oracle in
+# test_hybrid_hostbuild.py.
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
