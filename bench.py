@@ -61,23 +61,21 @@ def log(*a):
 
 
 def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
-    profiles/traffic_<workload>.json, if it was taken on the current kernel
-    sources; else None."""
-    from paper_2205_14330_amd.profiling import kernel_source_hash
-    if workload is None:
-        return None
-    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
-    if not os.path.exists(p):
-        return None
-    try:
-        d = json.load(open(p))
-    except (OSError, ValueError):
-        return None
-    e = d.get("kernels", {}).get(kernel)
-    if not e or d.get("source_hash") != kernel_source_hash():
-        return None
-    return e.get("bytes_per_launch")
+    """HBM bytes per launch of `kernel` (rocprofv3 FETCH_SIZE + WRITE_SIZE of
+    the training steps' launches) from the committed profile of `workload`,
+    if it was taken on the current kernel sources; else None."""
+    e = (load_profile(workload) or {}).get(kernel)
+    return None if not e else e.get("bytes_per_launch")
+
+
+def copy_calibration(torch, dev, mib):
+    """One device copy of `mib` MiB: the reference the HBM counters are scaled by."""
+    src = torch.empty(mib * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {mib} MiB read + written")
 
 
 TRAIN_STEPS = 100                 # Adam steps of the training trajectory (at least)
@@ -230,6 +228,9 @@ def main():
     ap.add_argument("--overload-rate", type=float, default=3000.0,
                     help="train: rate of the short overload trace of the serving leg (0 = skip)")
     ap.add_argument("--overload-seconds", type=float, default=2.0)
+    ap.add_argument("--profile", action="store_true",
+                    help="for rocprofv3: set-up, then only `warmup + steps` training steps (no timing events, "
+                         "parity, other legs or serving), then the copy calibration if asked")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this renderer runs on one GPU; --gpus above 1 is not supported "
@@ -371,6 +372,14 @@ def main():
         pair_acc[0] = 0
         item_acc[0] = 0
 
+    if args.profile:
+        dt = run(dpr.RenderParams(**base), True, W_, K)
+        log(f"profile run: {W_} + {K} training steps, {dt / K * 1e3:.3f} ms/step")
+        if args.copy_calibration_mib > 0:
+            copy_calibration(torch, dev, args.copy_calibration_mib)
+        print(json.dumps({"profile_run": True, "ms_per_step": round(dt / K * 1e3, 4)}), flush=True)
+        return
+
     # parity at step 0: the GPU's outputs on the initial cloud (compared with
     # the oracle below, together with the CPU baseline)
     weights = parity_weights(V, S)
@@ -465,7 +474,8 @@ def main():
         scale = 1e12 if roof["unit"] == "Tlane-op/s" else 1e9
         a = ops / (pk["avg_us"] * 1e-6) / scale
         roof["rocprof"] = {"launch_ms": round(pk["avg_us"] / 1e3, 4), "achieved": round(a, 3),
-                           "frac": round(a / roof["peak"], 4), "valu_busy_pct": pk.get("valu_busy_pct")}
+                           "frac": round(a / roof["peak"], 4), "valu_issue_pct": pk.get("valu_issue_pct"),
+                           "salu_per_wave": pk.get("salu_per_wave")}
 
     # the loss kernel alone (Eq. 8, one launch for the step's views): HBM-bound,
     # 36 algorithmic bytes per pixel (render and target read, gradient written)
@@ -491,13 +501,7 @@ def main():
     del imgs
 
     if args.copy_calibration_mib > 0:
-        src = torch.empty(args.copy_calibration_mib * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
-        del src, dst
+        copy_calibration(torch, dev, args.copy_calibration_mib)
 
     cpu = parity = None
     if not args.no_cpu_baseline:

@@ -129,17 +129,23 @@ __device__ __forceinline__ float splat_exponent(const SplatRec &s, float ux, flo
 // Conservative test of whether any pixel centre of tile (tx, ty) can pass the
 // candidate predicate a dx^2 + b dy^2 <= thr of a splat centred at (px, py):
 // the quadratic form at the point of the tile's pixel-centre box closest to
-// the centre is a lower bound for every pixel of the tile.  Used identically
-// by the count and emit kernels, so both see the same (tile, splat) pairs.
+// the centre is a lower bound for every pixel of the tile.  The count and emit
+// kernels must take the same decision for every (splat, tile) pair (the count
+// sizes each tile's list, the emission fills it), so the arithmetic is fixed:
+// contraction is off and every operation rounds once.  (Left to the compiler,
+// the two kernels fused different products into FMAs, and about one decision
+// in 5e7 differed.)
 __device__ __forceinline__ bool splat_touches_tile(float px, float py, float a, float b, float thr, uint32_t tx,
                                                    uint32_t ty) {
+#pragma clang fp contract(off)
     const float x0 = (float)(tx * kTile) + 0.5f, y0 = (float)(ty * kTile) + 0.5f;
     // the tile's pixel centre nearest to the splat centre: px clamped to
     // [x0, x0 + 15] (med3 returns that same value, in one instruction)
     const float cx = __builtin_amdgcn_fmed3f(px, x0, x0 + (float)(kTile - 1));
     const float cy = __builtin_amdgcn_fmed3f(py, y0, y0 + (float)(kTile - 1));
     const float dx = cx - px, dy = cy - py;
-    return a * dx * dx + b * dy * dy <= thr * (1.0f + 1.0f / 1024.0f) + 1.0e-6f;
+    const float qx = (a * dx) * dx, qy = (b * dy) * dy;
+    return qx + qy <= thr * (1.0f + 1.0f / 1024.0f) + 1.0e-6f;
 }
 
 }  // namespace dpr

@@ -15,9 +15,15 @@ steady_stats():  per-kernel statistics from the ``*_kernel_trace.csv`` of the
                  training targets comes before it), with the blend-count
                  forward variant named apart.
 
+summary():       all of the above for the training steps of one workload, plus
+                 SQ counters per dispatch and the VALU issue share, in one
+                 JSON that bench.py reads while its kernel sources match.
+
 Usage:
   python -m paper_2205_14330_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>" [<kernel_trace.csv>]
   python -m paper_2205_14330_amd.profiling traffic <fetch.csv> <write.csv> <copy MiB> <out.json> "<command>"
+  python -m paper_2205_14330_amd.profiling summary <workload> <kernel_trace.csv> <fetch.csv> <write.csv> <copy MiB>
+                                                   <out.json> "<commands>" [<sq counters.csv> ...]
 """
 from __future__ import annotations
 
@@ -156,6 +162,90 @@ def pmc_traffic(fetch_csv: str, write_csv: str, copy_mib: float):
     return res, f_scale, w_scale
 
 
+# MI355X: 256 CUs x 4 SIMDs; a wave64 VALU instruction with VGPR operands
+# issues every 2 clocks per SIMD at most, at the published 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2.0       # wave64 VALU instructions per second
+
+
+def _counter_rows(counter_csv: str):
+    """Per dispatch: (dispatch id, short kernel name, {counter: value})."""
+    by = collections.OrderedDict()
+    for r in csv.DictReader(open(counter_csv)):
+        did = int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0)
+        e = by.setdefault(did, [short_name(r["Kernel_Name"]), {}])
+        e[1][r["Counter_Name"]] = e[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [(d, v[0], v[1]) for d, v in sorted(by.items())]
+
+
+def _steady(rows):
+    """The dispatches from the first backward compositing launch on (the
+    set-up renders of the training targets come before it)."""
+    first = next((i for i, (_, name, _) in enumerate(rows) if name == "composite_bwd"), 0)
+    return rows[first:]
+
+
+def _mean_counters(rows):
+    acc = collections.OrderedDict()
+    for _, name, vals in rows:
+        e = acc.setdefault(name, {"dispatches": 0})
+        e["dispatches"] += 1
+        for k, v in vals.items():
+            e[k] = e.get(k, 0.0) + v
+    for e in acc.values():
+        n = e["dispatches"]
+        for k in list(e):
+            if k != "dispatches":
+                e[k] /= n
+    return acc
+
+
+def summary(workload: str, trace_csv: str, fetch_csv: str, write_csv: str, sq_csvs, copy_mib: float,
+            commands: str, out_json: str):
+    """One JSON per workload: for each kernel, over the launches of the
+    training steps (from the first backward compositing launch on), the
+    average duration (kernel trace), the HBM bytes per launch (FETCH_SIZE and
+    WRITE_SIZE in KiB per dispatch, each scaled by what it reads for the
+    run's device copy of copy_mib MiB) and the SQ counters per dispatch, with
+    the VALU issue share: SQ_INSTS_VALU over the duration at the peak issue
+    rate of one wave64 VALU instruction per 2 clocks per SIMD."""
+    stats = steady_stats(trace_csv)
+    kern = collections.OrderedDict()
+    for name, e in stats.items():
+        kern[name] = {"calls": e["calls"], "avg_us": round(e["avg_ns"] / 1e3, 3)}
+    known = copy_mib * (1 << 20)
+    scales = {}
+    for label, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = _counter_rows(path)
+        copies = [v.get("FETCH_SIZE" if label == "fetch" else "WRITE_SIZE", 0.0) * 1024.0
+                  for _, n, v in rows if "copyBuffer" in n]
+        scale = known / max(copies) if copies else 1.0
+        scales[label] = scale
+        for name, e in _mean_counters(_steady(rows)).items():
+            if name in kern:
+                b = e.get("FETCH_SIZE" if label == "fetch" else "WRITE_SIZE", 0.0) * 1024.0 * scale
+                kern[name][f"{label}_bytes"] = round(b, 1)
+    for k in kern.values():
+        if "fetch_bytes" in k or "write_bytes" in k:
+            k["bytes_per_launch"] = round(k.get("fetch_bytes", 0.0) + k.get("write_bytes", 0.0), 1)
+    for path in sq_csvs:
+        for name, e in _mean_counters(_steady(_counter_rows(path))).items():
+            if name in kern:
+                for c, v in e.items():
+                    if c != "dispatches":
+                        kern[name][c] = round(v, 1)
+    for k in kern.values():
+        if "SQ_INSTS_VALU" in k and k["avg_us"] > 0:
+            k["valu_issue_pct"] = round(100.0 * k["SQ_INSTS_VALU"] / (k["avg_us"] * 1e-6 * VALU_ISSUE_PEAK), 1)
+        if "SQ_INSTS_SALU" in k and "SQ_WAVES" in k and k["SQ_WAVES"] > 0:
+            k["salu_per_wave"] = round(k["SQ_INSTS_SALU"] / k["SQ_WAVES"], 1)
+    doc = {"workload": workload, "commands": commands, "source_hash": kernel_source_hash(),
+           "fetch_scale": scales.get("fetch"), "write_scale": scales.get("write"),
+           "scope": "launches from the first backward compositing launch on (the training steps)",
+           "kernels": kern}
+    json.dump(doc, open(out_json, "w"), indent=1)
+    return doc
+
+
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
         agg = write_stats_txt(argv[1], argv[2], argv[3], argv[4] if len(argv) >= 5 else None)
@@ -167,6 +257,12 @@ def main(argv):
                            for k, v in res.items()}}
         json.dump(doc, open(argv[4], "w"), indent=1)
         print(f"fetch scale {fs:.3f}, write scale {ws:.3f}")
+    elif len(argv) >= 8 and argv[0] == "summary":
+        # summary <workload> <trace csv> <fetch csv> <write csv> <copy MiB> <out json> "<commands>" [sq csv ...]
+        doc = summary(argv[1], argv[2], argv[3], argv[4], argv[8:], float(argv[5]), argv[7], argv[6])
+        for name, k in list(doc["kernels"].items())[:8]:
+            print(name, {kk: vv for kk, vv in k.items() if kk in ("avg_us", "bytes_per_launch", "valu_issue_pct",
+                                                                  "salu_per_wave")})
     else:
         print(__doc__)
         return 2

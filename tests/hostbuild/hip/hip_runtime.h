@@ -48,6 +48,9 @@ struct float2 { float x, y; };
 struct float4 { float x, y, z, w; };
 struct uint2 { uint32_t x, y; };
 struct uint4 { uint32_t x, y, z, w; };
+inline uint2 make_uint2(uint32_t x, uint32_t y) { return uint2{x, y}; }
+inline float2 make_float2(float x, float y) { return float2{x, y}; }
+inline float4 make_float4(float x, float y, float z, float w) { return float4{x, y, z, w}; }
 
 typedef int hipError_t;
 constexpr hipError_t hipSuccess = 0;
@@ -196,6 +199,11 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
 
 inline int __lane_id() { return (int)(threadIdx.x & 63u); }
 
+// The lanes of a wave run in lockstep on the GPU; here they meet at a barrier.
+inline void __builtin_amdgcn_wave_barrier() {
+    hostrt::pool().block().wave[threadIdx.x / 64]->arrive_and_wait();
+}
+
 // Lane l receives lane l - delta's value; lanes below delta keep their own.
 template <class T>
 inline T __shfl_up(T v, unsigned delta, int width = 64) {
@@ -247,6 +255,7 @@ inline double atomicAdd(double *p, double v) {
     return o;
 }
 inline uint32_t atomicAdd(uint32_t *p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
+inline uint32_t atomicOr(uint32_t *p, uint32_t v) { return __atomic_fetch_or(p, v, __ATOMIC_RELAXED); }
 
 inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
 inline int __popc(uint32_t x) { return __builtin_popcount(x); }
