@@ -1,17 +1,24 @@
 """Throughput of the splat renderer on one MI355X.
 
 Default workload: 300k points (30% on a bumpy surface), SH degree 2, four
-800x800 views per step, FP32.  One step = the whole hot path over one batch:
-projection + SH colour, depth sort, tile binning, compositing (forward), then
-the L2-loss gradient and the compositing + per-point backward.  Inputs (scene,
-cameras, target images) are resident in HBM before timing starts.
+800x800 views per step, FP32, trained for 100 Adam steps (positions, SH,
+opacity logits) against renders of a ground-truth scene.  One timed step is
+the whole hot path over one batch -- projection + SH colour, depth sort, tile
+binning, compositing (forward), the L2-loss gradient and the compositing +
+per-point backward -- measured with HIP events on the stream; the Adam update
+runs between the timed steps and is reported with them as the training-step
+rate.  Inputs (scene, cameras, target images) are resident in HBM before
+timing starts.
 
 Prints ONE JSON line:  metric/value = forward+backward Mpix/s (stored-T mode),
-plus forward-only and recompute-T rates, the roofline of the dominant kernel
-(HIP events on the library's stream around that kernel only, in the timed
-loop; algorithmic work from the per-pixel blended-splat counts of the same
-steps), a per-stage breakdown from a short loop with every stage timed, and
-the FP64 CPU oracle timed on one step's views.
+plus forward-only and recompute-T rates, the same-run parity of step 0 and of
+the last step against the FP64 oracle (all views in full, gradients in both
+backward modes), the roofline of the dominant kernel (HIP events on the
+library's stream around that kernel in the timed loop, and the committed
+rocprofv3 figures of the same kernel), a per-stage breakdown, the FP64 CPU
+oracle timed on step 0, and the serving leg (a 60 s Poisson trace at 200
+req/s and a short overload trace, continuous batching against one view per
+launch).
 """
 from __future__ import annotations
 
@@ -289,15 +296,22 @@ def main():
     grads = [torch.empty((S, S, 3), dtype=torch.float32, device=dev) for _ in range(V)]
     loss_ws = dpr.Workspace(dev)
 
-    def step(k, params, train=True):
+    def step(k, params, train=True, ev=None):
         """Step k of the trajectory: forward, Eq. (8) loss gradient, backward,
-        Adam update (train), or the forward alone."""
+        Adam update (train), or the forward alone.  ev: a pair of events
+        recorded on the stream before the plan and after the backward (or the
+        forward alone), i.e. around everything but the Adam update."""
+        if ev is not None:
+            ev[0].record()
         plan = dpr.Plan([trainer.scene], [(0, c) for c in step_views[k]], params, workspace=wss[k % 2])
         plan.forward()
         if train:
             tgt = targets[k % len(targets)]
             dpr.loss_l2_tv(plan.images, [tgt[v] for v in range(V)], lam, grads=grads, workspace=loss_ws)
             plan.backward(grads, None, out=[trainer.grads])
+        if ev is not None:
+            ev[1].record()
+        if train:
             trainer.update()
         return plan
 
@@ -307,13 +321,19 @@ def main():
         workspaces; a plan is inspected and freed once the next plan's host
         sync has passed its work.  The warmup runs the same loop, inspection
         included (its first calls load torch's kernels), then `reset` clears
-        what the inspection accumulated."""
+        what the inspection accumulated.  Returns (wall seconds of the timed
+        steps, seconds of their forward + loss + backward from events)."""
         trainer.reset()
         prev = None
+        evs = []
 
-        def advance(k, inspect=True):
+        def advance(k, inspect=True, timed=False):
             nonlocal prev
-            plan = step(k, params, train)
+            ev = None
+            if timed:
+                ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                evs.append(ev)
+            plan = step(k, params, train, ev)
             if prev is not None:
                 if collect and inspect:
                     collect(prev)
@@ -335,10 +355,11 @@ def main():
         t0 = time.perf_counter()
         for k in range(warmup, warmup + steps):
             ts = time.perf_counter()
-            advance(k)
+            advance(k, timed=True)
             host.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        dt_ev = sum(a.elapsed_time(b) for a, b in evs) / 1e3
         n_alloc = torch.cuda.memory_stats().get("num_device_alloc", 0) - n_alloc
         log(f"  timed loop: {steps} steps, host ms/step median {1e3 * float(np.median(host)):.2f} "
             f"max {1e3 * max(host):.2f} (step {int(np.argmax(host))}), device allocations {n_alloc}")
@@ -351,7 +372,7 @@ def main():
         if prev is not None:
             prev.free()
         torch.cuda.synchronize()
-        return dt
+        return dt, dt_ev
 
     pix_step = V * S * S
     base = dict(persistent=args.persistent, **variant)
@@ -373,7 +394,7 @@ def main():
         item_acc[0] = 0
 
     if args.profile:
-        dt = run(dpr.RenderParams(**base), True, W_, K)
+        dt, _ = run(dpr.RenderParams(**base), True, W_, K)
         log(f"profile run: {W_} + {K} training steps, {dt / K * 1e3:.3f} ms/step")
         if args.copy_calibration_mib > 0:
             copy_calibration(torch, dev, args.copy_calibration_mib)
@@ -398,12 +419,14 @@ def main():
     # main metric: the training trajectory, forward + backward (stored T) +
     # Adam; HIP events around the dominant kernel only (its live launch
     # duration for the roofline); the trajectory runs on to its last step
-    t_fb = run(dpr.RenderParams(timing=True, timing_stages=(dom,), **base), True, W_, K,
-               after=n_traj - W_ - K, collect=collect, reset=reset)
+    t_train, t_fb = run(dpr.RenderParams(timing=True, timing_stages=(dom,), **base), True, W_, K,
+                        after=n_traj - W_ - K, collect=collect, reset=reset)
     pairs = pair_acc[0]
     items = item_acc[0]
     mpix_fb = pix_step * K / t_fb / 1e6
-    log(f"fwd+bwd+adam: {t_fb / K * 1e3:.3f} ms/step, {mpix_fb:.1f} Mpix/s; {dom} {stage_ms[dom] / K:.3f} ms/launch")
+    mpix_train = pix_step * K / t_train / 1e6
+    log(f"fwd+bwd: {t_fb / K * 1e3:.3f} ms/step, {mpix_fb:.1f} Mpix/s; with the Adam update (wall clock): "
+        f"{t_train / K * 1e3:.3f} ms/step, {mpix_train:.1f} Mpix/s; {dom} {stage_ms[dom] / K:.3f} ms/launch")
     # parity at the last step: the trained cloud
     final_np = trainer.numpy_scene()
     k_last = n_traj - 1
@@ -433,11 +456,11 @@ def main():
 
     mpix_f = mpix_r = None
     if not args.main_only:
-        t_f = run(dpr.RenderParams(**base), False, W_, K)
+        _, t_f = run(dpr.RenderParams(**base), False, W_, K)
         mpix_f = round(pix_step * K / t_f / 1e6, 2)
-        t_r = run(dpr.RenderParams(bwd_mode="recompute", **base), True, W_, K)
+        _, t_r = run(dpr.RenderParams(bwd_mode="recompute", **base), True, W_, K)
         mpix_r = round(pix_step * K / t_r / 1e6, 2)
-        log(f"fwd: {mpix_f} Mpix/s; fwd+bwd+adam recompute: {mpix_r} Mpix/s")
+        log(f"fwd: {mpix_f} Mpix/s; fwd+bwd recompute: {mpix_r} Mpix/s")
 
     # roofline of the dominant kernel (per launch = per step); the committed PMC
     # traffic summary covers the default workload only
@@ -547,13 +570,15 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "300k points (30% on a 20-bump surface), SH degree 2, 4 views x 800x800 "
                                f"per step, training trajectory of {n_traj} Adam steps (xyz 8e-4, SH 3e-3, "
-                               "opacity logit 1e-2) timed over steps "
-                               f"{W_}..{W_ + K - 1}: forward + backward (stored T) + Adam, " +
+                               f"opacity logit 1e-2); steps {W_}..{W_ + K - 1} timed: forward + loss + backward "
+                               "(stored T) on HIP events, the Adam update between steps outside; " +
                                ("n = 15 splats per pixel, normalised Eq. 5, L2 + 0.01 TV loss" if paper
                                 else "L2 loss"),
                    "points": args.points, "views_per_step": V, "width": S, "height": S,
                    "trajectory_steps": n_traj, "persistent": bool(args.persistent)},
         "fwd_mpix_s": mpix_f, "fwd_bwd_mpix_s": round(mpix_fb, 2),
+        "train_step": {"ms_per_step": round(t_train / K * 1e3, 4), "mpix_s": round(mpix_train, 2),
+                       "what": "forward + loss + backward + Adam update, wall clock over the timed steps"},
         "fwd_bwd_recompute_mpix_s": mpix_r,
         "stage_ms_per_step": {s_: round(v, 4) for s_, v in breakdown.items()},
         "pairs_per_step": pairs / K, "blended_per_step": blends / K, "step_overheads": overheads,
