@@ -225,7 +225,7 @@ def main():
                     help="time only the forward + backward metric (skip the forward-only and recompute legs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (reference for HBM counters)")
-    ap.add_argument("--workload", choices=["train", "paper", "dynamic", "serve", "hull", "warmstart"],
+    ap.add_argument("--workload", choices=["train", "paper", "dynamic", "serve", "hull", "warmstart", "hybrid"],
                     default="train",
                     help="train: the default step; paper: the same step with the paper-literal renderer "
                          "(n = 15 splats per pixel, normalised Eq. 5) and the L2 + 0.01 TV loss")
@@ -259,6 +259,8 @@ def main():
         return bench_hull(args)
     if args.workload == "warmstart":
         return bench_warmstart(args)
+    if args.workload == "hybrid":
+        return bench_hybrid(args)
     if args.workload == "serve":
         out = {"metric": "served p50/p99 latency and Mpix/s (16 resident scenes, Poisson requests)",
                "n_gpus": 1, "dtype": "f32", "data": "synthetic"}
@@ -730,6 +732,100 @@ def bench_warmstart(args):
                      "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
                      "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": None,
                      "per_unit": f"{NN_OPS_PER_PAIR} lane-ops per pair distance", "units_per_launch": pairs},
+    }), flush=True)
+
+
+HYBRID_N, HYBRID_K, HYBRID_EPS = 128, 8, 0.01     # voxel grid, neighbours, spread threshold
+
+
+def bench_hybrid(args):
+    """Hybrid coarse-to-fine update (Sec. 3.3, Alg. 1) of the 300k-point
+    training cloud: voxel reduction on a 128^3 grid, removal of points whose
+    8-neighbour distance spread exceeds 0.01, one generated point per kept
+    point.  Timed per call (each call waits once per stage for a count); also
+    the voxel reduction and the neighbour search alone.  Parity: the points of
+    the corner box x, y < -0.5, z < 0 (about 6.5k, at the cloud's density) bit
+    for bit against the oracle, and the full cloud's voxel count against the
+    oracle's voxel keys."""
+    import torch
+    import workloads
+    import oracle
+    import paper_2205_14330_amd as dpr
+    from paper_2205_14330_amd import hybrid as hy
+    scene_np, _, _ = workloads.surface300k_4x800(steps=1)
+    scene = dpr.SceneTensors.from_numpy(scene_np)
+    N, Kn, eps = HYBRID_N, HYBRID_K, HYBRID_EPS
+    K, W = args.steps, args.warmup
+    for _ in range(W):
+        hy.hybrid_update(scene, N, Kn, eps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        out, counts = hy.hybrid_update(scene, N, Kn, eps)
+    torch.cuda.synchronize()
+    t_call = (time.perf_counter() - t0) / K
+    for _ in range(W):
+        hy.voxel_reduce(scene, N)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        red = hy.voxel_reduce(scene, N)
+    torch.cuda.synchronize()
+    t_red = (time.perf_counter() - t0) / K
+    rxyz = red.xyz.contiguous()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(W):
+        hy.knn(rxyz, Kn)
+    e0.record()
+    for _ in range(K):
+        hy.knn(rxyz, Kn)
+    e1.record()
+    torch.cuda.synchronize()
+    t_knn = e0.elapsed_time(e1) / K / 1e3
+    # parity: the full cloud's voxels, and a subset bit for bit
+    n_vox = len(np.unique(oracle.voxel_keys(scene_np.xyz, N)))
+    x = scene_np.xyz
+    sub = np.flatnonzero((x[:, 0] < -0.5) & (x[:, 1] < -0.5) & (x[:, 2] < 0.0))
+    c = oracle.Cloud(scene_np.xyz[sub], scene_np.sh[sub], scene_np.opacity[sub], scene_np.radius[sub])
+    got, gcounts = hy.hybrid_update(dpr.SceneTensors.from_numpy(c), N, Kn, eps)
+    t0 = time.perf_counter()
+    ref_red, ref_keep, ref = oracle.hybrid_update(c, N, Kn, eps)
+    t_cpu = time.perf_counter() - t0
+    mism = 0
+    for g, r in zip((got.xyz, got.sh, got.opacity, got.radius), (ref.xyz, ref.sh, ref.opacity, ref.radius)):
+        g = g.cpu().numpy()
+        r32 = np.asarray(r).astype(np.float32)
+        mism += int(g.size) if g.shape != r32.shape else int((g != r32).sum())
+    ok = mism == 0 and counts["voxels"] == n_vox and gcounts["voxels"] == ref_red.n
+    n = scene.n
+    k3 = scene_np.sh.shape[1] * 3
+    bytes_pt = 4 * (3 + k3 + 2)            # one point's parameters
+    algo = n * bytes_pt + counts["points"] * bytes_pt
+    achieved = algo / t_call
+    log(f"hybrid update: {n} points -> {counts['voxels']} voxels, {counts['kept']} kept, {counts['points']} out; "
+        f"{t_call * 1e3:.3f} ms/call ({n / t_call / 1e6:.1f} Mpoints/s); voxel reduce {t_red * 1e3:.3f} ms, "
+        f"knn {t_knn * 1e3:.3f} ms; parity {'pass' if ok else 'FAIL'} ({mism} mismatches); "
+        f"oracle {len(sub)} pts {t_cpu:.2f} s")
+    print(json.dumps({
+        "metric": "hybrid coarse-to-fine update (Alg. 1) of the 300k-point training cloud, input points per second",
+        "value": round(n / t_call / 1e6, 3), "unit": "Mpoints/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(t_call * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f64 sums)", "data": "synthetic",
+        "config": {"workload": f"300k-point surface cloud, SH degree 2; voxel grid {N}^3, K = {Kn}, eps = {eps}",
+                   "points": n, "N": N, "K": Kn, "eps": eps},
+        "counts": counts, "voxel_reduce_ms": round(t_red * 1e3, 4), "knn_ms": round(t_knn * 1e3, 4),
+        "parity": {"pass": bool(ok), "subset_points": int(len(sub)), "mismatched_values": mism,
+                   "full_voxels": counts["voxels"], "oracle_full_voxels": n_vox,
+                   "what": "the corner-box subset: every output value bit for bit against the oracle; "
+                           "full cloud: voxel count against the oracle's voxel keys"},
+        "roofline": {"kernel": "dpr_hybrid_update call", "bound": "hbm", "achieved": round(achieved / 1e9, 2),
+                     "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 5),
+                     "traffic": None,
+                     "per_unit": f"{bytes_pt} B read per input point + {bytes_pt} B written per output point "
+                                 "(the parameters once each way)", "units_per_launch": n},
+        "cpu_baseline": {"value": round(len(sub) / t_cpu / 1e6, 5), "unit": "Mpoints/s",
+                         "cores": 1, "kind": "oracle",
+                         "sample": f"the {len(sub)}-point corner-box subset (brute-force neighbours)"},
     }), flush=True)
 
 

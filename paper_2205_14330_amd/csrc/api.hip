@@ -191,7 +191,6 @@ struct dpr_plan {
     std::vector<uint32_t> u32tab;
     uint8_t *pws = nullptr;
     uint64_t pairs = 0;
-    uint64_t total_host[2] = {0, 0};
     int forward_done = 0;
     const void *fwd_ws = nullptr;
     Events ev;
@@ -633,9 +632,7 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
         STAGE_TRY(launch_tile_order(tile_total, (uint32_t)s.tiles, bucket_cnt,
                                     reinterpret_cast<uint32_t *>(w + lay.tile_order.off), st));
     }
-    STAGE_TRY(hipMemcpyAsync(p->total_host, total64, 8, hipMemcpyDeviceToHost, st));
-    STAGE_TRY(hipStreamSynchronize(st));
-    p->pairs = p->total_host[0];
+    STAGE_TRY(read_count(total64, &p->pairs, st));
     if (p->pairs >= 0xFFFFFFFFull)
         return cleanup_fail(fail(DPR_ERR_UNSUPPORTED, "%llu (tile, splat) pairs exceed 2^32 - 1",
                                  (unsigned long long)p->pairs));

@@ -668,6 +668,21 @@ hipError_t upload_async(void *dst, const void *src, size_t bytes, hipStream_t st
     return hipSuccess;
 }
 
+hipError_t read_count(const uint64_t *dev, uint64_t *out, hipStream_t st) {
+    // a pageable destination would go through the runtime's staging buffer
+    thread_local uint64_t *pinned = nullptr;
+    if (!pinned) {
+        void *h = nullptr;
+        const hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        pinned = static_cast<uint64_t *>(h);
+    }
+    hipError_t e = hipMemcpyAsync(pinned, dev, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) *out = *pinned;
+    return e;
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, uint64_t n) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;

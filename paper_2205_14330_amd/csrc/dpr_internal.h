@@ -355,6 +355,10 @@ uint32_t loss_blocks(int32_t width, int32_t height);
 hipError_t launch_loss(const LossImage *img, int n, float lambda, float *partial, double *loss, hipStream_t st);
 // Stream-ordered copy of a small host table (bytes % 4 == 0) through kernel arguments.
 hipError_t upload_async(void *dst, const void *src, size_t bytes, hipStream_t st);
+// Reads one 64-bit count that work queued on `st` produces: copies it into a
+// pinned host word of the calling thread (allocated on the thread's first
+// call and kept until the process ends), waits for the stream, stores it in *out.
+hipError_t read_count(const uint64_t *dev, uint64_t *out, hipStream_t st);
 
 // Sets the thread's dpr_last_error message and returns `code`.
 int set_last_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));

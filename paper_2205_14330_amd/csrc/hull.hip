@@ -287,9 +287,7 @@ hipError_t launch_hull(const HullJob &job, uint8_t *ws, uint64_t *kept_host, hip
         if (e != hipSuccess) return e;
     }
     if (!job.sync) return hipSuccess;
-    e = hipMemcpyAsync(kept_host, total, 8, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(st);
+    return read_count(total, kept_host, st);
 }
 
 }  // namespace dpr

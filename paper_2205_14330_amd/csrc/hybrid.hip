@@ -395,9 +395,7 @@ hipError_t launch_voxel_reduce(const float *xyz, const float *sh, const float *o
     e = launch_scan(s.flags, s.seg, n, s.part, s.total64, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_seg_starts, dim3(blocks_for(n)), dim3(kHyThreads), 0, st, s.flags, s.seg, n, s.starts);
-    e = hipMemcpyAsync(m_host, s.total64, 8, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(st);
+    e = read_count(s.total64, m_host, st);
     if (e != hipSuccess) return e;
     const uint32_t m = (uint32_t)*m_host;
     CloudIn in{xyz, sh, op, rad};
@@ -422,9 +420,7 @@ hipError_t launch_filter_generate(const float *xyz, const float *sh, const float
     CloudIn in{xyz, sh, op, rad};
     CloudOut out{oxyz, osh, oop, orad};
     hipLaunchKernelGGL(k_gather_kept, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, s.flags, s.seg, m, in, k3, out);
-    e = hipMemcpyAsync(kept_host, s.total64, 8, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(st);
+    e = read_count(s.total64, kept_host, st);
     if (e != hipSuccess) return e;
     const uint32_t mk = (uint32_t)*kept_host;
     *count_host = mk;
