@@ -9,9 +9,9 @@
 //   colscan: per tile, an exclusive scan down the chunk column (in place) and
 //            the column total; an exclusive scan of the totals (tile_base)
 //            gives every tile's list range [tile_base[t], tile_base[t + 1]);
-//   emit   : per chunk, one wave walks the items in depth order and appends
-//            each to every tile it touches through an LDS cursor per tile,
-//            starting at tile_base[t] + cnt[chunk][t].
+//   emit   : per chunk, an LDS bitmap per tile of which of the chunk's items
+//            touch it, read back in item order: each tile's run of the chunk
+//            is written contiguously at tile_base[t] + cnt[chunk][t].
 // Within a tile the lists come out in chunk order, and inside a chunk in item
 // order, i.e. exactly ascending (depth, point index): the front-to-back order
 // of Eq. (6)-(7).  The only pass over all pairs is the 4-byte write of emit.
@@ -20,7 +20,6 @@
 namespace dpr {
 
 constexpr int kCountThreads = 256;
-constexpr int kEmitLanes = 64;
 constexpr int kColThreads = 256;
 
 struct ChunkInfo {
@@ -208,137 +207,113 @@ hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, 
 // ---------------------------------------------------------------------------
 // emit
 // ---------------------------------------------------------------------------
-struct EmitItem {
-    uint32_t g, x0, y0, w, n;
-    float inv_w;
-    float px, py, a, b, thr;
-};
+// One workgroup per chunk.  The chunk's items are staged in LDS, and the
+// view's tiles are taken in bands: a rectangle of whole tile rows (as many as
+// fit kEmitBand tiles), or of a part of one row on views wider than kEmitBand
+// tiles.  Per band:
+//   mark : each thread takes items (i = tid, tid + kEmitThreads, ...) and sets
+//          bit i of the bitmap of every tile of the band it touches, and the
+//          bit of that bitmap word in the tile's word summary (LDS atomic OR:
+//          the order of the updates does not matter, a bit's place is the
+//          item's place in the chunk);
+//   write: each thread takes a tile and walks the non-empty words of its
+//          bitmap in bit order, so the tile's segment comes out in item order,
+//          stored by one lane in consecutive instructions at
+//          tile_base[t] + cnt[chunk][t] (loaded while the band is marked); it
+//          clears the words it reads, so the next band starts clear.
+// Every (item, tile) decision is splat_touches_tile, as in the count, so each
+// segment has exactly the length the count reserved.
+constexpr int kEmitThreads = 512;
+constexpr int kEmitBand = 512;                 // tiles per band (at most)
+constexpr int kEmitWords = kChunkItems / 32;   // bitmap words per tile
+constexpr int kEmitTilesPerThread = (kEmitBand + kEmitThreads - 1) / kEmitThreads;
+static_assert(kChunkItems % 32 == 0 && kEmitWords <= 32, "whole bitmap words, one summary word");
 
-// The items of a batch of 64 are staged in LDS, one per lane, and each is read
-// back as an LDS broadcast: its fields then sit in VGPRs, and the arithmetic of
-// the tile test issues at the VGPR-operand rate (an SGPR operand, as left by a
-// readlane, costs about twice as much per instruction).
-struct EmitStage {
-    float4 shape;      // px, py, a, b
-    float4 misc;       // thr, 1 / w, g (bits), x0 | y0 << 16 (bits)
-    uint2 wn;          // w, n
-};
-
-__device__ __forceinline__ void stage_item(EmitStage &st, uint32_t g, uint32_t ra, uint32_t rb, const float4 &shape,
-                                           float thr) {
-    const uint32_t x0 = ra & 0xFFFFu, y0 = ra >> 16;
-    const uint32_t x1 = rb & 0xFFFFu, y1 = rb >> 16;
-    const uint32_t w = x1 > x0 ? x1 - x0 : 0u;
-    const uint32_t h = y1 > y0 ? y1 - y0 : 0u;
-    st.shape = shape;
-    st.misc = make_float4(thr, w ? __builtin_amdgcn_rcpf((float)w) : 0.f, __uint_as_float(g), __uint_as_float(ra));
-    st.wn = make_uint2(w, w * h);
-}
-
-__device__ __forceinline__ EmitItem emit_item(const EmitStage *stage, uint32_t j) {
-    const EmitStage &st = stage[j];
-    const float4 shape = st.shape, misc = st.misc;
-    const uint2 wn = st.wn;
-    EmitItem it;
-    it.px = shape.x;
-    it.py = shape.y;
-    it.a = shape.z;
-    it.b = shape.w;
-    it.thr = misc.x;
-    it.inv_w = misc.y;
-    it.g = __float_as_uint(misc.z);
-    const uint32_t ra = __float_as_uint(misc.w);
-    it.x0 = ra & 0xFFFFu;
-    it.y0 = ra >> 16;
-    it.w = wn.x;
-    it.n = wn.y;
-    return it;
-}
-
-// Appends one item to all its tiles (any rectangle size); cell k of the
-// rectangle is row floor((k + 0.5) / w), exact for k < 2^20 and w <= 1024.
-__device__ __forceinline__ void emit_one(const EmitItem &it, uint32_t lane, uint32_t tiles_x, uint32_t band,
-                                         uint32_t bend, uint32_t *s_pos, uint32_t *pairs) {
-    for (uint32_t k = lane; k < it.n; k += kEmitLanes) {
-        const uint32_t r = (uint32_t)(((float)k + 0.5f) * it.inv_w);
-        const uint32_t cx = it.x0 + k - r * it.w, cy = it.y0 + r;
-        const uint32_t tt = cy * tiles_x + cx;
-        if (tt >= band && tt < bend && splat_touches_tile(it.px, it.py, it.a, it.b, it.thr, cx, cy))
-            pairs[atomicAdd(&s_pos[tt - band], 1u)] = it.g;
-    }
-}
-
-// One wave per chunk.  Items are appended strictly in depth order; four items
-// are interleaved so that their LDS cursor updates are in flight together
-// (LDS operations of one wave complete in program order, so a tile touched by
-// two of them still receives them in order).
-__global__ __launch_bounds__(kEmitLanes) void k_tile_emit(Tables tb, const uint32_t *order, const uint2 *rect,
-                                                           const SplatRec *rec, float lambda, const uint32_t *pre,
-                                                           const uint32_t *tile_base, uint32_t *pairs,
-                                                           uint32_t band_tiles) {
-    extern __shared__ uint32_t s_pos[];    // [band_tiles]
-    __shared__ EmitStage s_stage[kEmitLanes];
+__global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uint32_t *order, const uint2 *rect,
+                                                             const SplatRec *rec, float lambda, const uint32_t *pre,
+                                                             const uint32_t *tile_base, uint32_t *pairs) {
+    // word w of band tile b at s_bits[w * kEmitBand + b]: the write phase's
+    // lanes (consecutive tiles) read consecutive words
+    __shared__ uint32_t s_bits[kEmitWords * kEmitBand];
+    __shared__ uint32_t s_sum[kEmitBand];
+    __shared__ uint32_t s_g[kChunkItems];
+    __shared__ uint2 s_rect[kChunkItems];
     const ChunkInfo ci = chunk_info(tb);
-    const uint32_t lane = threadIdx.x;
-    const uint32_t tx = (uint32_t)ci.tiles_x;
-    for (uint32_t band = 0; band < ci.ntiles; band += band_tiles) {
-        const uint32_t bend = min(band + band_tiles, ci.ntiles);
-        const uint32_t nb_t = bend - band;
-        for (uint32_t t = lane; t < nb_t; t += kEmitLanes)
-            s_pos[t] = tile_base[ci.tile_off + band + t] + pre[ci.row + band + t];
-        __syncthreads();
-        for (uint32_t s0 = ci.beg; s0 < ci.end; s0 += kEmitLanes) {
-            const uint32_t my = s0 + lane;
-            uint32_t g = 0;
-            uint2 rc = make_uint2(0u, 0u);
-            float4 shape = make_float4(0.f, 0.f, 0.f, 0.f);
-            float thr = -1.f;
-            if (my < ci.end) {
-                g = order[my];
-                rc = rect[g];
-                shape = reinterpret_cast<const float4 *>(rec + g)[0];
-                thr = reinterpret_cast<const float4 *>(rec + g)[1].x + lambda;
-            }
-            __syncthreads();                 // the previous batch's broadcasts are done (one wave: cheap)
-            stage_item(s_stage[lane], g, rc.x, rc.y, shape, thr);
-            __syncthreads();
-            const uint32_t nb = min((uint32_t)kEmitLanes, ci.end - s0);
-            uint32_t j = 0;
-            for (; j + 4 <= nb; j += 4) {
-                EmitItem it[4];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t n = ci.end - ci.beg;
+    for (uint32_t i = tid; i < n; i += kEmitThreads) {
+        const uint32_t g = order[ci.beg + i];
+        s_g[i] = g;
+        s_rect[i] = rect[g];
+    }
+    {
+        // the bitmaps start clear; the write phase clears the words it reads
+        uint4 *const z = reinterpret_cast<uint4 *>(s_bits);
+        for (uint32_t k = tid; k < (uint32_t)(kEmitWords * kEmitBand / 4); k += kEmitThreads)
+            z[k] = make_uint4(0u, 0u, 0u, 0u);
+        for (uint32_t k = tid; k < (uint32_t)kEmitBand; k += kEmitThreads) s_sum[k] = 0u;
+    }
+    const uint32_t TX = (uint32_t)ci.tiles_x, TY = TX ? ci.ntiles / TX : 0u;
+    const uint32_t bw = min(TX, (uint32_t)kEmitBand), bh = (uint32_t)kEmitBand / max(bw, 1u);
+    for (uint32_t r0 = 0; r0 < TY; r0 += bh) {
+        for (uint32_t c0 = 0; c0 < TX; c0 += bw) {
+            const uint32_t r1 = min(r0 + bh, TY), c1 = min(c0 + bw, TX);
+            const uint32_t bwid = c1 - c0, nt = bwid * (r1 - r0);
+            // the band's segment starts, in flight while the band is marked
+            uint32_t pos[kEmitTilesPerThread];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) it[q] = emit_item(s_stage, j + q);
-                const uint32_t nmax = max(max(it[0].n, it[1].n), max(it[2].n, it[3].n));
-                if (nmax <= (uint32_t)kEmitLanes) {
-                    uint32_t t[4], p[4];
-                    bool on[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        on[q] = false;
-                        t[q] = 0;
-                        if (lane < it[q].n) {
-                            const uint32_t r = (uint32_t)(((float)lane + 0.5f) * it[q].inv_w);
-                            const uint32_t cx = it[q].x0 + lane - r * it[q].w, cy = it[q].y0 + r;
-                            const uint32_t tt = cy * tx + cx;
-                            on[q] = tt >= band && tt < bend &&
-                                    splat_touches_tile(it[q].px, it[q].py, it[q].a, it[q].b, it[q].thr, cx, cy);
-                            t[q] = tt - band;
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (on[q]) p[q] = atomicAdd(&s_pos[t[q]], 1u);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (on[q]) pairs[p[q]] = it[q].g;
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) emit_one(it[q], lane, tx, band, bend, s_pos, pairs);
+            for (int q = 0; q < kEmitTilesPerThread; ++q) {
+                const uint32_t lt = tid + (uint32_t)q * kEmitThreads;
+                pos[q] = 0;
+                if (lt < nt) {
+                    const uint32_t rr = lt / bwid, t = (r0 + rr) * TX + c0 + (lt - rr * bwid);
+                    pos[q] = tile_base[ci.tile_off + t] + pre[ci.row + t];
                 }
             }
-            for (; j < nb; ++j) emit_one(emit_item(s_stage, j), lane, tx, band, bend, s_pos, pairs);
+            __syncthreads();              // the bitmaps are clear; the staged items are published
+            for (uint32_t i = tid; i < n; i += kEmitThreads) {
+                const uint2 rc = s_rect[i];
+                const uint32_t x0 = max(rc.x & 0xFFFFu, c0), y0 = max(rc.x >> 16, r0);
+                const uint32_t x1 = min(rc.y & 0xFFFFu, c1), y1 = min(rc.y >> 16, r1);
+                if (x1 <= x0 || y1 <= y0) continue;
+                const float4 *rr_ = reinterpret_cast<const float4 *>(rec + s_g[i]);
+                const float4 sh = rr_[0];
+                const float thr = rr_[1].x + lambda;
+                const uint32_t bit = 1u << (i & 31u), word = i >> 5, wbit = 1u << word;
+                uint32_t *const bits = s_bits + word * (uint32_t)kEmitBand;
+                for (uint32_t ty = y0; ty < y1; ++ty) {
+                    const uint32_t rowb = (ty - r0) * bw - c0;
+                    for (uint32_t cx = x0; cx < x1; ++cx) {
+                        if (splat_touches_tile(sh.x, sh.y, sh.z, sh.w, thr, cx, ty)) {
+                            atomicOr(&bits[rowb + cx], bit);
+                            atomicOr(&s_sum[rowb + cx], wbit);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kEmitTilesPerThread; ++q) {
+                const uint32_t lt = tid + (uint32_t)q * kEmitThreads;
+                if (lt >= nt) continue;
+                const uint32_t rr = lt / bwid, b = rr * bw + (lt - rr * bwid);
+                uint32_t p = pos[q];
+                uint32_t words = s_sum[b];
+                s_sum[b] = 0u;
+                while (words) {
+                    const uint32_t w = (uint32_t)__builtin_ctz(words);
+                    words &= words - 1u;
+                    uint32_t m = s_bits[w * (uint32_t)kEmitBand + b];
+                    s_bits[w * (uint32_t)kEmitBand + b] = 0u;
+                    while (m) {
+                        const uint32_t k = (uint32_t)__builtin_ctz(m);
+                        m &= m - 1u;
+                        pairs[p++] = s_g[w * 32u + k];
+                    }
+                }
+            }
+            __syncthreads();              // the bitmaps are read before the next band clears them
         }
-        __syncthreads();
     }
 }
 
@@ -359,9 +334,8 @@ hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *o
                             const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
                             const uint32_t *tile_base, uint32_t *pairs, hipStream_t st) {
     if (chunks == 0) return hipSuccess;
-    const uint32_t band = band_for(tb);
-    hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitLanes), (size_t)band * 4, st, tb, order, rect, rec,
-                       lambda, pre, tile_base, pairs, band);
+    hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitThreads), 0, st, tb, order, rect, rec, lambda, pre,
+                       tile_base, pairs);
     return hipGetLastError();
 }
 

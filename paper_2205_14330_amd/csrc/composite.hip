@@ -2,13 +2,14 @@
 // derivative.
 //
 // Forward: one workgroup of 2 waves per 16x16 tile; wave w owns the 16x8
-// half w, two horizontally adjacent pixels per lane.  The tile's
-// depth-ordered list is consumed in chunks of 256 splat records gathered into
-// LDS (the next chunk is prefetched into registers while the current one is
-// processed) and read back as LDS broadcasts, each 32-byte record one record
-// ahead of its use.  The blend is branch-free per pixel.  A pixel stops after the first blended splat that
-// leaves T < t_min; a wave leaves the chunk once its 128 pixels have stopped,
-// and the workgroup leaves the list once all 256 have.
+// half w, two horizontally adjacent pixels per lane.  Each wave walks the
+// tile's depth-ordered list on its own, in chunks of 128 positions: the splat
+// records are gathered into registers one chunk ahead; at a chunk's start the
+// records that may reach one of the wave's live pixels are kept in LDS, and
+// read back as broadcasts, each 32-byte record one record ahead of its use.
+// The blend is branch-free per pixel.  A pixel stops after the first blended
+// splat that leaves T < t_min; a wave leaves the list once its 128 pixels have
+// stopped.
 //
 // Backward: one wave per (tile, segment) work item; each lane owns a 2x2
 // pixel quad so that the per-splat reduction is shared by 256 pixels.  A
@@ -101,13 +102,24 @@ __device__ __forceinline__ uint32_t pop_tile(uint32_t *queue) {
 }
 
 // ---------------------------------------------------------------------------
-// forward (COLOR = true) and recompute of the per-pixel state (COLOR = false)
+// forward
 // ---------------------------------------------------------------------------
 // Two waves per tile: wave w owns rows [8w, 8w + 8), each lane a horizontal
-// pixel pair.  Each chunk stages 2 records per thread.
+// pixel pair.  The waves walk the tile's list independently, kFwdChunk list
+// positions at a time.  Each lane gathers kFwdPerLane records of the next
+// chunk into registers while the current chunk is blended (the ids one chunk
+// further ahead, so the record loads never wait for them).  At the start of a
+// chunk the wave takes the bounding box of its live pixels from two ballots
+// and keeps, in LDS and in list order, only the records that may reach a pixel
+// centre of that box (splat_reaches_box, conservative).  A skipped record
+// cannot blend a live pixel, and a pixel that has stopped blends nothing more,
+// so the result is the walk over every record.  The kept records are read back
+// from LDS one record ahead; a record that no pixel of the wave blends skips
+// the blend after its exponents.
 constexpr int kFwdPx = 2;                 // pixels per lane
 constexpr int kFwdThreads = 128;
-constexpr int kFwdChunk = 2 * kFwdThreads;
+constexpr int kFwdChunk = 128;            // list positions per chunk
+constexpr int kFwdPerLane = kFwdChunk / 64;
 
 // A pixel is live while T >= t_min: T only decreases, by T alpha <= T, and
 // the pixel stops right after the blend that takes it below t_min, so the
@@ -116,12 +128,23 @@ constexpr int kFwdChunk = 2 * kFwdThreads;
 // With backward state requested (a.nlast non-null) the kernel also writes,
 // per pixel, its blend end (one past the list position of the last splat it
 // blended, 0 if none: no later splat changes the pixel) and the final (T, I);
-// at every list position s * kBwdSeg it reaches, the (T, I) checkpoint of
-// each pixel; and it appends the tile's backward work items (tile, s) for
+// at every list position s * kBwdSeg its wave reaches, the (T, I) checkpoint
+// of each of the wave's pixels (a pixel that blends past that position keeps
+// its wave walking, so every checkpoint the backward reads is written); and
+// it appends the tile's backward work items (tile, s) for
 // s < ceil(max blend end / kBwdSeg).  Within a chunk a pixel keeps the LDS
 // offset of its last blended record, which is already in a VGPR; the list
 // position is formed once per chunk.
 static_assert(kBwdSeg % kFwdChunk == 0, "backward segments are whole forward chunks");
+
+// The 8 bits of a 64-lane mask folded over its 8 groups of 8 lanes: bit c is
+// set if lane 8r + c is set for some r.
+__device__ __forceinline__ uint32_t fold_columns(uint64_t m) {
+    m |= m >> 32;
+    m |= m >> 16;
+    m |= m >> 8;
+    return (uint32_t)m & 0xFFu;
+}
 
 // COUNT: the kernel counts each pixel's blended splats, for the per-pixel
 // statistics and for the cap th.max_splats: a pixel also stops after blending
@@ -131,16 +154,20 @@ static_assert(kBwdSeg % kFwdChunk == 0, "backward segments are whole forward chu
 // kernel keeps no blend ends.
 template <bool PERSISTENT, bool COUNT, bool STATE>
 __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
-    constexpr int PX = kFwdPx, kThreads = kFwdThreads, kChunk = kFwdChunk;
-    // two padding records: the read-ahead reaches index kChunk + 1
-    __shared__ float4 s_r0[kChunk + 2], s_r1[kChunk + 2];
+    constexpr int PX = kFwdPx, kThreads = kFwdThreads, kChunk = kFwdChunk, kPer = kFwdPerLane;
+    // per wave: the kept records of the current chunk, two padding records
+    // for the read-ahead, and the chunk position of each kept record
+    __shared__ float4 s_r0[2][kChunk + 2], s_r1[2][kChunk + 2];
+    __shared__ uint32_t s_j[2][kChunk];
     __shared__ uint32_t s_next, s_max[2], s_work;
-    const float neg_lambda = in_vgpr(-a.th.lambda);
+    const float lambda = a.th.lambda;
+    const float neg_lambda = in_vgpr(-lambda);
     const float alpha_max = a.th.alpha_max;
     const float w_noclamp = in_vgpr(no_clamp_w(alpha_max));
     const float t_min = in_vgpr(a.th.t_min);
     const uint32_t cap = in_vgpr(a.th.max_splats > 0 ? a.th.max_splats : 0xFFFFFFFFu);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const char *b0 = reinterpret_cast<const char *>(s_r0[wave]), *b1 = reinterpret_cast<const char *>(s_r1[wave]);
     // block (or popped) index -> tile: through the longest-first order when there is one
     for (uint32_t idx = blockIdx.x; idx < a.total_tiles;) {
         const uint32_t tile = a.tile_order ? a.tile_order[idx] : (PERSISTENT ? idx : xcd_remap(idx, a.total_tiles));
@@ -152,6 +179,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
         const uint32_t start = a.tile_base[tile], end = a.tile_base[tile + 1];
         const int lx = 2 * (lane & 7), ly = 8 * wave + (lane >> 3);     // in-tile position of pixel 0
         const int x0 = (int)(tx * kTile) + lx, y0 = (int)(ty * kTile) + ly;
+        // pixel centres of the wave's first column and row
+        const float cx0 = (float)(tx * kTile) + 0.5f, cy0 = (float)(ty * kTile + 8 * wave) + 0.5f;
         float ux[PX], uy[PX], T[PX], I0[PX], I1[PX], I2[PX];
         uint32_t nlast[PX], nblend[PX];
         int last[PX];                     // LDS byte offset of the last blended record of this chunk, or -1
@@ -164,63 +193,99 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             I0[p] = I1[p] = I2[p] = 0.f;
             nlast[p] = 0; nblend[p] = 0; last[p] = -1;
         }
-        float4 n0[2], n1[2];
+        // records of the chunk at `base` (registers), ids of the chunk after it
+        float4 n0[kPer], n1[kPer];
+        uint32_t nid[kPer];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            n0[h] = make_float4(0.f, 0.f, 0.f, 0.f);
-            n1[h] = make_float4(-INFINITY, 0.f, 0.f, 0.f);
-            if (start + h * kThreads + tid < end) {
-                const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[start + h * kThreads + tid]);
-                n0[h] = src[0];
-                n1[h] = src[1];
+        for (int q = 0; q < kPer; ++q) {
+            const uint32_t k = start + q * 64 + lane;
+            n0[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            n1[q] = make_float4(-INFINITY, 0.f, 0.f, 0.f);
+            if (k < end) {
+                const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[k]);
+                n0[q] = src[0];
+                n1[q] = src[1];
             }
+            nid[q] = (k + kChunk < end) ? a.pairs[k + kChunk] : 0u;
         }
         for (uint32_t base = start; base < end; base += kChunk) {
+            bool live[PX];
+#pragma unroll
+            for (int p = 0; p < PX; ++p) live[p] = T[p] >= t_min && (!COUNT || nblend[p] < cap);
+            const uint64_t m0 = __ballot(live[0]), m1 = __ballot(live[1]);
+            if ((m0 | m1) == 0ull) break;
             if (STATE && a.ckpt && base > start && (base - start) % (uint32_t)kBwdSeg == 0) {
                 float4 *dst = a.ckpt + ckpt_slot(start, tile, (base - start) / (uint32_t)kBwdSeg) * kTilePix +
                               ly * kTile + lx;
 #pragma unroll
                 for (int p = 0; p < PX; ++p) dst[p] = make_float4(T[p], I0[p], I1[p], I2[p]);
             }
-            // the chunk flag: may any of its records reach the alpha_max clamp
-            // (records past the list end are never blended; a stale one only
-            // sets the flag needlessly)
+            // the live pixels' box: rows from the first and last live lane
+            // (row = lane / 8), columns from the folded masks of the even
+            // (pixel 0) and odd (pixel 1) columns
+            const uint64_t m = m0 | m1;
+            const int r_lo = __builtin_ctzll(m) >> 3, r_hi = (63 - __builtin_clzll(m)) >> 3;
+            const uint32_t c0 = fold_columns(m0), c1 = fold_columns(m1);
+            int x_lo = 2 * kTile, x_hi = -1;
+            if (c0) { x_lo = 2 * __builtin_ctz(c0); x_hi = 2 * (31 - __builtin_clz(c0)); }
+            if (c1) { x_lo = min(x_lo, 2 * __builtin_ctz(c1) + 1); x_hi = max(x_hi, 2 * (31 - __builtin_clz(c1)) + 1); }
+            const float bx0 = cx0 + (float)x_lo, bx1 = cx0 + (float)x_hi;
+            const float by0 = cy0 + (float)r_lo, by1 = cy0 + (float)r_hi;
+            // keep the records that may reach the box, in list order
+            int kept = 0;
             bool near = false;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                s_r0[h * kThreads + tid] = n0[h];
-                s_r1[h * kThreads + tid] = n1[h];
-                near = near || n1[h].x > w_noclamp;
-            }
-            const bool chunk_clamp = __syncthreads_or(near);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const uint32_t k = base + kChunk + h * kThreads + tid;
-                if (k < end) {
-                    const float4 *src = reinterpret_cast<const float4 *>(a.rec + a.pairs[k]);
-                    n0[h] = src[0];
-                    n1[h] = src[1];
+            for (int q = 0; q < kPer; ++q) {
+                const uint32_t j = (uint32_t)(q * 64 + lane);
+                const bool keep = base + j < end &&
+                                  splat_reaches_box(n0[q].x, n0[q].y, n0[q].z, n0[q].w, n1[q].x + lambda, bx0, bx1,
+                                                    by0, by1);
+                const uint64_t km = __ballot(keep);
+                if (keep) {
+                    const int pos = kept + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+                    s_r0[wave][pos] = n0[q];
+                    s_r1[wave][pos] = n1[q];
+                    if (STATE) s_j[wave][pos] = j;
+                    near = near || n1[q].x > w_noclamp;
                 }
+                kept += __builtin_popcountll(km);
             }
-            const int cnt = (int)min((uint32_t)kChunk, end - base);
-            for (int j0 = 0; j0 < cnt; j0 += 16) {
-                bool any_live = false;
+            // the chunk flag: may any kept record reach the alpha_max clamp
+            const bool chunk_clamp = __ballot(near) != 0ull;
+            // the next chunk's records, and the ids of the one after it
 #pragma unroll
-                for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!COUNT || nblend[p] < cap));
-                if (__ballot(any_live) == 0ull) break;
-                const int jn = min(j0 + 16, cnt);
-                // Record j sits at byte 16 j of s_r0 and of s_r1; the offset is kept
-                // in a VGPR (see in_vgpr) and addresses both LDS reads.  The loop is
-                // unrolled by two over the register sets A and B: the next record is
-                // read while the current one is processed, so the LDS latency
-                // overlaps the arithmetic.  The whole record is read ahead (a later
-                // read of the colour would have to wait for the read-ahead as well).
-                const char *b0 = reinterpret_cast<const char *>(s_r0), *b1 = reinterpret_cast<const char *>(s_r1);
+            for (int q = 0; q < kPer; ++q) {
+                const uint32_t k = base + kChunk + q * 64 + lane;
+                if (k < end) {
+                    const float4 *src = reinterpret_cast<const float4 *>(a.rec + nid[q]);
+                    n0[q] = src[0];
+                    n1[q] = src[1];
+                }
+                if (k + kChunk < end) nid[q] = a.pairs[k + kChunk];
+            }
+            // the kept records are written before any lane of the wave reads them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int j0 = 0; j0 < kept; j0 += 16) {
+                if (j0 > 0) {
+                    bool any_live = false;
+#pragma unroll
+                    for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!COUNT || nblend[p] < cap));
+                    if (__ballot(any_live) == 0ull) break;
+                }
+                const int jn = min(j0 + 16, kept);
+                // Kept record j sits at byte 16 j of the wave's s_r0 and s_r1; the
+                // offset is kept in a VGPR (see in_vgpr) and addresses both LDS
+                // reads.  The loop is unrolled by two over the register sets A and
+                // B: the next record is read while the current one is blended.
                 auto blend = [&](const float4 &r0, const float4 &r1, int ro) {
                     SplatRec s;
                     s.px = r0.x; s.py = r0.y; s.a = r0.z; s.b = r0.w;
                     s.w = r1.x;
-                    float e[PX];
+                    s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
+                    float alpha[PX], e[PX];
                     bool hit[PX];
                     bool any = false;
 #pragma unroll
@@ -231,10 +296,6 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                         any = any || hit[p];
                     }
                     if (__ballot(any) == 0ull) return;
-                    s.cr = r1.y; s.cg = r1.z; s.cb = r1.w;
-                    // branch-free over the lane's pixels: alpha = 0 leaves a pixel
-                    // that does not blend this splat exactly unchanged
-                    float alpha[PX];
 #pragma unroll
                     for (int p = 0; p < PX; ++p) alpha[p] = hit[p] ? __builtin_amdgcn_exp2f(e[p]) : 0.f;
                     if (__builtin_expect(chunk_clamp, 0)) {
@@ -274,13 +335,13 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
 #pragma unroll
             for (int p = 0; p < PX; ++p)
                 if (STATE && last[p] >= 0) {
-                    nlast[p] = base - start + (uint32_t)last[p] / 16u + 1u;
+                    nlast[p] = base - start + s_j[wave][last[p] / 16] + 1u;
                     last[p] = -1;
                 }
-            bool any_live = false;
-#pragma unroll
-            for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!COUNT || nblend[p] < cap));
-            if (__syncthreads_count(any_live) == 0) break;
+            // this chunk's kept records are read before the next chunk's are written
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         uint32_t mymax = 0;
 #pragma unroll

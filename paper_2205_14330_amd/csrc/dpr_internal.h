@@ -135,17 +135,35 @@ __device__ __forceinline__ float splat_exponent(const SplatRec &s, float ux, flo
 // contraction is off and every operation rounds once.  (Left to the compiler,
 // the two kernels fused different products into FMAs, and about one decision
 // in 5e7 differed.)
+__device__ __forceinline__ float box_form(float px, float py, float a, float b, float x0, float x1, float y0,
+                                          float y1) {
+#pragma clang fp contract(off)
+    // the box's point nearest to the splat centre: px clamped to [x0, x1]
+    // (med3 returns that same value, in one instruction)
+    const float cx = __builtin_amdgcn_fmed3f(px, x0, x1);
+    const float cy = __builtin_amdgcn_fmed3f(py, y0, y1);
+    const float dx = cx - px, dy = cy - py;
+    const float qx = (a * dx) * dx, qy = (b * dy) * dy;
+    return qx + qy;
+}
+
 __device__ __forceinline__ bool splat_touches_tile(float px, float py, float a, float b, float thr, uint32_t tx,
                                                    uint32_t ty) {
 #pragma clang fp contract(off)
     const float x0 = (float)(tx * kTile) + 0.5f, y0 = (float)(ty * kTile) + 0.5f;
-    // the tile's pixel centre nearest to the splat centre: px clamped to
-    // [x0, x0 + 15] (med3 returns that same value, in one instruction)
-    const float cx = __builtin_amdgcn_fmed3f(px, x0, x0 + (float)(kTile - 1));
-    const float cy = __builtin_amdgcn_fmed3f(py, y0, y0 + (float)(kTile - 1));
-    const float dx = cx - px, dy = cy - py;
-    const float qx = (a * dx) * dx, qy = (b * dy) * dy;
-    return qx + qy <= thr * (1.0f + 1.0f / 1024.0f) + 1.0e-6f;
+    const float q = box_form(px, py, a, b, x0, x0 + (float)(kTile - 1), y0, y0 + (float)(kTile - 1));
+    return q <= thr * (1.0f + 1.0f / 1024.0f) + 1.0e-6f;
+}
+
+// The same lower bound over the pixel centres [x0, x1] x [y0, y1], with a
+// margin that covers the rounding of the per-pixel exponent of splat_exponent
+// (a few ulps of |w| + lambda + q, below 1e-5 for |w| < 80): if the test fails,
+// no pixel centre of the box passes e >= -lambda.  The forward uses it to skip
+// records that cannot reach any of a wave's live pixels.
+__device__ __forceinline__ bool splat_reaches_box(float px, float py, float a, float b, float thr, float x0, float x1,
+                                                  float y0, float y1) {
+#pragma clang fp contract(off)
+    return box_form(px, py, a, b, x0, x1, y0, y1) <= thr * (1.0f + 1.0f / 1024.0f) + 1.0e-5f;
 }
 
 }  // namespace dpr
