@@ -64,7 +64,7 @@ struct Sizes {
 
 struct PlanLayout {
     Region views, scenes, u32tab, rec, keys, vals, keys_alt, vals_alt, rect, hist, part, cnt, segs, tile_total,
-        tile_base, tile_order, bucket_cnt;
+        tile_base, tile_order, bucket_cnt, block_sum;
     uint64_t total = 0;
 };
 
@@ -91,6 +91,7 @@ PlanLayout plan_layout(const Sizes &s) {
     p.tile_base = L.add(4 * (s.tiles + 1));
     p.tile_order = L.add(4 * s.tiles);
     p.bucket_cnt = L.add(4ull * kOrderBuckets * order_count_blocks(s.tiles));
+    p.block_sum = L.add(8ull * order_count_blocks(s.tiles));
     p.total = L.total;
     return p;
 }
@@ -157,7 +158,7 @@ int check_inputs(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *view
         s.cnt += tx * ty * nch;
         s.segs += tx * ty * nseg;
         s.max_view_segs = std::max(s.max_view_segs, nseg);
-        s.sort_blocks += (n + kSortTile - 1) / kSortTile;
+        s.sort_blocks += (n + kDepthSortTile - 1) / kDepthSortTile;
     }
     if (s.items >= 0x7FFFFFFFull) return fail(DPR_ERR_UNSUPPORTED, "total view-points must be < 2^31");
     if (s.tiles >= 0xFFFFFFFFull || s.cnt >= 0xFFFFFFFFull || s.chunks >= 0xFFFFFFFFull)
@@ -189,6 +190,7 @@ struct dpr_plan {
     std::vector<ViewDesc> vdesc;
     std::vector<SceneDesc> sdesc;
     std::vector<uint32_t> u32tab;
+    std::vector<uint32_t> up_img;   // the upload image of views, scenes and u32tab
     uint8_t *pws = nullptr;
     uint64_t pairs = 0;
     int forward_done = 0;
@@ -558,7 +560,7 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
             d.chunk_off = (uint32_t)chunk;
             d.nchunks = (uint32_t)(((uint64_t)sc.n + kChunkItems - 1) / kChunkItems);
             d.sort_block_off = (uint32_t)sblk;
-            d.nsort_blocks = (uint32_t)(((uint64_t)sc.n + kSortTile - 1) / kSortTile);
+            d.nsort_blocks = (uint32_t)(((uint64_t)sc.n + kDepthSortTile - 1) / kDepthSortTile);
             d.hist_off = hist;
             d.cnt_off = cnt;
             d.seg_off = seg;
@@ -607,9 +609,14 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
 
     {
         StageScope sc_(p, DPR_STAGE_UPLOAD, st);
-        STAGE_TRY(upload_async(w + lay.views.off, p->vdesc.data(), sizeof(ViewDesc) * V, st));
-        STAGE_TRY(upload_async(w + lay.scenes.off, p->sdesc.data(), sizeof(SceneDesc) * S, st));
-        STAGE_TRY(upload_async(w + lay.u32tab.off, p->u32tab.data(), 4 * p->u32tab.size(), st));
+        // the three tables are the first regions of the layout: one image of them
+        const uint64_t img = lay.u32tab.off + 4 * p->u32tab.size() - lay.views.off;
+        p->up_img.assign((size_t)(img / 4), 0u);
+        uint8_t *h = reinterpret_cast<uint8_t *>(p->up_img.data());
+        memcpy(h + (lay.views.off - lay.views.off), p->vdesc.data(), sizeof(ViewDesc) * V);
+        memcpy(h + (lay.scenes.off - lay.views.off), p->sdesc.data(), sizeof(SceneDesc) * S);
+        memcpy(h + (lay.u32tab.off - lay.views.off), p->u32tab.data(), 4 * p->u32tab.size());
+        STAGE_TRY(upload_async(w + lay.views.off, h, img, st));
     }
     {
         StageScope sc_(p, DPR_STAGE_PROJECT, st);
@@ -627,10 +634,9 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
     {
         StageScope sc_(p, DPR_STAGE_TILE_SCAN, st);
         uint32_t *bucket_cnt = reinterpret_cast<uint32_t *>(w + lay.bucket_cnt.off);
-        STAGE_TRY(launch_tile_colscan(tb, cnt, segs, tile_total, bucket_cnt, st));
-        STAGE_TRY(launch_scan(tile_total, tile_base, s.tiles, part, total64, st));
-        STAGE_TRY(launch_tile_order(tile_total, (uint32_t)s.tiles, bucket_cnt,
-                                    reinterpret_cast<uint32_t *>(w + lay.tile_order.off), st));
+        uint64_t *block_sum = reinterpret_cast<uint64_t *>(w + lay.block_sum.off);
+        STAGE_TRY(launch_tile_colscan(tb, cnt, segs, tile_total, bucket_cnt, block_sum, tile_base,
+                                      reinterpret_cast<uint32_t *>(w + lay.tile_order.off), total64, st));
     }
     STAGE_TRY(read_count(total64, &p->pairs, st));
     if (p->pairs >= 0xFFFFFFFFull)
@@ -670,7 +676,8 @@ int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
                                  reinterpret_cast<const SplatRec *>(p->pws + lay.rec.off), p->th.lambda,
                                  reinterpret_cast<const uint32_t *>(p->pws + lay.cnt.off),
                                  reinterpret_cast<const uint32_t *>(p->pws + lay.tile_base.off),
-                                 reinterpret_cast<uint32_t *>(w + f.pairs.off), st));
+                                 reinterpret_cast<uint32_t *>(w + f.pairs.off),
+                                 reinterpret_cast<uint32_t *>(w + f.counters.off), st));
     }
     CompositeArgs a = composite_args(p, ws);
     a.write_views = 1;
@@ -679,8 +686,7 @@ int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
     a.counters = reinterpret_cast<uint32_t *>(w + f.counters.off);
     const bool persistent = (p->params.flags & DPR_FLAG_PERSISTENT) != 0;
     {
-        HIP_TRY(launch_fill_u32(a.counters, 0u, 4, st));
-        StageScope sc_(p, DPR_STAGE_COMPOSITE_FWD, st);
+        StageScope sc_(p, DPR_STAGE_COMPOSITE_FWD, st);   // the counters were cleared by the emission
         HIP_TRY(launch_composite_fwd(a, persistent, st));
     }
     p->forward_done = 1;
@@ -729,8 +735,18 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
         p->sdesc_bwd[s].dsh = dL_dsh ? dL_dsh[s] : nullptr;
         p->sdesc_bwd[s].dopacity = dL_dopacity ? dL_dopacity[s] : nullptr;
     }
-    HIP_TRY(upload_async(bw + bl.tabs.off, p->bwd_tab.data(), 8 * p->bwd_tab.size(), st));
-    HIP_TRY(upload_async(bw + bl.sgrad.off, p->sdesc_bwd.data(), sizeof(SceneDesc) * S, st));
+    // pointer tables and gradient scene descriptors (adjacent regions: one
+    // image), with the counters and the gradient accumulators cleared in the
+    // same launch
+    {
+        const uint64_t img = bl.sgrad.off + sizeof(SceneDesc) * S - bl.tabs.off;
+        p->up_img.assign((size_t)(img / 4), 0u);
+        uint8_t *h = reinterpret_cast<uint8_t *>(p->up_img.data());
+        memcpy(h, p->bwd_tab.data(), 8 * p->bwd_tab.size());
+        memcpy(h + (bl.sgrad.off - bl.tabs.off), p->sdesc_bwd.data(), sizeof(SceneDesc) * S);
+        HIP_TRY(upload_zero_async(bw + bl.tabs.off, h, img, reinterpret_cast<uint32_t *>(bw + bl.counters.off), 4,
+                                  reinterpret_cast<uint32_t *>(bw + bl.grad.off), 8ull * p->sz.items, st));
+    }
 
     CompositeArgs a = composite_args(p, ws);
     const bool persistent = (p->params.flags & DPR_FLAG_PERSISTENT) != 0;
@@ -739,7 +755,6 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
     b.dimage = reinterpret_cast<const float *const *>(bw + bl.tabs.off);
     b.dtrans = dL_dtrans ? reinterpret_cast<const float *const *>(bw + bl.tabs.off + 8ull * V) : nullptr;
     b.grad = reinterpret_cast<float *>(bw + bl.grad.off);
-    HIP_TRY(launch_fill_u32(counters, 0u, 4, st));
     if (recompute) {
         // the forward again, writing only the backward state (to the backward workspace)
         set_bwd_state(a, bw, bl.st);
@@ -763,7 +778,6 @@ int dpr_render_backward(dpr_plan *p, const void *ws, size_t ws_bytes, const floa
     a.counters = nullptr;
     b.c = a;
     {
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(b.grad), 0u, 8ull * p->sz.items, st));
         StageScope sc_(p, DPR_STAGE_COMPOSITE_BWD, st);
         HIP_TRY(launch_composite_bwd(b, st));
     }

@@ -115,13 +115,16 @@ __global__ __launch_bounds__(kColThreads) void k_col_segsum(Tables tb, const uin
     segs[c.seg_off + (uint64_t)s * c.ntiles + c.t] = sum;
 }
 
-// Also counts the block's tiles per order bucket (bucket_cnt[block][kOrderBuckets]).
+// Also counts the block's tiles per order bucket (bucket_cnt[block][kOrderBuckets])
+// and sums its tiles' totals (block_sum[block]).
 __global__ __launch_bounds__(kColThreads) void k_col_segscan(Tables tb, uint32_t *segs, uint32_t *tile_total,
-                                                             uint32_t *bucket_cnt) {
+                                                             uint32_t *bucket_cnt, uint64_t *block_sum) {
     __shared__ uint32_t s_b[kOrderBuckets];
+    __shared__ uint64_t s_w[kColThreads / 64];
     if (threadIdx.x < (uint32_t)kOrderBuckets) s_b[threadIdx.x] = 0;
     __syncthreads();
     const ColCtx c = col_ctx(tb);
+    uint64_t mine = 0;
     if (c.ok) {
         uint32_t run = 0;
         for (uint32_t s = 0; s < c.nseg; ++s) {
@@ -132,21 +135,67 @@ __global__ __launch_bounds__(kColThreads) void k_col_segscan(Tables tb, uint32_t
         }
         tile_total[c.gtile] = run;
         atomicAdd(&s_b[order_bucket(run)], 1u);
+        mine = run;
     }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mine += __shfl_xor(mine, d, 64);
+    if ((threadIdx.x & 63u) == 0) s_w[threadIdx.x >> 6] = mine;
     __syncthreads();
     if (threadIdx.x < (uint32_t)kOrderBuckets)
         bucket_cnt[(uint64_t)blockIdx.x * kOrderBuckets + threadIdx.x] = s_b[threadIdx.x];
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kColThreads / 64; ++w) t += s_w[w];
+        block_sum[blockIdx.x] = t;
+    }
 }
 
 uint64_t order_count_blocks(uint64_t tiles) { return (tiles + kColThreads - 1) / kColThreads; }
 
-// Same blocks of kColThreads tiles as k_col_segscan.  Bucket b starts after
-// every tile of the longer buckets and after bucket b's tiles of the earlier
-// blocks; inside a block the tiles of a bucket take its slots by LDS atomics.
-__global__ __launch_bounds__(kColThreads) void k_tile_order(const uint32_t *len, uint32_t n, const uint32_t *bucket_cnt,
-                                                            uint32_t nblk, uint32_t *order) {
+// The column down-sweep (grid (tile blocks, segments): segment s covers chunks
+// [s kSegChunks, (s + 1) kSegChunks) of every tile column), and in the blocks
+// of segment 0 also, over the same blocks of kColThreads tiles as
+// k_col_segscan:
+//   tile_base: the exclusive scan of the tile totals (the block's base is the
+//              sum of the earlier blocks' sums; the last block writes the
+//              total after the last tile and the 64-bit pair count);
+//   order    : the tiles longest list first.  Bucket b starts after every tile
+//              of the longer buckets and after bucket b's tiles of the earlier
+//              blocks; inside a block the tiles of a bucket take its slots by
+//              LDS atomics.
+__global__ __launch_bounds__(kColThreads) void k_col_finish(Tables tb, uint32_t *cnt, const uint32_t *segs,
+                                                            const uint32_t *tile_total, const uint64_t *block_sum,
+                                                            const uint32_t *bucket_cnt, uint32_t nblk,
+                                                            uint32_t *tile_base, uint32_t *order,
+                                                            uint64_t *total64) {
+    {
+        const ColCtx c = col_ctx(tb);
+        const uint32_t s = blockIdx.y;
+        if (c.ok && s < c.nseg) {
+            const uint32_t c0 = s * kSegChunks, c1 = min(c0 + (uint32_t)kSegChunks, c.nchunks);
+            uint32_t run = segs[c.seg_off + (uint64_t)s * c.ntiles + c.t];
+            for (uint32_t k = c0; k < c1; ++k) {
+                uint32_t *p = cnt + c.cnt_off + (uint64_t)k * c.ntiles + c.t;
+                const uint32_t v = *p;
+                *p = run;
+                run += v;
+            }
+        }
+    }
+    if (blockIdx.y != 0) return;
+    __shared__ uint64_t s_w[kColThreads / 64];
     __shared__ uint32_t s_tot[kOrderBuckets], s_before[kOrderBuckets], s_base[kOrderBuckets];
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t n = tb.total_tiles;
+    const uint32_t t = blockIdx.x * kColThreads + tid;
+    const uint32_t len = t < n ? tile_total[t] : 0u;
+    // block base: the earlier blocks' sums
+    uint64_t pre = 0;
+    for (uint32_t b = tid; b < blockIdx.x; b += kColThreads) pre += block_sum[b];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) pre += __shfl_xor(pre, d, 64);
+    if (lane == 0) s_w[wave] = pre;
     if (tid < (uint32_t)kOrderBuckets) {
         uint32_t tot = 0, before = 0;
 #pragma unroll 8
@@ -159,6 +208,9 @@ __global__ __launch_bounds__(kColThreads) void k_tile_order(const uint32_t *len,
         s_before[tid] = before;
     }
     __syncthreads();
+    uint64_t base = 0;
+#pragma unroll
+    for (int w = 0; w < kColThreads / 64; ++w) base += s_w[w];
     if (tid == 0) {
         uint32_t run = 0;
         for (int b = 0; b < kOrderBuckets; ++b) {
@@ -166,41 +218,48 @@ __global__ __launch_bounds__(kColThreads) void k_tile_order(const uint32_t *len,
             run += s_tot[b];
         }
     }
+    __syncthreads();                          // every thread has read s_w
+    // exclusive scan of the block's lengths
+    uint64_t incl = len;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += y;
+    }
+    if (lane == 63) s_w[wave] = incl;
     __syncthreads();
-    const uint32_t t = blockIdx.x * kColThreads + tid;
-    if (t < n) order[atomicAdd(&s_base[order_bucket(len[t])], 1u)] = t;
-}
-
-hipError_t launch_tile_order(const uint32_t *len, uint32_t n, const uint32_t *bucket_cnt, uint32_t *order,
-                             hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    const uint32_t nblk = (uint32_t)order_count_blocks(n);
-    hipLaunchKernelGGL(k_tile_order, dim3(nblk), dim3(kColThreads), 0, st, len, n, bucket_cnt, nblk, order);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(kColThreads) void k_col_down(Tables tb, uint32_t *cnt, const uint32_t *segs) {
-    const ColCtx c = col_ctx(tb);
-    const uint32_t s = blockIdx.y;
-    if (!c.ok || s >= c.nseg) return;
-    const uint32_t c0 = s * kSegChunks, c1 = min(c0 + (uint32_t)kSegChunks, c.nchunks);
-    uint32_t run = segs[c.seg_off + (uint64_t)s * c.ntiles + c.t];
-    for (uint32_t k = c0; k < c1; ++k) {
-        uint32_t *p = cnt + c.cnt_off + (uint64_t)k * c.ntiles + c.t;
-        const uint32_t v = *p;
-        *p = run;
-        run += v;
+    uint64_t wbase = 0, btot = 0;
+#pragma unroll
+    for (int w = 0; w < kColThreads / 64; ++w) {
+        const uint64_t v = s_w[w];
+        wbase += (uint32_t)w < wave ? v : 0u;
+        btot += v;
+    }
+    if (t < n) {
+        tile_base[t] = (uint32_t)(base + wbase + incl - len);
+        order[atomicAdd(&s_base[order_bucket(len)], 1u)] = t;
+    }
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) {
+        tile_base[n] = (uint32_t)(base + btot);
+        *total64 = base + btot;
     }
 }
 
 hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, uint32_t *tile_total,
-                               uint32_t *bucket_cnt, hipStream_t st) {
-    if (tb.total_tiles == 0) return hipSuccess;
+                               uint32_t *bucket_cnt, uint64_t *block_sum, uint32_t *tile_base, uint32_t *order,
+                               uint64_t *total64, hipStream_t st) {
+    if (tb.total_tiles == 0) {
+        hipError_t e = launch_fill_u32(tile_base, 0u, 1, st);
+        if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(total64), 0u, 2, st);
+        return e;
+    }
     const uint32_t bx = (tb.total_tiles + kColThreads - 1) / kColThreads;
     const uint32_t ns = tb.max_view_segs > 0 ? tb.max_view_segs : 1;
     hipLaunchKernelGGL(k_col_segsum, dim3(bx, ns), dim3(kColThreads), 0, st, tb, cnt, segs);
-    hipLaunchKernelGGL(k_col_segscan, dim3(bx), dim3(kColThreads), 0, st, tb, segs, tile_total, bucket_cnt);
-    hipLaunchKernelGGL(k_col_down, dim3(bx, ns), dim3(kColThreads), 0, st, tb, cnt, segs);
+    hipLaunchKernelGGL(k_col_segscan, dim3(bx), dim3(kColThreads), 0, st, tb, segs, tile_total, bucket_cnt,
+                       block_sum);
+    hipLaunchKernelGGL(k_col_finish, dim3(bx, ns), dim3(kColThreads), 0, st, tb, cnt, segs, tile_total, block_sum,
+                       bucket_cnt, bx, tile_base, order, total64);
     return hipGetLastError();
 }
 
@@ -231,7 +290,8 @@ static_assert(kChunkItems % 32 == 0 && kEmitWords <= 32, "whole bitmap words, on
 
 __global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uint32_t *order, const uint2 *rect,
                                                              const SplatRec *rec, float lambda, const uint32_t *pre,
-                                                             const uint32_t *tile_base, uint32_t *pairs) {
+                                                             const uint32_t *tile_base, uint32_t *pairs,
+                                                             uint32_t *zero4) {
     // word w of band tile b at s_bits[w * kEmitBand + b]: the write phase's
     // lanes (consecutive tiles) read consecutive words
     __shared__ uint32_t s_bits[kEmitWords * kEmitBand];
@@ -241,6 +301,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uin
     const ChunkInfo ci = chunk_info(tb);
     const uint32_t tid = threadIdx.x;
     const uint32_t n = ci.end - ci.beg;
+    if (blockIdx.x == 0 && tid < 4u) zero4[tid] = 0u;
     for (uint32_t i = tid; i < n; i += kEmitThreads) {
         const uint32_t g = order[ci.beg + i];
         s_g[i] = g;
@@ -332,10 +393,10 @@ hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *
 
 hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
                             const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
-                            const uint32_t *tile_base, uint32_t *pairs, hipStream_t st) {
-    if (chunks == 0) return hipSuccess;
+                            const uint32_t *tile_base, uint32_t *pairs, uint32_t *zero4, hipStream_t st) {
+    if (chunks == 0) return launch_fill_u32(zero4, 0u, 4, st);
     hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitThreads), 0, st, tb, order, rect, rec, lambda, pre,
-                       tile_base, pairs);
+                       tile_base, pairs, zero4);
     return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@
 // the per-item gradient records with one 64-lane float atomic.
 #include "dpr_internal.h"
 
+#include <cstring>
+
 namespace dpr {
 
 constexpr int kCompLanes = 64;
@@ -727,6 +729,50 @@ hipError_t upload_async(void *dst, const void *src, size_t bytes, hipStream_t st
         n -= c.nwords;
     }
     return hipSuccess;
+}
+
+// The same for a table of at most kUploadZeroWords words, in the one launch
+// that also clears up to two word ranges (grid-stride).
+constexpr int kUploadZeroWords = 896;
+struct UploadZeroArgs {
+    uint32_t *dst;
+    uint32_t *z0, *z1;
+    uint64_t n0, n1;
+    uint32_t nwords;
+    uint32_t words[kUploadZeroWords];
+};
+
+__global__ void k_upload_zero(UploadZeroArgs a) {
+    if (blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < a.nwords; i += blockDim.x) a.dst[i] = a.words[i];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t k = i0; k < a.n0; k += stride) a.z0[k] = 0u;
+    for (uint64_t k = i0; k < a.n1; k += stride) a.z1[k] = 0u;
+}
+
+hipError_t upload_zero_async(void *dst, const void *src, size_t bytes, uint32_t *z0, uint64_t n0, uint32_t *z1,
+                             uint64_t n1, hipStream_t st) {
+    if (bytes % 4 != 0) return hipErrorInvalidValue;
+    if (bytes / 4 > (size_t)kUploadZeroWords) {
+        hipError_t e = upload_async(dst, src, bytes, st);
+        if (e == hipSuccess && n0) e = launch_fill_u32(z0, 0u, n0, st);
+        if (e == hipSuccess && n1) e = launch_fill_u32(z1, 0u, n1, st);
+        return e;
+    }
+    UploadZeroArgs a;
+    a.dst = static_cast<uint32_t *>(dst);
+    a.z0 = z0;
+    a.z1 = z1;
+    a.n0 = z0 ? n0 : 0;
+    a.n1 = z1 ? n1 : 0;
+    a.nwords = (uint32_t)(bytes / 4);
+    memcpy(a.words, src, bytes);
+    const uint64_t big = a.n0 > a.n1 ? a.n0 : a.n1;
+    const uint64_t blocks = (big + 4ull * 256 - 1) / (4ull * 256);
+    const uint32_t grid = (uint32_t)(blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks));
+    hipLaunchKernelGGL(k_upload_zero, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t read_count(const uint64_t *dev, uint64_t *out, hipStream_t st) {

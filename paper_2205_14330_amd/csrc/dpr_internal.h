@@ -17,6 +17,8 @@ constexpr int kBwdSeg = 256;              // list positions per backward work it
 constexpr int kSortThreads = 256;
 constexpr int kSortItemsPerThread = 8;
 constexpr int kSortTile = kSortThreads * kSortItemsPerThread;   // 2048 keys per sort block
+constexpr int kDepthSortThreads = 1024;
+constexpr int kDepthSortTile = 8 * kDepthSortThreads;              // 8192 keys per depth-sort block
 constexpr int kScanThreads = 256;
 constexpr int kScanItemsPerThread = 8;
 constexpr int kScanTile = kScanThreads * kScanItemsPerThread;   // 2048 elements per scan block
@@ -204,14 +206,18 @@ uint64_t scan_partials(uint64_t n);
 // Binning.  cnt is chunk-major per view: cnt[cnt_off + c * tiles + t].
 hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *order,
                              const uint2 *rect, const SplatRec *rec, float lambda, uint32_t *cnt, hipStream_t st);
-// In place: cnt[c][t] -> sum of cnt[c'][t] over c' < c; tile_total[tile] = column sum.
-// segs: scratch of sum over views of tiles * segments u32.
+// In place: cnt[c][t] -> sum of cnt[c'][t] over c' < c; tile_total[tile] = column sum;
+// tile_base = exclusive scan of tile_total (tiles + 1 entries, the last = pair
+// count mod 2^32, the exact count in *total64); order = the tiles longest list
+// first.  segs: scratch of sum over views of tiles * segments u32; bucket_cnt
+// and block_sum: kOrderBuckets u32 and one u64 per order_count_blocks(tiles).
 hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, uint32_t *tile_total,
-                               uint32_t *bucket_cnt, hipStream_t st);
-// tile_base = exclusive scan of tile_total (tiles + 1 entries).
+                               uint32_t *bucket_cnt, uint64_t *block_sum, uint32_t *tile_base, uint32_t *order,
+                               uint64_t *total64, hipStream_t st);
+// Also clears the 4 words at zero4 (the compositing counters that follow it).
 hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
                             const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
-                            const uint32_t *tile_base, uint32_t *pairs, hipStream_t st);
+                            const uint32_t *tile_base, uint32_t *pairs, uint32_t *zero4, hipStream_t st);
 
 // Backward state of a tile list at the list positions s * kBwdSeg (s >= 1):
 // per pixel (T, I) after the first s * kBwdSeg splats, 256 float4 per slot in
@@ -248,15 +254,12 @@ hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStre
 // time grows with the list positions it visits, and the kernel's end is set by
 // the last long tile to start.  The length ranks that work only roughly (early
 // termination), so the order is by bucket: the bit length of the length,
-// longest first.  k_col_segscan counts each block's tiles per bucket; the
-// order kernel places them (the order of tiles within a bucket changes no
+// longest first.  k_col_segscan counts each block's tiles per bucket;
+// k_col_finish places them (the order of tiles within a bucket changes no
 // result).
 constexpr int kOrderBuckets = 33;            // bit lengths 32 .. 0
 __device__ __forceinline__ uint32_t order_bucket(uint32_t len) { return len ? (uint32_t)__clz(len) : 32u; }
 uint64_t order_count_blocks(uint64_t tiles);
-// order[] = the n tiles, longest list first, from the per-block bucket counts of k_col_segscan
-hipError_t launch_tile_order(const uint32_t *len, uint32_t n, const uint32_t *bucket_cnt, uint32_t *order,
-                             hipStream_t st);
 
 struct BackwardArgs {
     CompositeArgs c;
@@ -373,6 +376,11 @@ uint32_t loss_blocks(int32_t width, int32_t height);
 hipError_t launch_loss(const LossImage *img, int n, float lambda, float *partial, double *loss, hipStream_t st);
 // Stream-ordered copy of a small host table (bytes % 4 == 0) through kernel arguments.
 hipError_t upload_async(void *dst, const void *src, size_t bytes, hipStream_t st);
+// One launch: a table of bytes % 4 == 0 copied as upload_async does, and the
+// word ranges z0[0..n0), z1[0..n1) cleared (null ranges allowed).  Tables
+// above kUploadZeroWords words take separate launches.
+hipError_t upload_zero_async(void *dst, const void *src, size_t bytes, uint32_t *z0, uint64_t n0, uint32_t *z1,
+                             uint64_t n1, hipStream_t st);
 // Reads one 64-bit count that work queued on `st` produces: copies it into a
 // pinned host word of the calling thread (allocated on the thread's first
 // call and kept until the process ends), waits for the stream, stores it in *out.

@@ -14,7 +14,7 @@
 // its squared difference and its differences to the right and lower
 // neighbours; a block sums them in FP32, and a second kernel adds each
 // image's block sums in FP64 in a fixed order, so the result does not depend
-// on scheduling.  Up to kLossBatch images travel in the kernel arguments.
+// on scheduling.  With lambda = 0 (the plain L2 loss) no neighbour is read.  Up to kLossBatch images travel in the kernel arguments.
 #include "dpr_internal.h"
 
 namespace dpr {
@@ -62,18 +62,21 @@ __global__ __launch_bounds__(kLossThreads) void k_loss(LossBatch bt) {
         if (vec) {
             r = ld4(R + i);
             t = ld4(T + i);
-            lf = i >= 4 ? ld4(R + i - 4) : make_float4(0.f, 0.f, 0.f, 0.f);
-            if (i + 8 <= nf) {
-                rt = ld4(R + i + 4);
-            } else {                                  // the image ends inside the next group
-                rt.x = i + 4 < nf ? R[i + 4] : 0.f;
-                rt.y = i + 5 < nf ? R[i + 5] : 0.f;
-                rt.z = i + 6 < nf ? R[i + 6] : 0.f;
-                rt.w = 0.f;                           // i + 7: only e + 3 <= i + 6 is ever read
-            }
-            if (vrow) {
-                up = i >= row ? ld4(R + i - row) : make_float4(0.f, 0.f, 0.f, 0.f);
-                dn = i + row + 4 <= nf ? ld4(R + i + row) : make_float4(0.f, 0.f, 0.f, 0.f);
+            lf = rt = up = dn = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (lambda != 0.f) {                      // the neighbours enter only the TV term
+                if (i >= 4) lf = ld4(R + i - 4);
+                if (i + 8 <= nf) {
+                    rt = ld4(R + i + 4);
+                } else {                              // the image ends inside the next group
+                    rt.x = i + 4 < nf ? R[i + 4] : 0.f;
+                    rt.y = i + 5 < nf ? R[i + 5] : 0.f;
+                    rt.z = i + 6 < nf ? R[i + 6] : 0.f;
+                    rt.w = 0.f;                       // i + 7: only e + 3 <= i + 6 is ever read
+                }
+                if (vrow) {
+                    if (i >= row) up = ld4(R + i - row);
+                    if (i + row + 4 <= nf) dn = ld4(R + i + row);
+                }
             }
         }
         float g[4];
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(kLossThreads) void k_loss(LossBatch bt) {
                 // e + 3: float k + 3 of the group: k == 0 in r, else float k - 1 of rt
                 Rr = k == 0 ? at(r, 3) : at(rt, k - 1);
                 if (vrow) { Ru = at(up, k); Rd = at(dn, k); }
-                else {
+                else if (lambda != 0.f) {
                     if (y > 0) Ru = R[e - row];
                     if (y + 1 < H) Rd = R[e + row];
                 }
@@ -137,16 +140,22 @@ __global__ __launch_bounds__(kLossThreads) void k_loss(LossBatch bt) {
     if (threadIdx.x == 0) bt.partial[blockIdx.x] = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
 }
 
-// One wave per image: lane l adds block sums l, l + 64, ... in FP64, then a
-// fixed butterfly combines the lanes.
-__global__ __launch_bounds__(64) void k_loss_sum(LossBatch bt) {
+// One block of kLossSumThreads per image: thread l adds block sums l,
+// l + kLossSumThreads, ... in FP64, then a fixed butterfly in each wave and a
+// fixed order across the waves combine them.
+constexpr int kLossSumThreads = 256;
+
+__global__ __launch_bounds__(kLossSumThreads) void k_loss_sum(LossBatch bt) {
+    __shared__ double s_w[kLossSumThreads / 64];
     const int v = blockIdx.x;
     const uint32_t b0 = bt.block_start[v], b1 = bt.block_start[v + 1];
     double s = 0.0;
-    for (uint32_t b = b0 + threadIdx.x; b < b1; b += 64) s += (double)bt.partial[b];
+    for (uint32_t b = b0 + threadIdx.x; b < b1; b += kLossSumThreads) s += (double)bt.partial[b];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-    if (threadIdx.x == 0) bt.loss[v] = s;
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) bt.loss[v] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
 }
 
 uint32_t loss_blocks(int32_t width, int32_t height) {
@@ -169,7 +178,7 @@ hipError_t launch_loss(const LossImage *img, int n, float lambda, float *partial
         bt.partial = partial;
         bt.loss = loss + b0;
         hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(kLossThreads), 0, st, bt);
-        hipLaunchKernelGGL(k_loss_sum, dim3(bt.n), dim3(64), 0, st, bt);
+        hipLaunchKernelGGL(k_loss_sum, dim3(bt.n), dim3(kLossSumThreads), 0, st, bt);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -7,8 +7,10 @@
 // the front-to-back order (Sec. 3.2: points sorted by z-distance).
 //
 // Segmentation costs nothing extra: the per-block digit histograms are laid
-// out view-major ([view][digit][block of view]), so one exclusive scan over
-// them yields output positions that stay inside each view's item range.
+// out view-major ([view][digit][block of view]); a block's output positions
+// are its view's first item, plus the view's counts of the smaller digits,
+// plus its digit's counts in the view's earlier blocks, so they stay inside
+// each view's item range.
 #include "dpr_internal.h"
 
 namespace dpr {
@@ -32,7 +34,7 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
-// Exclusive scan over a block of 256 threads; returns the block total in *total.
+// Exclusive scan over the block (any multiple of 64 threads); returns the block total in *total.
 __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *s_wave, uint32_t *total) {
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
@@ -193,13 +195,14 @@ hipError_t launch_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint64_t *
 // segmented radix sort
 // ---------------------------------------------------------------------------
 struct SortSeg {
-    uint32_t lb;       // block index within the view
+    uint32_t lb;       // block index within the segment
     uint32_t beg, end; // item range of this block
-    uint32_t nsb;      // sort blocks of the view
+    uint32_t nsb;      // sort blocks of the segment
+    uint32_t base;     // first item of the segment
     uint64_t hist_off;
 };
 
-// Segments = the views of a plan (the depth sort).
+// Segments = the views of a plan (the depth sort), blocks of kDepthSortTile keys.
 struct ViewSegs {
     Tables tb;
     __device__ __forceinline__ SortSeg operator()() const {
@@ -207,20 +210,22 @@ struct ViewSegs {
         const ViewDesc &vd = tb.views[v];
         SortSeg s;
         s.lb = blockIdx.x - vd.sort_block_off;
-        s.beg = vd.item_off + s.lb * kSortTile;
-        s.end = min(s.beg + (uint32_t)kSortTile, vd.item_off + (uint32_t)vd.n);
+        s.base = vd.item_off;
+        s.beg = vd.item_off + s.lb * (uint32_t)kDepthSortTile;
+        s.end = min(s.beg + (uint32_t)kDepthSortTile, vd.item_off + (uint32_t)vd.n);
         s.nsb = vd.nsort_blocks;
         s.hist_off = vd.hist_off;
         return s;
     }
 };
 
-// One segment of n keys.
+// One segment of n keys, blocks of kSortTile keys.
 struct FlatSeg {
     uint32_t n, nblocks;
     __device__ __forceinline__ SortSeg operator()() const {
         SortSeg s;
         s.lb = blockIdx.x;
+        s.base = 0;
         s.beg = blockIdx.x * (uint32_t)kSortTile;
         s.end = min(s.beg + (uint32_t)kSortTile, n);
         s.nsb = nblocks;
@@ -229,42 +234,50 @@ struct FlatSeg {
     }
 };
 
-template <class SEG>
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(SEG seg, const uint32_t *keys, uint32_t *hist,
-                                                             int shift) {
+template <int THREADS, class SEG>
+__global__ __launch_bounds__(THREADS) void k_radix_hist(SEG seg, const uint32_t *keys, uint32_t *hist, int shift) {
     __shared__ uint32_t h[256];
     const SortSeg sg = seg();
-    h[threadIdx.x] = 0;
+    for (uint32_t d = threadIdx.x; d < 256u; d += THREADS) h[d] = 0;
     __syncthreads();
-    for (uint32_t i = sg.beg + threadIdx.x; i < sg.end; i += kSortThreads)
+    for (uint32_t i = sg.beg + threadIdx.x; i < sg.end; i += THREADS)
         atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
     __syncthreads();
-    hist[sg.hist_off + (uint64_t)threadIdx.x * sg.nsb + sg.lb] = h[threadIdx.x];
+    for (uint32_t d = threadIdx.x; d < 256u; d += THREADS)
+        hist[sg.hist_off + (uint64_t)d * sg.nsb + sg.lb] = h[d];
 }
 
-template <class SEG>
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(SEG seg, const uint32_t *keys_in,
-                                                                const uint32_t *vals_in, uint32_t *keys_out,
-                                                                uint32_t *vals_out, const uint32_t *offs,
-                                                                int shift) {
-    __shared__ uint32_t s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
-    __shared__ uint32_t s_wcnt[kSortThreads / 64][256];
+// Stable scatter of one block of THREADS * ITEMS keys by one 8-bit digit.
+// OWN_OFFSETS: `offs` is the raw histogram ([digit][block] per segment), and
+// the block adds up the output base of each of its digits itself (the
+// segment's totals of the smaller digits and its own digit's counts in the
+// earlier blocks: at most 256 x the segment's blocks reads); otherwise `offs`
+// is the exclusive scan of the histogram.
+template <int THREADS, int ITEMS, bool OWN_OFFSETS, class SEG>
+__global__ __launch_bounds__(THREADS) void k_radix_scatter(SEG seg, const uint32_t *keys_in,
+                                                          const uint32_t *vals_in, uint32_t *keys_out,
+                                                          uint32_t *vals_out, const uint32_t *offs, int shift) {
+    constexpr int TILE = THREADS * ITEMS, WAVES = THREADS / 64;
+    static_assert(THREADS >= 256 && THREADS % 64 == 0, "one thread per digit");
+    __shared__ uint32_t s_keys[TILE];
+    __shared__ uint32_t s_vals[TILE];
+    __shared__ uint32_t s_wcnt[WAVES][256];
     __shared__ uint32_t s_run[256];
     __shared__ uint32_t s_start[256];
     __shared__ uint32_t s_gbase[256];
-    __shared__ uint32_t s_wave[kSortThreads / 64];
+    __shared__ uint32_t s_wave[WAVES];
 
     const SortSeg sg = seg();
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
+    const uint32_t tid = threadIdx.x;
 
-    s_run[threadIdx.x] = 0;
-    uint32_t k_[kSortItemsPerThread], v_[kSortItemsPerThread], r_[kSortItemsPerThread];
+    if (tid < 256u) s_run[tid] = 0;
+    uint32_t k_[ITEMS], v_[ITEMS], r_[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kSortItemsPerThread; ++r) {
-        const uint32_t idx = sg.beg + (uint32_t)r * kSortThreads + threadIdx.x;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = sg.beg + (uint32_t)r * THREADS + tid;
         const bool valid = idx < sg.end;
         const uint32_t key = valid ? keys_in[idx] : 0u;
         const uint32_t val = valid ? vals_in[idx] : 0u;
@@ -283,15 +296,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(SEG seg, const u
         const uint32_t lrank = (uint32_t)__popcll(peers & lt_mask);
         if (valid && lrank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
         __syncthreads();
-        {   // digit threadIdx.x: running count + earlier waves of this round
-            uint32_t acc = s_run[threadIdx.x];
+        if (tid < 256u) {   // digit tid: running count + earlier waves of this round
+            uint32_t acc = s_run[tid];
 #pragma unroll
-            for (int w = 0; w < kSortThreads / 64; ++w) {
-                const uint32_t c = s_wcnt[w][threadIdx.x];
-                s_wcnt[w][threadIdx.x] = acc;
+            for (int w = 0; w < WAVES; ++w) {
+                const uint32_t c = s_wcnt[w][tid];
+                s_wcnt[w][tid] = acc;
                 acc += c;
             }
-            s_run[threadIdx.x] = acc;
+            s_run[tid] = acc;
         }
         __syncthreads();
         k_[r] = key;
@@ -301,13 +314,28 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(SEG seg, const u
     }
     // local start of every digit, and the global base of this block's digit runs
     uint32_t total;
-    const uint32_t cnt = s_run[threadIdx.x];
+    const uint32_t cnt = tid < 256u ? s_run[tid] : 0u;
     const uint32_t start = block_excl_scan_u32(cnt, s_wave, &total);
-    s_start[threadIdx.x] = start;
-    s_gbase[threadIdx.x] = offs[sg.hist_off + (uint64_t)threadIdx.x * sg.nsb + sg.lb];
+    if (tid < 256u) s_start[tid] = start;
+    if (OWN_OFFSETS) {
+        uint32_t tot = 0, pre = 0;
+        if (tid < 256u) {
+            const uint32_t *hd = offs + sg.hist_off + (uint64_t)tid * sg.nsb;
+            for (uint32_t b = 0; b < sg.nsb; ++b) {
+                const uint32_t v = hd[b];
+                tot += v;
+                pre += b < sg.lb ? v : 0u;
+            }
+        }
+        uint32_t all;
+        const uint32_t below = block_excl_scan_u32(tot, s_wave, &all);
+        if (tid < 256u) s_gbase[tid] = sg.base + below + pre;
+    } else {
+        if (tid < 256u) s_gbase[tid] = offs[sg.hist_off + (uint64_t)tid * sg.nsb + sg.lb];
+    }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortItemsPerThread; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         if (r_[r] != 0xFFFFFFFFu) {
             const uint32_t d = (k_[r] >> shift) & 255u;
             const uint32_t pos = s_start[d] + r_[r];
@@ -317,7 +345,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(SEG seg, const u
     }
     __syncthreads();
     const uint32_t count = sg.end > sg.beg ? sg.end - sg.beg : 0u;
-    for (uint32_t i = threadIdx.x; i < count; i += kSortThreads) {
+    for (uint32_t i = tid; i < count; i += THREADS) {
         const uint32_t key = s_keys[i];
         const uint32_t d = (key >> shift) & 255u;
         const uint32_t dst = s_gbase[d] + (i - s_start[d]);
@@ -326,23 +354,146 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(SEG seg, const u
     }
 }
 
+// The same scatter with each wave owning a contiguous run of ITEMS * 64 keys
+// (the input order is wave-major, then round, then lane): a wave ranks its
+// keys with its own digit counters, round after round, with no block
+// barrier; one barrier then turns the counters into per-wave bases.  Used by
+// the depth sort, with its own offsets.
+template <int THREADS, int ITEMS, class SEG>
+__global__ __launch_bounds__(THREADS) void k_radix_scatter_wm(SEG seg, const uint32_t *keys_in,
+                                                             const uint32_t *vals_in, uint32_t *keys_out,
+                                                             uint32_t *vals_out, const uint32_t *hist, int shift) {
+    constexpr int TILE = THREADS * ITEMS, WAVES = THREADS / 64;
+    static_assert(THREADS >= 256 && THREADS % 256 == 0, "whole threads per digit");
+    __shared__ uint32_t s_keys[TILE];
+    __shared__ uint32_t s_vals[TILE];
+    __shared__ uint32_t s_wcnt[WAVES][256];
+    __shared__ uint32_t s_start[256];
+    __shared__ uint32_t s_gbase[256];
+    __shared__ uint32_t s_wave[WAVES];
+
+    constexpr int QUARTERS = THREADS / 256;
+    __shared__ uint32_t s_tot[QUARTERS][256], s_pre[QUARTERS][256];
+    const SortSeg sg = seg();
+    const uint32_t lane = (uint32_t)__lane_id();
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    // this block's offsets, issued first so that their loads overlap the
+    // ranking: thread (q, d) sums digit d's counts over blocks q, q + QUARTERS, ...
+    uint32_t tot_q = 0, pre_q = 0;
+    {
+        const uint32_t d = tid & 255u, q = tid >> 8;
+        const uint32_t *hd = hist + sg.hist_off + (uint64_t)d * sg.nsb;
+#pragma unroll 4
+        for (uint32_t b = q; b < sg.nsb; b += QUARTERS) {
+            const uint32_t v = hd[b];
+            tot_q += v;
+            pre_q += b < sg.lb ? v : 0u;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_wcnt[wave][lane + 64 * q] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t k_[ITEMS], v_[ITEMS], r_[ITEMS];
+    const uint32_t wbeg = sg.beg + wave * (uint32_t)(ITEMS * 64);
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = wbeg + (uint32_t)r * 64u + lane;
+        const bool valid = idx < sg.end;
+        const uint32_t key = valid ? keys_in[idx] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        k_[r] = key;
+        v_[r] = valid ? vals_in[idx] : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t lrank = (uint32_t)__popcll(peers & lt_mask);
+        // every lane of a digit reads the counter before its first lane adds
+        // the digit's count (one wave: its LDS operations complete in order)
+        const uint32_t before = s_wcnt[wave][d];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (valid && lrank == 0) s_wcnt[wave][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        r_[r] = valid ? before + lrank : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    // digit tid: the waves' counts -> per-wave bases, and the block's total
+    uint32_t cnt = 0;
+    if (tid < 256u) {
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t c = s_wcnt[w][tid];
+            s_wcnt[w][tid] = cnt;
+            cnt += c;
+        }
+    }
+    uint32_t total;
+    const uint32_t start = block_excl_scan_u32(cnt, s_wave, &total);
+    if (tid < 256u) s_start[tid] = start;
+    s_tot[tid >> 8][tid & 255u] = tot_q;
+    s_pre[tid >> 8][tid & 255u] = pre_q;
+    __syncthreads();
+    uint32_t tot = 0, pre = 0;
+    if (tid < 256u) {
+#pragma unroll
+        for (int q = 0; q < QUARTERS; ++q) {
+            tot += s_tot[q][tid];
+            pre += s_pre[q][tid];
+        }
+    }
+    uint32_t all;
+    const uint32_t below = block_excl_scan_u32(tot, s_wave, &all);
+    if (tid < 256u) s_gbase[tid] = sg.base + below + pre;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        if (r_[r] != 0xFFFFFFFFu) {
+            const uint32_t d = (k_[r] >> shift) & 255u;
+            const uint32_t pos = s_start[d] + s_wcnt[wave][d] + r_[r];
+            s_keys[pos] = k_[r];
+            s_vals[pos] = v_[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t count = sg.end > sg.beg ? sg.end - sg.beg : 0u;
+    for (uint32_t i = tid; i < count; i += THREADS) {
+        const uint32_t key = s_keys[i];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t dst = s_gbase[d] + (i - s_start[d]);
+        keys_out[dst] = key;
+        vals_out[dst] = s_vals[i];
+    }
+}
+
+// The depth sort: 4 passes of 2 launches (histogram, scatter with its own
+// offsets); the histogram of a view is small enough (256 x its blocks of
+// kDepthSortTile keys) for every block to read the part it needs.
 hipError_t launch_depth_sort(const Tables &tb, uint32_t sort_blocks, uint32_t items,
                              uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                              uint32_t *hist, uint64_t *part, hipStream_t st) {
     (void)items;
+    (void)part;
     if (sort_blocks == 0) return hipSuccess;
-    const uint64_t nh = (uint64_t)sort_blocks * 256u;
     uint32_t *kin = keys, *vin = vals, *kout = keys_alt, *vout = vals_alt;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
         const ViewSegs seg{tb};
-        hipLaunchKernelGGL(k_radix_hist<ViewSegs>, dim3(sort_blocks), dim3(kSortThreads), 0, st, seg, kin, hist,
+        hipLaunchKernelGGL((k_radix_hist<kDepthSortThreads, ViewSegs>), dim3(sort_blocks), dim3(kDepthSortThreads),
+                           0, st, seg, kin, hist, shift);
+        hipLaunchKernelGGL((k_radix_scatter_wm<kDepthSortThreads, kDepthSortTile / kDepthSortThreads, ViewSegs>),
+                           dim3(sort_blocks), dim3(kDepthSortThreads), 0, st, seg, kin, vin, kout, vout, hist,
                            shift);
-        hipError_t e = launch_scan(hist, hist, nh, part, reinterpret_cast<uint64_t *>(part) + scan_partials(nh),
-                                   st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter<ViewSegs>, dim3(sort_blocks), dim3(kSortThreads), 0, st, seg, kin, vin,
-                           kout, vout, hist, shift);
         uint32_t *t;
         t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
@@ -361,11 +512,12 @@ hipError_t launch_radix_sort(uint32_t n, int bits, uint32_t *keys, uint32_t *val
     const FlatSeg seg{n, nb};
     uint32_t *kin = keys, *vin = vals, *kout = keys_alt, *vout = vals_alt;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist<FlatSeg>, dim3(nb), dim3(kSortThreads), 0, st, seg, kin, hist, shift);
+        hipLaunchKernelGGL((k_radix_hist<kSortThreads, FlatSeg>), dim3(nb), dim3(kSortThreads), 0, st, seg, kin, hist,
+                           shift);
         hipError_t e = launch_scan(hist, hist, nh, part, part + scan_partials(nh), st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter<FlatSeg>, dim3(nb), dim3(kSortThreads), 0, st, seg, kin, vin, kout,
-                           vout, hist, shift);
+        hipLaunchKernelGGL((k_radix_scatter<kSortThreads, kSortItemsPerThread, false, FlatSeg>), dim3(nb),
+                           dim3(kSortThreads), 0, st, seg, kin, vin, kout, vout, hist, shift);
         uint32_t *t;
         t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;

@@ -18,6 +18,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -198,6 +199,9 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
 }
 
 inline int __lane_id() { return (int)(threadIdx.x & 63u); }
+
+// A memory fence of the given order and scope; here a full fence of the host.
+inline void __builtin_amdgcn_fence(int, const char *) { std::atomic_thread_fence(std::memory_order_seq_cst); }
 
 // The lanes of a wave run in lockstep on the GPU; here they meet at a barrier.
 inline void __builtin_amdgcn_wave_barrier() {
