@@ -305,7 +305,8 @@ def main():
         forward alone), i.e. around everything but the Adam update."""
         if ev is not None:
             ev[0].record()
-        plan = dpr.Plan([trainer.scene], [(0, c) for c in step_views[k]], params, workspace=wss[k % 2])
+        plan = dpr.Plan([trainer.scene], [(0, c) for c in step_views[k]], params, workspace=wss[k % 2],
+                        forward_now=True)
         plan.forward()
         if train:
             tgt = targets[k % len(targets)]

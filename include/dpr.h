@@ -38,7 +38,8 @@
  *
  * Streams: a stream argument is a hipStream_t passed as void* (NULL = the
  * default stream).  Everything is asynchronous on that stream except
- * dpr_plan_forward, which waits once for the number of (tile, splat) pairs.
+ * dpr_plan_forward and dpr_plan_forward_render, which wait once for the
+ * number of (tile, splat) pairs.
  *
  * Errors: functions returning int return a dpr_status; a non-zero status
  * leaves a message in dpr_last_error() (thread-local).  The library never
@@ -200,6 +201,26 @@ size_t dpr_workspace_bytes(const dpr_plan *plan);
  * to back (Eq. 5-7), writing image and trans of each view.  `ws` must stay
  * alive and untouched until the last dpr_render_backward of this plan. */
 int dpr_render_forward(dpr_plan *plan, void *ws, size_t ws_bytes, void *stream);
+
+/* dpr_plan_forward and dpr_render_forward in one call, for a caller that keeps
+ * a forward workspace from plan to plan (the rendering of Sec. 3.2, Eq. 5-7,
+ * of the plan stage's splats).  The forward is queued right behind the plan
+ * stage, before the wait for the pair count, laid out for as many pairs as
+ * fwd_ws_bytes can hold; its kernels read the pair count on the device and do
+ * nothing if the lists do not fit.  So the device goes on from the plan to the
+ * forward without the host's round trip.
+ *   *rendered = 1: the forward ran into fwd_ws, exactly as dpr_render_forward
+ *                  would have; fwd_ws is this plan's forward workspace (for
+ *                  dpr_render_backward) and dpr_plan_get_info reports its layout.
+ *   *rendered = 0: fwd_ws was too small (dpr_workspace_bytes tells the size);
+ *                  nothing was written to it or to the images.  The plan is
+ *                  valid: call dpr_render_forward with a large enough buffer.
+ * Arguments, ownership and errors otherwise as dpr_plan_forward; fwd_ws and
+ * rendered must not be NULL (DPR_ERR_INVALID_ARG). */
+int dpr_plan_forward_render(const dpr_scene *scenes, int32_t n_scenes,
+                            const dpr_view *views, int32_t n_views, const dpr_params *params,
+                            void *plan_ws, size_t plan_ws_bytes, void *fwd_ws, size_t fwd_ws_bytes,
+                            void *stream, dpr_plan **out, int32_t *rendered);
 
 /* Bytes of the backward scratch workspace (per-view-point gradient records,
  * plus, in recompute mode, the backward state that stored mode keeps in the

@@ -26,7 +26,7 @@ EXPORTED = ["dpr_version", "dpr_last_error", "dpr_plan_ws_bytes", "dpr_plan_forw
             "dpr_render_forward_1", "dpr_loss_ws_bytes", "dpr_loss_l2_tv", "dpr_knn_ws_bytes", "dpr_knn",
             "dpr_hybrid_ws_bytes", "dpr_voxel_reduce", "dpr_hybrid_update", "dpr_hull_ws_bytes", "dpr_hull_sample",
             "dpr_consistency", "dpr_consistency_filter", "dpr_chamfer_ws_bytes", "dpr_chamfer", "dpr_topk_sh",
-            "dpr_adam_step", "dpr_render_forward_1_noalloc"]
+            "dpr_adam_step", "dpr_render_forward_1_noalloc", "dpr_plan_forward_render"]
 
 
 class Camera(ctypes.Structure):
@@ -87,6 +87,10 @@ def load(path: str = LIB_PATH):
     L.dpr_plan_forward.argtypes = [ctypes.POINTER(Scene), c_i32, ctypes.POINTER(View), c_i32,
                                    ctypes.POINTER(Params), c_p, c_sz, c_p, ctypes.POINTER(c_p)]
     L.dpr_plan_forward.restype = c_i32
+    L.dpr_plan_forward_render.argtypes = [ctypes.POINTER(Scene), c_i32, ctypes.POINTER(View), c_i32,
+                                          ctypes.POINTER(Params), c_p, c_sz, c_p, c_sz, c_p, ctypes.POINTER(c_p),
+                                          ctypes.POINTER(c_i32)]
+    L.dpr_plan_forward_render.restype = c_i32
     L.dpr_workspace_bytes.argtypes, L.dpr_workspace_bytes.restype = [c_p], c_sz
     L.dpr_backward_ws_bytes.argtypes, L.dpr_backward_ws_bytes.restype = [c_p], c_sz
     L.dpr_render_forward.argtypes, L.dpr_render_forward.restype = [c_p, c_p, c_sz, c_p], c_i32

@@ -193,6 +193,7 @@ struct dpr_plan {
     std::vector<uint32_t> up_img;   // the upload image of views, scenes and u32tab
     uint8_t *pws = nullptr;
     uint64_t pairs = 0;
+    uint64_t fwd_pairs = 0;          // the pair count the forward workspace in use was laid out for
     int forward_done = 0;
     const void *fwd_ws = nullptr;
     Events ev;
@@ -247,12 +248,12 @@ struct BwdState {
     Region nlast, fin, ckpt, work;
 };
 
-BwdState add_bwd_state(Layout &L, const dpr_plan *p, bool on) {
+BwdState add_bwd_state(Layout &L, const dpr_plan *p, bool on, uint64_t pairs) {
     BwdState s;
     s.nlast = L.add(on ? 4 * p->sz.pixels : 0);
     s.fin = L.add(on ? 16 * p->sz.pixels : 0);
-    s.ckpt = L.add(on ? 16ull * kTilePix * ckpt_slots(p->pairs, p->sz.tiles) : 0);
-    s.work = L.add(on ? 8 * work_capacity(p->pairs, p->sz.tiles) : 0);
+    s.ckpt = L.add(on ? 16ull * kTilePix * ckpt_slots(pairs, p->sz.tiles) : 0);
+    s.work = L.add(on ? 8 * work_capacity(pairs, p->sz.tiles) : 0);
     return s;
 }
 
@@ -262,15 +263,33 @@ struct FwdLayout {
     uint64_t total = 0;
 };
 
-FwdLayout fwd_layout(const dpr_plan *p) {
+// The forward workspace laid out for `pairs` (tile, splat) pairs: a workspace
+// laid out for more pairs than the plan has serves it as well.
+FwdLayout fwd_layout_for(const dpr_plan *p, uint64_t pairs) {
     Layout L;
     FwdLayout f;
-    f.pairs = L.add(4 * p->pairs);
-    f.st = add_bwd_state(L, p, p->params.bwd_mode == DPR_BWD_STORED);
+    f.pairs = L.add(4 * pairs);
+    f.st = add_bwd_state(L, p, p->params.bwd_mode == DPR_BWD_STORED, pairs);
     f.stats = L.add((p->params.flags & DPR_FLAG_STATS) ? 4 * p->sz.pixels : 0);
     f.counters = L.add(16);
     f.total = L.total;
     return f;
+}
+
+// The layout of the forward workspace in use.
+FwdLayout fwd_layout(const dpr_plan *p) { return fwd_layout_for(p, p->fwd_pairs); }
+
+// The most pairs a forward workspace of `bytes` can hold (its size grows with
+// the pair count), or -1 if it cannot hold the plan's per-pixel state at all.
+int64_t pairs_that_fit(const dpr_plan *p, uint64_t bytes) {
+    if (fwd_layout_for(p, 0).total > bytes) return -1;
+    uint64_t lo = 0, hi = 0xFFFFFFFEull;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (fwd_layout_for(p, mid).total <= bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return (int64_t)lo;
 }
 
 struct BwdLayout {
@@ -285,7 +304,7 @@ BwdLayout bwd_layout(const dpr_plan *p) {
     b.tabs = L.add(8ull * 2 * p->sz.n_views);
     b.sgrad = L.add(sizeof(SceneDesc) * (uint64_t)p->sz.n_scenes);
     b.grad = L.add(32ull * p->sz.items);
-    b.st = add_bwd_state(L, p, p->params.bwd_mode == DPR_BWD_RECOMPUTE);
+    b.st = add_bwd_state(L, p, p->params.bwd_mode == DPR_BWD_RECOMPUTE, p->pairs);
     b.counters = L.add(16);
     b.total = L.total;
     return b;
@@ -455,12 +474,20 @@ size_t dpr_plan_ws_bytes(const dpr_scene *scenes, int32_t n_scenes, const dpr_vi
     return (size_t)plan_layout(s).total;
 }
 
-int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *views, int32_t n_views,
-                     const dpr_params *params, void *plan_ws, size_t plan_ws_bytes, void *stream,
-                     dpr_plan **out) {
+namespace {
+int launch_forward(dpr_plan *p, void *ws, uint64_t layout_pairs, uint32_t pair_cap, hipStream_t st);
+int64_t pairs_that_fit(const dpr_plan *p, uint64_t bytes);
+
+// The plan stage; with fwd_ws, also the forward into it, queued before the
+// wait for the pair count (the kernels check the count against what fwd_ws
+// can hold and do nothing if it does not fit); *rendered tells which.
+int plan_forward_impl(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *views, int32_t n_views,
+                      const dpr_params *params, void *plan_ws, size_t plan_ws_bytes, void *fwd_ws,
+                      size_t fwd_ws_bytes, void *stream, dpr_plan **out, int32_t *rendered) {
     g_err.clear();
     if (!out) return fail(DPR_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    if (rendered) *rendered = 0;
     int rc = check_params(params);
     if (rc) return rc;
     Sizes s;
@@ -638,7 +665,23 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
         STAGE_TRY(launch_tile_colscan(tb, cnt, segs, tile_total, bucket_cnt, block_sum, tile_base,
                                       reinterpret_cast<uint32_t *>(w + lay.tile_order.off), total64, st));
     }
-    STAGE_TRY(read_count(total64, &p->pairs, st));
+    if (!fwd_ws) {
+        STAGE_TRY(read_count(total64, &p->pairs, st));
+    } else {
+        STAGE_TRY(read_count_begin(total64, st));
+        const int64_t cap = pairs_that_fit(p, fwd_ws_bytes);
+        if (cap >= 0) {
+            const int rc2 = launch_forward(p, fwd_ws, (uint64_t)cap, (uint32_t)cap, st);
+            if (rc2) return cleanup_fail(rc2);
+        }
+        STAGE_TRY(read_count_end(&p->pairs));
+        if (cap >= 0 && p->pairs <= (uint64_t)cap) {
+            p->forward_done = 1;
+            p->fwd_ws = fwd_ws;
+            if (rendered) *rendered = 1;
+        }
+    }
+    if (!p->forward_done) p->fwd_pairs = p->pairs;
     if (p->pairs >= 0xFFFFFFFFull)
         return cleanup_fail(fail(DPR_ERR_UNSUPPORTED, "%llu (tile, splat) pairs exceed 2^32 - 1",
                                  (unsigned long long)p->pairs));
@@ -647,9 +690,27 @@ int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *
     return DPR_OK;
 }
 
+}  // namespace
+
+int dpr_plan_forward(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *views, int32_t n_views,
+                     const dpr_params *params, void *plan_ws, size_t plan_ws_bytes, void *stream,
+                     dpr_plan **out) {
+    return plan_forward_impl(scenes, n_scenes, views, n_views, params, plan_ws, plan_ws_bytes, nullptr, 0, stream,
+                             out, nullptr);
+}
+
+int dpr_plan_forward_render(const dpr_scene *scenes, int32_t n_scenes, const dpr_view *views, int32_t n_views,
+                            const dpr_params *params, void *plan_ws, size_t plan_ws_bytes, void *fwd_ws,
+                            size_t fwd_ws_bytes, void *stream, dpr_plan **out, int32_t *rendered) {
+    if (!rendered) return fail(DPR_ERR_INVALID_ARG, "rendered is NULL");
+    if (!fwd_ws) return fail(DPR_ERR_INVALID_ARG, "fwd_ws is NULL (dpr_plan_forward plans without a forward)");
+    return plan_forward_impl(scenes, n_scenes, views, n_views, params, plan_ws, plan_ws_bytes, fwd_ws, fwd_ws_bytes,
+                             stream, out, rendered);
+}
+
 size_t dpr_workspace_bytes(const dpr_plan *plan) {
     if (!plan) return 0;
-    return (size_t)fwd_layout(plan).total;
+    return (size_t)fwd_layout_for(plan, plan->pairs).total;
 }
 
 size_t dpr_backward_ws_bytes(const dpr_plan *plan) {
@@ -657,15 +718,13 @@ size_t dpr_backward_ws_bytes(const dpr_plan *plan) {
     return (size_t)bwd_layout(plan).total;
 }
 
-int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
-    g_err.clear();
-    if (!p) return fail(DPR_ERR_INVALID_ARG, "plan is NULL");
+namespace {
+
+// Emission and compositing into `ws`, laid out for layout_pairs pairs; the
+// kernels do nothing if the plan holds more than pair_cap pairs.
+int launch_forward(dpr_plan *p, void *ws, uint64_t layout_pairs, uint32_t pair_cap, hipStream_t st) {
+    p->fwd_pairs = layout_pairs;
     const FwdLayout f = fwd_layout(p);
-    if (!ws || ws_bytes < f.total)
-        return fail(DPR_ERR_WORKSPACE, "forward workspace needs %llu bytes, got %llu",
-                    (unsigned long long)f.total, (unsigned long long)ws_bytes);
-    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
-    hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t *w = static_cast<uint8_t *>(ws);
     const Tables tb = make_tables(p);
     const PlanLayout &lay = p->lay;
@@ -677,9 +736,10 @@ int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
                                  reinterpret_cast<const uint32_t *>(p->pws + lay.cnt.off),
                                  reinterpret_cast<const uint32_t *>(p->pws + lay.tile_base.off),
                                  reinterpret_cast<uint32_t *>(w + f.pairs.off),
-                                 reinterpret_cast<uint32_t *>(w + f.counters.off), st));
+                                 reinterpret_cast<uint32_t *>(w + f.counters.off), pair_cap, st));
     }
     CompositeArgs a = composite_args(p, ws);
+    a.pair_cap = pair_cap;
     a.write_views = 1;
     a.stats = f.stats.bytes ? reinterpret_cast<uint32_t *>(w + f.stats.off) : nullptr;
     if (p->params.bwd_mode == DPR_BWD_STORED) set_bwd_state(a, w, f.st);
@@ -689,6 +749,22 @@ int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
         StageScope sc_(p, DPR_STAGE_COMPOSITE_FWD, st);   // the counters were cleared by the emission
         HIP_TRY(launch_composite_fwd(a, persistent, st));
     }
+    return DPR_OK;
+}
+
+}  // namespace
+
+int dpr_render_forward(dpr_plan *p, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!p) return fail(DPR_ERR_INVALID_ARG, "plan is NULL");
+    const uint64_t need = fwd_layout_for(p, p->pairs).total;
+    if (!ws || ws_bytes < need)
+        return fail(DPR_ERR_WORKSPACE, "forward workspace needs %llu bytes, got %llu", (unsigned long long)need,
+                    (unsigned long long)ws_bytes);
+    if (fault_injected("launch")) return fail(DPR_ERR_HIP, "injected launch failure (DPR_FAULT=launch)");
+    p->forward_done = 0;
+    const int rc = launch_forward(p, ws, p->pairs, 0xFFFFFFFFu, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
     p->forward_done = 1;
     p->fwd_ws = ws;
     return DPR_OK;

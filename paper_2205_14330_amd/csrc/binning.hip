@@ -291,13 +291,14 @@ static_assert(kChunkItems % 32 == 0 && kEmitWords <= 32, "whole bitmap words, on
 __global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uint32_t *order, const uint2 *rect,
                                                              const SplatRec *rec, float lambda, const uint32_t *pre,
                                                              const uint32_t *tile_base, uint32_t *pairs,
-                                                             uint32_t *zero4) {
+                                                             uint32_t *zero4, uint32_t pair_cap) {
     // word w of band tile b at s_bits[w * kEmitBand + b]: the write phase's
     // lanes (consecutive tiles) read consecutive words
     __shared__ uint32_t s_bits[kEmitWords * kEmitBand];
     __shared__ uint32_t s_sum[kEmitBand];
     __shared__ uint32_t s_g[kChunkItems];
     __shared__ uint2 s_rect[kChunkItems];
+    if (tile_base[tb.total_tiles] > pair_cap) return;     // the pair lists do not fit the workspace
     const ChunkInfo ci = chunk_info(tb);
     const uint32_t tid = threadIdx.x;
     const uint32_t n = ci.end - ci.beg;
@@ -393,10 +394,11 @@ hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *
 
 hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
                             const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
-                            const uint32_t *tile_base, uint32_t *pairs, uint32_t *zero4, hipStream_t st) {
-    if (chunks == 0) return launch_fill_u32(zero4, 0u, 4, st);
+                            const uint32_t *tile_base, uint32_t *pairs, uint32_t *zero4, uint32_t pair_cap,
+                            hipStream_t st) {
+    if (chunks == 0) return launch_fill_u32(zero4, 0u, 4, st);     // no items: no pairs
     hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitThreads), 0, st, tb, order, rect, rec, lambda, pre,
-                       tile_base, pairs, zero4);
+                       tile_base, pairs, zero4, pair_cap);
     return hipGetLastError();
 }
 

@@ -168,6 +168,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     const float w_noclamp = in_vgpr(no_clamp_w(alpha_max));
     const float t_min = in_vgpr(a.th.t_min);
     const uint32_t cap = in_vgpr(a.th.max_splats > 0 ? a.th.max_splats : 0xFFFFFFFFu);
+    if (a.tile_base[a.total_tiles] > a.pair_cap) return;   // the pair lists do not fit the workspace
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const char *b0 = reinterpret_cast<const char *>(s_r0[wave]), *b1 = reinterpret_cast<const char *>(s_r1[wave]);
     // block (or popped) index -> tile: through the longest-first order when there is one
@@ -775,18 +776,45 @@ hipError_t upload_zero_async(void *dst, const void *src, size_t bytes, uint32_t 
     return hipGetLastError();
 }
 
-hipError_t read_count(const uint64_t *dev, uint64_t *out, hipStream_t st) {
-    // a pageable destination would go through the runtime's staging buffer
-    thread_local uint64_t *pinned = nullptr;
-    if (!pinned) {
+// The thread's pinned word and event for count read-backs (a pageable
+// destination would go through the runtime's staging buffer).
+namespace {
+struct CountSlot {
+    uint64_t *pinned = nullptr;
+    hipEvent_t ev = nullptr;
+};
+thread_local CountSlot t_count;
+
+hipError_t count_slot() {
+    if (!t_count.pinned) {
         void *h = nullptr;
         const hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
         if (e != hipSuccess) return e;
-        pinned = static_cast<uint64_t *>(h);
+        t_count.pinned = static_cast<uint64_t *>(h);
     }
-    hipError_t e = hipMemcpyAsync(pinned, dev, 8, hipMemcpyDeviceToHost, st);
+    if (!t_count.ev) return hipEventCreateWithFlags(&t_count.ev, hipEventDisableTiming);
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t read_count(const uint64_t *dev, uint64_t *out, hipStream_t st) {
+    hipError_t e = count_slot();
+    if (e == hipSuccess) e = hipMemcpyAsync(t_count.pinned, dev, 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess) *out = *pinned;
+    if (e == hipSuccess) *out = *t_count.pinned;
+    return e;
+}
+
+hipError_t read_count_begin(const uint64_t *dev, hipStream_t st) {
+    hipError_t e = count_slot();
+    if (e == hipSuccess) e = hipMemcpyAsync(t_count.pinned, dev, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(t_count.ev, st);
+    return e;
+}
+
+hipError_t read_count_end(uint64_t *out) {
+    const hipError_t e = hipEventSynchronize(t_count.ev);
+    if (e == hipSuccess) *out = *t_count.pinned;
     return e;
 }
 

@@ -215,9 +215,11 @@ hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, 
                                uint32_t *bucket_cnt, uint64_t *block_sum, uint32_t *tile_base, uint32_t *order,
                                uint64_t *total64, hipStream_t st);
 // Also clears the 4 words at zero4 (the compositing counters that follow it).
+// With more than pair_cap pairs in the plan (tile_base[total tiles]) it does nothing.
 hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
                             const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
-                            const uint32_t *tile_base, uint32_t *pairs, uint32_t *zero4, hipStream_t st);
+                            const uint32_t *tile_base, uint32_t *pairs, uint32_t *zero4, uint32_t pair_cap,
+                            hipStream_t st);
 
 // Backward state of a tile list at the list positions s * kBwdSeg (s >= 1):
 // per pixel (T, I) after the first s * kBwdSeg splats, 256 float4 per slot in
@@ -248,6 +250,9 @@ struct CompositeArgs {
     uint2 *work;                // (tile, segment) backward work items
     uint32_t *counters;         // [0] persistent queue, [1] work items appended
     Thresholds th;
+    // the pair capacity the forward workspace was laid out for: a launch whose
+    // plan holds more pairs (tile_base[total_tiles]) does nothing
+    uint32_t pair_cap = 0xFFFFFFFFu;
 };
 hipError_t launch_composite_fwd(const CompositeArgs &a, bool persistent, hipStream_t st);
 // The forward takes the tiles longest pair list first: a tile's compositing
@@ -385,6 +390,10 @@ hipError_t upload_zero_async(void *dst, const void *src, size_t bytes, uint32_t 
 // pinned host word of the calling thread (allocated on the thread's first
 // call and kept until the process ends), waits for the stream, stores it in *out.
 hipError_t read_count(const uint64_t *dev, uint64_t *out, hipStream_t st);
+// The same in two halves: the copy into the thread's pinned word and an event
+// behind it, queued on `st`; then the wait for that event and the value.
+hipError_t read_count_begin(const uint64_t *dev, hipStream_t st);
+hipError_t read_count_end(uint64_t *out);
 
 // Sets the thread's dpr_last_error message and returns `code`.
 int set_last_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));

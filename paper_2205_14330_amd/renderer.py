@@ -144,7 +144,13 @@ class Plan:
     def __init__(self, scenes: Sequence[SceneTensors], views: Sequence[Tuple[int, object]],
                  params: RenderParams = RenderParams(), stream: Optional[torch.cuda.Stream] = None,
                  images: Optional[Sequence[torch.Tensor]] = None, trans: Optional[Sequence[torch.Tensor]] = None,
-                 workspace: Optional[Workspace] = None):
+                 workspace: Optional[Workspace] = None, forward_now: bool = False):
+        """forward_now: also render, in the same call (then forward() returns
+        the images without further work the first time).  With a Workspace
+        that already holds a forward buffer, the forward is queued behind the
+        plan stage before the host waits for the pair count
+        (dpr_plan_forward_render); if the buffer proves too small, it is grown
+        and the forward runs after the wait."""
         self.lib = load()
         self.workspace = workspace
         self.scenes = list(scenes)
@@ -175,11 +181,28 @@ class Plan:
         else:
             self.plan_ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
         self._plan = ctypes.c_void_p()
-        rc = self.lib.dpr_plan_forward(self._c_scenes, len(self.scenes), self._c_views, len(cv),
-                                       ctypes.byref(self._c_params), self.plan_ws.data_ptr(), int(nbytes),
-                                       _stream_handle(stream), ctypes.byref(self._plan))
-        check(rc)
         self.ws = None
+        self._rendered = False
+        fwd = workspace.bufs.get("fwd") if (forward_now and workspace is not None) else None
+        if fwd is not None:
+            done = ctypes.c_int32(0)
+            rc = self.lib.dpr_plan_forward_render(self._c_scenes, len(self.scenes), self._c_views, len(cv),
+                                                  ctypes.byref(self._c_params), self.plan_ws.data_ptr(),
+                                                  int(nbytes), fwd.data_ptr(), int(fwd.numel()),
+                                                  _stream_handle(stream), ctypes.byref(self._plan),
+                                                  ctypes.byref(done))
+            check(rc)
+            if done.value:
+                self.ws = fwd
+                self._rendered = True
+        else:
+            rc = self.lib.dpr_plan_forward(self._c_scenes, len(self.scenes), self._c_views, len(cv),
+                                           ctypes.byref(self._c_params), self.plan_ws.data_ptr(), int(nbytes),
+                                           _stream_handle(stream), ctypes.byref(self._plan))
+            check(rc)
+        if forward_now and not self._rendered:
+            self.forward()
+            self._rendered = True
 
     def _check_owner(self):
         if self.workspace is not None and self.workspace.owner is not self:
@@ -188,6 +211,9 @@ class Plan:
     # -- forward ------------------------------------------------------------------
     def forward(self):
         self._check_owner()
+        if self._rendered:           # rendered together with the plan
+            self._rendered = False
+            return self.images, self.trans
         n = int(self.lib.dpr_workspace_bytes(self._plan))
         if self.ws is None or self.ws.numel() < n:
             if self.workspace is not None:

@@ -181,6 +181,25 @@ def test_invalid_arguments_rejected(abi, case, expect):
     assert not out.value
 
 
+@pytest.mark.parametrize("case", ["null_rendered", "null_fwd_ws", "bad_params"])
+def test_plan_forward_render_rejects_before_device_work(abi, case):
+    """The argument checks of dpr_plan_forward_render run on the host, before
+    any device call (the fake workspace pointers are never touched)."""
+    lib = abi.load()
+    S = (abi.Scene * 1)(_scene(abi))
+    V = (abi.View * 1)(_view(abi))
+    params = _params(abi, alpha_min=1.5) if case == "bad_params" else _params(abi)
+    out = ctypes.c_void_p()
+    done = ctypes.c_int32(5)
+    fwd = None if case == "null_fwd_ws" else FAKE
+    rendered = None if case == "null_rendered" else ctypes.byref(done)
+    rc = lib.dpr_plan_forward_render(S, 1, V, 1, ctypes.byref(params), FAKE, 1 << 40, fwd, 1 << 40, None,
+                                     ctypes.byref(out), rendered)
+    assert rc == 1 and lib.dpr_last_error().decode() and not out.value
+    if case == "bad_params":
+        assert done.value == 0
+
+
 def test_plan_ws_bytes_host_only(abi):
     lib = abi.load()
     S = (abi.Scene * 1)(_scene(abi, n=5000))
