@@ -47,8 +47,7 @@ KERNELS = {
     "dpr::k_tile_count": "tile_count",
     "dpr::k_col_segsum": "col_segsum",
     "dpr::k_col_segscan": "col_segscan",
-    "dpr::k_col_down": "col_down",
-    "dpr::k_tile_order": "tile_order",
+    "dpr::k_col_finish": "col_finish",
     "dpr::k_tile_emit": "tile_emit",
     "dpr::k_composite_bwd": "composite_bwd",
     "dpr::k_composite<false, true,": "composite_fwd_count",   # forward keeping blend counts
@@ -58,6 +57,7 @@ KERNELS = {
     "dpr::k_fill_u32": "fill",
     "dpr::k_loss_sum": "loss_sum",
     "dpr::k_loss": "loss",
+    "dpr::k_upload_zero": "upload_zero",
     "dpr::k_upload": "upload",
 }
 
