@@ -172,6 +172,10 @@ class RenderResult:
     trans: np.ndarray      # [npix]    (or [H, W])
     ncontrib: np.ndarray   # number of blended splats per pixel
     stopped: np.ndarray    # early stop fired
+    # under a cap (max_splats > 0): the pixel's result rests on a predicate
+    # decided within a relative 1e-4 of alpha_min, which an evaluation in
+    # another precision may decide the other way (two valid results)
+    near_tie: Optional[np.ndarray] = None
 
 
 def render(scene, cam, params: Params = Params(), pixels: Optional[np.ndarray] = None,
@@ -193,9 +197,12 @@ def render(scene, cam, params: Params = Params(), pixels: Optional[np.ndarray] =
                              _p(img), _p(tr), _p(nc), _p(st), threads)
     if rc:
         raise ValueError("oracle_render failed")
+    tie = (st >> 1) & 1
+    st = st & 1
     if pix is None:
-        return RenderResult(img.reshape(H, W, 3), tr.reshape(H, W), nc.reshape(H, W), st.reshape(H, W))
-    return RenderResult(img, tr, nc, st)
+        return RenderResult(img.reshape(H, W, 3), tr.reshape(H, W), nc.reshape(H, W), st.reshape(H, W),
+                            tie.reshape(H, W).astype(bool))
+    return RenderResult(img, tr, nc, st, tie.astype(bool))
 
 
 @dataclass
@@ -260,7 +267,7 @@ def render_double(xyz, sh, opacity, radius, cam, params: Params = Params(), pixe
                              _p(pix), _p(img), _p(tr), _p(nc), _p(st), threads)
     if rc:
         raise ValueError("oracle_render failed")
-    return RenderResult(img, tr, nc, st)
+    return RenderResult(img, tr, nc, st & 1, ((st >> 1) & 1).astype(bool))
 
 
 def backward_double(xyz, sh, opacity, radius, cam, dL_dimage, dL_dtrans=None, params: Params = Params(),

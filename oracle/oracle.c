@@ -283,6 +283,12 @@ typedef struct {
     int kernel_norm;         /* 1: Eq. (5)'s normalisation prefactor is kept  */
 } or_params;
 
+/* Relative distance to alpha_min within which a capped pixel's predicate
+ * decision counts as a near tie (see composite_pixel).  A float32 evaluation of
+ * the exponent (from float32 splat centres and shapes) differs from this
+ * float64 one by up to a few 1e-5 relative in alpha. */
+#define OR_NEAR_TIE 1e-4
+
 static void read_params(const double *params, or_params *pr)
 {
     pr->alpha_min = params[0]; pr->t_min = params[1]; pr->alpha_max = params[2]; pr->z_near = params[3];
@@ -291,12 +297,13 @@ static void read_params(const double *params, or_params *pr)
 }
 
 static int splat_alpha(const or_point *p, double o, double ux, double uy, const or_params *pr,
-                       double *alpha, double *G, int *clamped, double *dx, double *dy)
+                       double *alpha, double *G, int *clamped, double *dx, double *dy, double *a_raw)
 {
     double ex = p->px - ux, ey = p->py - uy;
     double q = ex * ex / (p->sx * p->sx) + ey * ey / (p->sy * p->sy);
     double g = exp(-0.5 * q);
     double a = o * p->k * g;
+    *a_raw = a;
     if (!(a >= pr->alpha_min)) return 0;
     *G = g; *dx = ex; *dy = ey;
     if (a > pr->alpha_max) { *alpha = pr->alpha_max; *clamped = 1; }
@@ -304,14 +311,16 @@ static int splat_alpha(const or_point *p, double o, double ux, double uy, const 
     return 1;
 }
 
-/* Support of the predicate: the ellipse (ex/sx)^2 + (ey/sy)^2 <= 2 ln(o/alpha_min). */
+/* Support of the predicate: the ellipse (ex/sx)^2 + (ey/sy)^2 <= 2 ln(o/alpha_min).
+ * Under a cap it reaches down to alpha_min (1 - OR_NEAR_TIE), so that a pixel
+ * also meets the splats it flags as near ties without blending them. */
 static int support_box(const or_point *p, double o, const or_params *pr,
                        double *x0, double *x1, double *y0, double *y1)
 {
-    double s;
+    double s, lo = pr->max_splats > 0 ? pr->alpha_min * (1.0 - OR_NEAR_TIE) : pr->alpha_min;
     if (!(pr->alpha_min > 0.0)) return -1;            /* unbounded */
-    if (!(o * p->k >= pr->alpha_min)) return 0;        /* never a candidate */
-    s = sqrt(2.0 * log(o * p->k / pr->alpha_min)) * (1.0 + 1e-9) + 1e-9;
+    if (!(o * p->k >= lo)) return 0;                   /* never a candidate */
+    s = sqrt(2.0 * log(o * p->k / lo)) * (1.0 + 1e-9) + 1e-9;
     *x0 = p->px - s * p->sx; *x1 = p->px + s * p->sx;
     *y0 = p->py - s * p->sy; *y1 = p->py + s * p->sy;
     return 1;
@@ -419,9 +428,16 @@ typedef struct {
     int clamped;
 } or_hit;
 
+/* Under a cap (max_splats > 0) the splats a pixel blends depend on every
+ * predicate decision before the cap is reached: a candidate decided within a
+ * relative OR_NEAR_TIE of alpha_min may be decided the other way by an
+ * evaluation in another precision, and then the pixel's n-th splat, and its
+ * colour, change by a whole splat.  Such a pixel has two valid results;
+ * *near_tie is set for it (never without a cap). */
 static int64_t composite_pixel(const or_lists *L, const or_point *pts, const double *opacity,
                                int width, int x, int y, const or_params *pr,
-                               double I[3], double *T_out, int *stopped, or_hit *hits, int64_t hit_cap)
+                               double I[3], double *T_out, int *stopped, int *near_tie, or_hit *hits,
+                               int64_t hit_cap)
 {
     const int64_t *items;
     int64_t cnt, s, nh = 0;
@@ -430,12 +446,14 @@ static int64_t composite_pixel(const or_lists *L, const or_point *pts, const dou
     double ux = x + 0.5, uy = y + 0.5;
     I[0] = I[1] = I[2] = 0.0;
     *stopped = 0;
+    *near_tie = 0;
     pixel_list(L, width, x, y, &items, &cnt, &indirect);
     for (s = 0; s < cnt; ++s) {
         int64_t i = items[s];
-        double alpha, G, dx, dy;
-        int clamped;
-        if (!splat_alpha(&pts[i], opacity[i], ux, uy, pr, &alpha, &G, &clamped, &dx, &dy)) continue;
+        double alpha, G, dx, dy, a;
+        int clamped, hit = splat_alpha(&pts[i], opacity[i], ux, uy, pr, &alpha, &G, &clamped, &dx, &dy, &a);
+        if (pr->max_splats > 0 && fabs(a - pr->alpha_min) <= OR_NEAR_TIE * pr->alpha_min) *near_tie = 1;
+        if (!hit) continue;
         if (hits && nh < hit_cap) {
             hits[nh].i = i; hits[nh].alpha = alpha; hits[nh].T = T; hits[nh].G = G;
             hits[nh].dx = dx; hits[nh].dy = dy; hits[nh].clamped = clamped;
@@ -469,7 +487,8 @@ static void project_all(int64_t n, const double *xyz, const double *sh, int degr
  *   pix: npix linear pixel indices (y * width + x), or NULL for the whole image
  *        in row-major order (npix must then equal width * height)
  *   image[npix][3], trans[npix]; ncontrib[npix] (nullable) = number of blended
- *   splats; stopped[npix] (nullable) = 1 where the early stop fired.
+ *   splats; stopped[npix] (nullable): bit 0 where the early stop fired, bit 1
+ *   where a cap's outcome rests on a near-threshold predicate (composite_pixel).
  */
 int oracle_render(int64_t n, const double *xyz, const double *sh, int degree, const double *opacity,
                   const double *radius, const double *cam, int width, int height,
@@ -494,12 +513,12 @@ int oracle_render(int64_t n, const double *xyz, const double *sh, int degree, co
         int64_t lin = pix ? pix[p] : p;
         int x = (int)(lin % width), y = (int)(lin / width);
         double I[3], T;
-        int st;
-        int64_t nh = composite_pixel(&L, pts, opacity, width, x, y, &pr, I, &T, &st, NULL, 0);
+        int st, tie;
+        int64_t nh = composite_pixel(&L, pts, opacity, width, x, y, &pr, I, &T, &st, &tie, NULL, 0);
         image[3 * p + 0] = I[0]; image[3 * p + 1] = I[1]; image[3 * p + 2] = I[2];
         trans[p] = T;
         if (ncontrib) ncontrib[p] = nh;
-        if (stopped) stopped[p] = st;
+        if (stopped) stopped[p] = st | (tie << 1);
     }
     free_lists(&L);
     free(pts);
@@ -570,7 +589,8 @@ int oracle_backward(int64_t n, const double *xyz, const double *sh, int degree, 
             const double *gI = dL_dimage + 3 * p;
             double gT = dL_dtrans ? dL_dtrans[p] : 0.0;
             int st;
-            int64_t h, nh = composite_pixel(&L, pts, opacity, width, x, y, &pr, I, &T, &st, hits, cap);
+            int tie;
+            int64_t h, nh = composite_pixel(&L, pts, opacity, width, x, y, &pr, I, &T, &st, &tie, hits, cap);
             for (h = nh - 1; h >= 0; --h) {
                 const or_hit *e = &hits[h];
                 const or_point *q = &pts[e->i];

@@ -78,3 +78,38 @@ def test_surface300k_4x800_parity(dpr, headline, mode):
     info = plan.info()
     print(f"  pairs {info.pairs}; list positions ordered differently by float32 key and float64 Z: "
           f"{_near_tie_swaps(scene, cams)} of {4 * scene.n}", flush=True)
+
+
+def test_surface300k_paper_renderer_parity_outside_near_ties(dpr, headline):
+    """The paper-literal renderer (n = 15 splats per pixel, normalised Eq. 5)
+    at the benchmark workload.  Under the cap, a pixel whose 15th splat rests
+    on a predicate within a relative 1e-4 of alpha_min has two valid results a
+    whole splat apart (the oracle decides in FP64, the kernel in FP32: their
+    exponents differ by up to a few 1e-5 here); the oracle flags those pixels
+    (near_tie).  They must be rare, and every other pixel and the gradients of
+    the loss with weight 0 on them must match."""
+    import torch
+    scene, cams, pix, w = headline
+    params = dpr.RenderParams.paper()
+    op = oparams(params)
+    cams = cams[:2]
+    refs = [oracle.render(scene, cam, op) for cam in cams]
+    ties = [r.near_tie for r in refs]
+    n_ties = sum(int(t.sum()) for t in ties)
+    print(f"paper renderer at 300k x 800x800: {n_ties} near-tie pixels of {2 * 800 * 800}", flush=True)
+    assert n_ties <= 1e-3 * 2 * 800 * 800
+    plan = gpu_plan([scene], [(0, c) for c in cams], params)
+    for v, (r, t) in enumerate(zip(refs, ties)):
+        img, tr = to_np(plan.images[v]).astype(np.float64), to_np(plan.trans[v]).astype(np.float64)
+        ei = float(np.abs(img - r.image)[~t].max())
+        et = float(np.abs(tr - r.trans)[~t].max())
+        assert ei <= 1e-4 and et <= 1e-4, (v, ei, et)
+    wm = [np.where(t[..., None], np.float32(0.0), x).astype(np.float32) for x, t in zip(w[:2], ties)]
+    # view 1's weights are zero outside its 4096 sampled pixels already
+    out = plan.backward([torch.from_numpy(x).cuda() for x in wm], None)
+    torch.cuda.synchronize()
+    got = [to_np(t) for t in out[0]]
+    ref = oracle.backward(scene, cams, [x.astype(np.float64) for x in wm], None, params=op)
+    compare_grads(got[0], ref.xyz, "paper headline dxyz")
+    compare_grads(got[1], ref.sh, "paper headline dsh")
+    compare_grads(got[2], ref.opacity, "paper headline dopacity")

@@ -63,6 +63,24 @@ def test_cap_three_stacked_splats(n):
     assert r.ncontrib[8, 8] == min(n, 3)
 
 
+@pytest.mark.parametrize("rel,cap,flagged", [(3e-5, 2, True), (-3e-5, 2, True), (3e-4, 2, False),
+                                              (1.0, 2, False), (3e-5, 0, False)])
+def test_cap_near_tie_flag(rel, cap, flagged):
+    """Under a cap, a pixel whose candidate is decided within a relative 1e-4
+    of alpha_min is flagged (an evaluation in float32 may decide it the other
+    way and shift the pixel's n-th splat); at the shared centre alpha = o, so
+    the first splat's opacity sets that distance.  Without a cap no pixel is
+    flagged, and the flag changes nothing else."""
+    sc, _ = _three_stacked()
+    amin = oracle.Params().alpha_min
+    sc.opacity[0] = np.float32(amin * (1.0 + rel))
+    r = oracle.render(sc, _cam(), oracle.Params(max_splats=cap), mode="brute")
+    assert bool(r.near_tie[8, 8]) == flagged
+    assert r.stopped.max() <= 1 and r.near_tie.sum() <= (1 if flagged else 0)
+    ref = oracle.render(sc, _cam(), oracle.Params(max_splats=cap), mode="grid")
+    assert np.array_equal(ref.image, r.image) and np.array_equal(ref.near_tie, r.near_tie)
+
+
 def test_cap_above_candidate_count_is_uncapped_bitwise():
     sc = workloads.small_scene(41, 60, extent=0.2)
     rng = np.random.default_rng(41)
