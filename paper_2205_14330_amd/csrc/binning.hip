@@ -31,11 +31,12 @@ struct ChunkInfo {
     uint64_t row;        // first count entry of this chunk's row
 };
 
-__device__ __forceinline__ ChunkInfo chunk_info(const Tables &tb) {
-    const int v = find_segment(tb.chunk_start, tb.n_views, blockIdx.x);
+// Chunk of work index b (a block index, or a remapped one).
+__device__ __forceinline__ ChunkInfo chunk_info(const Tables &tb, uint32_t b) {
+    const int v = find_segment(tb.chunk_start, tb.n_views, b);
     const ViewDesc &vd = tb.views[v];
     ChunkInfo ci;
-    ci.c = blockIdx.x - vd.chunk_off;
+    ci.c = b - vd.chunk_off;
     ci.beg = vd.item_off + ci.c * (uint32_t)kChunkItems;
     ci.end = min(ci.beg + (uint32_t)kChunkItems, vd.item_off + (uint32_t)vd.n);
     ci.tiles_x = vd.tiles_x;
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(kCountThreads) void k_tile_count(Tables tb, const u
                                                                const SplatRec *rec, float lambda, uint32_t *cnt,
                                                                uint32_t band_tiles) {
     extern __shared__ uint32_t s_h[];
-    const ChunkInfo ci = chunk_info(tb);
+    const ChunkInfo ci = chunk_info(tb, blockIdx.x);
     for (uint32_t band = 0; band < ci.ntiles; band += band_tiles) {
         const uint32_t bend = min(band + band_tiles, ci.ntiles);
         for (uint32_t t = threadIdx.x; t < bend - band; t += kCountThreads) s_h[t] = 0;
@@ -282,6 +283,23 @@ hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, 
 //          clears the words it reads, so the next band starts clear.
 // Every (item, tile) decision is splat_touches_tile, as in the count, so each
 // segment has exactly the length the count reserved.
+// Block b runs on XCD b % 8 (round-robin dispatch).  The emission maps the
+// blocks so that each XCD takes stripes of kEmitStripe consecutive chunks: the
+// runs that consecutive chunks write into one tile list are adjacent, so most
+// 128-byte lines of the lists are completed inside one XCD's L2 before they
+// are written back (about half the written bytes of the identity map), while
+// the stripes of all XCDs still advance through the views together (one
+// contiguous range per XCD left the XCDs unevenly loaded).  A bijection of
+// [0, total): the blocks past the last whole group of 8 stripes map to
+// themselves.
+constexpr uint32_t kEmitStripe = 16;
+__device__ __forceinline__ uint32_t emit_chunk_of_block(uint32_t b, uint32_t total) {
+    const uint32_t full = total / (8u * kEmitStripe) * (8u * kEmitStripe);
+    if (b >= full) return b;
+    const uint32_t x = b & 7u, i = b >> 3;
+    return ((i / kEmitStripe) * 8u + x) * kEmitStripe + i % kEmitStripe;
+}
+
 constexpr int kEmitThreads = 512;
 constexpr int kEmitBand = 512;                 // tiles per band (at most)
 constexpr int kEmitWords = kChunkItems / 32;   // bitmap words per tile
@@ -299,7 +317,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uin
     __shared__ uint32_t s_g[kChunkItems];
     __shared__ uint2 s_rect[kChunkItems];
     if (tile_base[tb.total_tiles] > pair_cap) return;     // the pair lists do not fit the workspace
-    const ChunkInfo ci = chunk_info(tb);
+    const ChunkInfo ci = chunk_info(tb, emit_chunk_of_block(blockIdx.x, gridDim.x));
     const uint32_t tid = threadIdx.x;
     const uint32_t n = ci.end - ci.beg;
     if (blockIdx.x == 0 && tid < 4u) zero4[tid] = 0u;
