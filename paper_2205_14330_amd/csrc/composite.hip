@@ -6,8 +6,9 @@
 // tile's depth-ordered list on its own, in chunks of 128 positions: the splat
 // records are gathered into registers one chunk ahead; at a chunk's start the
 // records that may reach one of the wave's live pixels are kept in LDS, and
-// read back as broadcasts, each 32-byte record one record ahead of its use.
-// The blend is branch-free per pixel.  A pixel stops after the first blended
+// read back as broadcasts in unrolled groups of 16 (compile-time offsets),
+// each 32-byte record one record ahead of its use.  The blend is branch-free
+// per pixel.  A pixel stops after the first blended
 // splat that leaves T < t_min; a wave leaves the list once its 128 pixels have
 // stopped.
 //
@@ -115,13 +116,18 @@ __device__ __forceinline__ uint32_t pop_tile(uint32_t *queue) {
 // and keeps, in LDS and in list order, only the records that may reach a pixel
 // centre of that box (splat_reaches_box, conservative).  A skipped record
 // cannot blend a live pixel, and a pixel that has stopped blends nothing more,
-// so the result is the walk over every record.  The kept records are read back
-// from LDS one record ahead; a record that no pixel of the wave blends skips
+// so the result is the walk over every record.  The kept records are padded
+// with inert ones (w = -inf) to whole groups of kFwdGroup, and each group is
+// walked fully unrolled, so every LDS read of a record has a compile-time
+// offset and the walk has no per-record loop control; each record is read one
+// record ahead of its use.  A record that no pixel of the wave blends skips
 // the blend after its exponents.
 constexpr int kFwdPx = 2;                 // pixels per lane
 constexpr int kFwdThreads = 128;
 constexpr int kFwdChunk = 128;            // list positions per chunk
 constexpr int kFwdPerLane = kFwdChunk / 64;
+constexpr int kFwdGroup = 16;             // kept records per unrolled group
+static_assert(kFwdChunk % kFwdGroup == 0, "whole groups fit the staged chunk");
 
 // A pixel is live while T >= t_min: T only decreases, by T alpha <= T, and
 // the pixel stops right after the blend that takes it below t_min, so the
@@ -134,9 +140,10 @@ constexpr int kFwdPerLane = kFwdChunk / 64;
 // of each of the wave's pixels (a pixel that blends past that position keeps
 // its wave walking, so every checkpoint the backward reads is written); and
 // it appends the tile's backward work items (tile, s) for
-// s < ceil(max blend end / kBwdSeg).  Within a chunk a pixel keeps the LDS
-// offset of its last blended record, which is already in a VGPR; the list
-// position is formed once per chunk.
+// s < ceil(max blend end / kBwdSeg).  Within a group a pixel keeps the
+// group-relative index of its last blended record (a compile-time constant
+// of the unrolled walk), folded into the chunk's kept-record index after the
+// group; the list position is formed once per chunk.
 static_assert(kBwdSeg % kFwdChunk == 0, "backward segments are whole forward chunks");
 
 // The 8 bits of a 64-lane mask folded over its 8 groups of 8 lanes: bit c is
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
         const float cx0 = (float)(tx * kTile) + 0.5f, cy0 = (float)(ty * kTile + 8 * wave) + 0.5f;
         float ux[PX], uy[PX], T[PX], I0[PX], I1[PX], I2[PX];
         uint32_t nlast[PX], nblend[PX];
-        int last[PX];                     // LDS byte offset of the last blended record of this chunk, or -1
+        int last[PX];                     // index of the last blended kept record of this chunk, or -1
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
             const int px = x0 + p, py = y0;
@@ -256,6 +263,14 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             }
             // the chunk flag: may any kept record reach the alpha_max clamp
             const bool chunk_clamp = __ballot(near) != 0ull;
+            // inert records (w = -inf: no pixel passes e >= -lambda) up to a whole group
+            {
+                const int kp = (kept + kFwdGroup - 1) & ~(kFwdGroup - 1);
+                if (lane < kp - kept) {
+                    s_r0[wave][kept + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    s_r1[wave][kept + lane] = make_float4(-INFINITY, 0.f, 0.f, 0.f);
+                }
+            }
             // the next chunk's records, and the ids of the one after it
 #pragma unroll
             for (int q = 0; q < kPer; ++q) {
@@ -271,19 +286,17 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (int j0 = 0; j0 < kept; j0 += 16) {
+            for (int j0 = 0; j0 < kept; j0 += kFwdGroup) {
                 if (j0 > 0) {
                     bool any_live = false;
 #pragma unroll
                     for (int p = 0; p < PX; ++p) any_live = any_live || (T[p] >= t_min && (!COUNT || nblend[p] < cap));
                     if (__ballot(any_live) == 0ull) break;
                 }
-                const int jn = min(j0 + 16, kept);
-                // Kept record j sits at byte 16 j of the wave's s_r0 and s_r1; the
-                // offset is kept in a VGPR (see in_vgpr) and addresses both LDS
-                // reads.  The loop is unrolled by two over the register sets A and
-                // B: the next record is read while the current one is blended.
-                auto blend = [&](const float4 &r0, const float4 &r1, int ro) {
+                int lrel[PX];
+#pragma unroll
+                for (int p = 0; p < PX; ++p) lrel[p] = -1;
+                auto blend = [&](const float4 &r0, const float4 &r1, int jr) {
                     SplatRec s;
                     s.px = r0.x; s.py = r0.y; s.a = r0.z; s.b = r0.w;
                     s.w = r1.x;
@@ -302,7 +315,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
 #pragma unroll
                     for (int p = 0; p < PX; ++p) alpha[p] = hit[p] ? __builtin_amdgcn_exp2f(e[p]) : 0.f;
                     if (__builtin_expect(chunk_clamp, 0)) {
-                        const float am = in_vgpr(alpha_max);         // read here so the compares stay here
+                        const float am = in_vgpr(alpha_max);
 #pragma unroll
                         for (int p = 0; p < PX; ++p)
                             if (alpha[p] > am) alpha[p] = am;
@@ -314,31 +327,27 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
                         I1[p] = fmaf(Ta, s.cg, I1[p]);
                         I2[p] = fmaf(Ta, s.cb, I2[p]);
                         if (COUNT) nblend[p] += hit[p] ? 1u : 0u;
-                        T[p] = T[p] - Ta;                           // T (1 - alpha)
-                        if (STATE && hit[p]) last[p] = ro;
+                        T[p] = T[p] - Ta;
+                        if (STATE && hit[p]) lrel[p] = jr;
                     }
                 };
-                int roff = in_vgpr(16 * j0);
-                float4 a0 = *reinterpret_cast<const float4 *>(b0 + roff);
-                float4 a1 = *reinterpret_cast<const float4 *>(b1 + roff);
-                for (int j = j0; j < jn; j += 2) {
-                    const int ra = roff;
-                    roff = in_vgpr(roff + 16);                      // record j + 1 (at most index kChunk)
-                    const float4 c0 = *reinterpret_cast<const float4 *>(b0 + roff);
-                    const float4 c1 = *reinterpret_cast<const float4 *>(b1 + roff);
-                    blend(a0, a1, ra);
-                    if (j + 1 >= jn) break;
-                    const int rc = roff;
-                    roff = in_vgpr(roff + 16);                      // record j + 2 (at most index kChunk + 1)
-                    a0 = *reinterpret_cast<const float4 *>(b0 + roff);
-                    a1 = *reinterpret_cast<const float4 *>(b1 + roff);
-                    blend(c0, c1, rc);
+                const float4 *q0 = s_r0[wave] + j0, *q1 = s_r1[wave] + j0;
+                float4 a0 = q0[0], a1 = q1[0];
+#pragma unroll
+                for (int j = 0; j < kFwdGroup; ++j) {
+                    float4 c0 = a0, c1 = a1;
+                    if (j + 1 < kFwdGroup) { c0 = q0[j + 1]; c1 = q1[j + 1]; }
+                    blend(a0, a1, j);
+                    a0 = c0; a1 = c1;
                 }
+#pragma unroll
+                for (int p = 0; p < PX; ++p)
+                    if (STATE && lrel[p] >= 0) last[p] = j0 + lrel[p];
             }
 #pragma unroll
             for (int p = 0; p < PX; ++p)
                 if (STATE && last[p] >= 0) {
-                    nlast[p] = base - start + s_j[wave][last[p] / 16] + 1u;
+                    nlast[p] = base - start + s_j[wave][last[p]] + 1u;
                     last[p] = -1;
                 }
             // this chunk's kept records are read before the next chunk's are written
