@@ -164,9 +164,9 @@ __device__ __forceinline__ uint32_t fold_columns(uint64_t m) {
 template <bool PERSISTENT, bool COUNT, bool STATE>
 __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     constexpr int PX = kFwdPx, kThreads = kFwdThreads, kChunk = kFwdChunk, kPer = kFwdPerLane;
-    // per wave: the kept records of the current chunk, two padding records
-    // for the read-ahead, and the chunk position of each kept record
-    __shared__ float4 s_r0[2][kChunk + 2], s_r1[2][kChunk + 2];
+    // per wave: the kept records of the current chunk (padded to whole groups)
+    // and the chunk position of each kept record
+    __shared__ float4 s_r0[2][kChunk], s_r1[2][kChunk];
     __shared__ uint32_t s_j[2][kChunk];
     __shared__ uint32_t s_next, s_max[2], s_work;
     const float lambda = a.th.lambda;
@@ -452,10 +452,8 @@ __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t 
 __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     __shared__ float s_part[kSlots * kSlotStride];
     __shared__ uint32_t s_gid[kSlots];
-    // the current chunk: record j at s_rec[2j], s_rec[2j + 1]; two padding records
-    // in front, which the read-ahead of records -1 and -2 reaches
-    __shared__ float4 s_rec_store[2 * kCompLanes + 4];
-    float4 *const s_rec = s_rec_store + 4;
+    // the current chunk: record j at s_rec[2j], s_rec[2j + 1]
+    __shared__ float4 s_rec[2 * kCompLanes];
     const CompositeArgs &a = b.c;
     const float neg_lambda = in_vgpr(-a.th.lambda);
     const float alpha_max = a.th.alpha_max;
@@ -517,13 +515,13 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
             uint32_t nid;
             load_rec(a, cbeg + lane, lend, n0, n1, nid);
             // Pixel p may have blended the record at list position cbeg - start + j
-            // only if that position is below nl[p], i.e. iff 32 (j - 1) < lim[p] =
-            // 32 (nl[p] - (cbeg - start) - 1) for the current chunk: the test takes
-            // the byte offset of record j - 1, which the walk already holds for its
-            // read-ahead.  lim grows by 32 * 64 per chunk back.
-            int lim[kQuad];
+            // only if that position is below nl[p], i.e. iff j < lim[p] =
+            // nl[p] - (cbeg - start) for the current chunk; lim grows by 64 per
+            // chunk back.  Within a group of 16 records from g0 the test is
+            // jj < limg[p] = lim[p] - g0 with jj = j - g0 a compile-time constant.
+            int lim[kQuad], limg[kQuad];
 #pragma unroll
-            for (int p = 0; p < kQuad; ++p) lim[p] = 32 * ((int)nl[p] - (int)(cbeg - c.start) - 1);
+            for (int p = 0; p < kQuad; ++p) lim[p] = (int)nl[p] - (int)(cbeg - c.start);
             while (true) {
                 const uint32_t id = nid;
                 __syncthreads();                 // the previous chunk's broadcasts are done
@@ -533,8 +531,8 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 const bool more = cbeg > sbeg;
                 if (more) load_rec(a, cbeg - kCompLanes + lane, lend, n0, n1, nid);
                 const int cnt = (int)min((uint32_t)kCompLanes, lend - cbeg);
-                // one (pixel, splat) record of the walk: record j, whose predecessor sits at byte offset ro
-                auto splat = [&](const float4 &f0, const float4 &f1, int ro, int j) {
+                // one (pixel, splat) record of the walk: record j = g0 + jj of the chunk
+                auto splat = [&](const float4 &f0, const float4 &f1, int jj, int j) {
                     SplatRec s;
                     s.px = f0.x; s.py = f0.y; s.a = f0.z; s.b = f0.w;
                     s.w = f1.x;
@@ -547,7 +545,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         float dx, dy;
                         e[p] = splat_exponent(s, ux[p], uy[p], dx, dy);
                         if (p == 0) { dx0 = dx; dy0 = dy; }
-                        hit[p] = (ro < lim[p]) & (e[p] >= neg_lambda);
+                        hit[p] = (jj < limg[p]) & (e[p] >= neg_lambda);
                         any = any || hit[p];
                     }
                     // a splat that no pixel of the tile blended changes nothing below
@@ -635,29 +633,26 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         nslots = 0;
                     }
                 };
-                // Record j sits at byte 32 j of s_rec; the offset is kept in a VGPR (see
-                // in_vgpr): it addresses the LDS reads and takes part in the position
-                // test without SGPR operands.  The walk is unrolled by two over the
-                // register sets A and B: the record before the current one is read while
-                // the current one is processed, so the LDS latency overlaps the
-                // arithmetic.
-                const char *rb = reinterpret_cast<const char *>(s_rec);
-                int roff = in_vgpr(32 * (cnt - 1));
-                float4 a0 = *reinterpret_cast<const float4 *>(rb + roff);
-                float4 a1 = *reinterpret_cast<const float4 *>(rb + roff + 16);
-                for (int j = cnt - 1; j >= 0; j -= 2) {
-                    roff = in_vgpr(roff - 32);                  // record j - 1 (at least index -1)
-                    const float4 c0 = *reinterpret_cast<const float4 *>(rb + roff);
-                    const float4 c1 = *reinterpret_cast<const float4 *>(rb + roff + 16);
-                    splat(a0, a1, roff, j);
-                    if (j == 0) break;
-                    roff = in_vgpr(roff - 32);                  // record j - 2 (at least index -2)
-                    a0 = *reinterpret_cast<const float4 *>(rb + roff);
-                    a1 = *reinterpret_cast<const float4 *>(rb + roff + 16);
-                    splat(c0, c1, roff, j - 1);
+                // The chunk is walked back to front in groups of 16 records, each
+                // fully unrolled so that every LDS read has a compile-time offset;
+                // record j - 1 is read while record j is processed.  The records
+                // past cnt in the top group are the inert ones of the chunk load.
+                const float4 *rb = s_rec;
+                for (int g0 = ((cnt - 1) / 16) * 16; g0 >= 0; g0 -= 16) {
+#pragma unroll
+                    for (int p = 0; p < kQuad; ++p) limg[p] = lim[p] - g0;
+                    const float4 *gb = rb + 2 * g0;
+                    float4 a0 = gb[2 * 15], a1 = gb[2 * 15 + 1];
+#pragma unroll
+                    for (int jj = 15; jj >= 0; --jj) {
+                        float4 c0 = a0, c1 = a1;
+                        if (jj > 0) { c0 = gb[2 * (jj - 1)]; c1 = gb[2 * (jj - 1) + 1]; }
+                        splat(a0, a1, jj, g0 + jj);
+                        a0 = c0; a1 = c1;
+                    }
                 }
 #pragma unroll
-                for (int p = 0; p < kQuad; ++p) lim[p] += 32 * kCompLanes;   // the previous chunk
+                for (int p = 0; p < kQuad; ++p) lim[p] += kCompLanes;   // the previous chunk
                 if (!more) break;
                 cbeg -= kCompLanes;
             }
