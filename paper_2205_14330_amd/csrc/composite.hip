@@ -23,12 +23,11 @@
 // colour blended behind (B = I_final - I_checkpoint at a segment end), and
 // folding each (pixel, splat) contribution into 7 per-lane partial sums.  A
 // chunk of 64 records is gathered one per lane, written to LDS and read back
-// as broadcasts, one record ahead of its use.  T is recovered with one
-// reciprocal per lane and splat, of the product of the quad's four (1 - alpha).
-// The sums are reduced across each pair of lanes with one quad-permute
-// swizzle (LDS pipe, so the VALU only adds), the 32 pair sums of up to 7
-// splats are staged in LDS, and each flush completes 49 sums and adds them to
-// the per-item gradient records with one 64-lane float atomic.
+// as broadcasts, one record ahead of its use, in unrolled groups of 16.  T is
+// recovered with one reciprocal per lane and splat, of the product of the
+// quad's four (1 - alpha).  Each lane stages its 7 sums of up to 4 splats in
+// LDS, and each flush completes the 28 sums over the 64 lanes and adds them to
+// the per-item gradient records with one float atomic each.
 #include "dpr_internal.h"
 
 #include <cstring>
@@ -399,50 +398,46 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
 // ---------------------------------------------------------------------------
 // The value of the lane given by a quad-permute pattern.  ds_swizzle in quad
 // mode (offset bit 15 set; two bits per destination lane of the quad) runs on
-// the LDS pipe, so only the adds of a reduction issue on the VALU; a
-// DPP-modified add costs about twice a plain one there.
+// the LDS pipe; a DPP-modified add costs about twice a plain one on the VALU.
 template <int PATTERN>
 __device__ __forceinline__ float swizzle(float v) {
     return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x8000 | PATTERN));
 }
 
-// Sums over each pair of consecutive lanes (valid in both lanes) of N values;
-// the swizzles are issued together so that one wait covers them.
-template <int N>
-__device__ __forceinline__ void pair_sums(float (&v)[N]) {
-    float t[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) t[i] = swizzle<0xB1>(v[i]);     // quad_perm [1,0,3,2]
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = v[i] + t[i];
-}
-
-// Staging of per-splat partial sums: slot k holds, for one splat, the 32
-// lane-pair sums of each of the 7 quantities at [k][pair][column].  The pair
-// stride of 7 words (odd) keeps the 32 writers of one column on distinct
-// banks; the slot stride of 264 words (8 mod 64) keeps the 49 flush readers
-// (7 slots x 7 columns) on distinct banks.  7 slots keep the kernel's LDS
-// within 16 waves per CU.
-constexpr int kSlots = 7;
+// Staging of per-splat partial sums: slot k holds, for one splat, each lane's
+// 7 sums (over its 4 pixels) column by column, the 64 lanes of a column in
+// consecutive words (one conflict-free store per column), columns
+// kColStride = 68 words apart.  No cross-lane operation runs per splat: a
+// lane-pair swizzle per sum cost more (7 LDS-pipe operations and a wait per
+// splat) than the longer flush sums.  4 slots keep the kernel's LDS within
+// 16 waves per CU.
+constexpr int kSlots = 4;
 constexpr int kCols = 7;
-constexpr int kPairStride = kCols;
-constexpr int kSlotStride = 32 * kPairStride + 40;
-static_assert(kSlotStride % 64 == 8, "flush readers on distinct banks");
+constexpr int kColStride = 68;
+constexpr int kSlotStride = kCols * kColStride;
 
-// Completes the sums of the first nslots slots (lane L handles slot L/8,
-// column L%8 < 7) and adds them to the gradient records.  Columns 0-2 are
-// quantities 0-2 and columns 3-6 quantities 4-7 (quantity 3 is unused).
+// Completes the sums of the first nslots slots and adds them to the gradient
+// records: lane L sums half h = L & 1 (32 lanes' values, eight 16-byte reads)
+// of column c = (L >> 1) & 7 < 7 of slot L >> 4, one swizzle adds the other
+// half, and the lane with h = 0 issues the atomic.  Columns 0-2 are quantities
+// 0-2 and columns 3-6 quantities 4-7 (quantity 3 is unused).
 __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t *s_gid, int nslots, float *grad,
                                             int lane) {
-    const int c = lane & 7;
-    const int k = lane >> 3;
-    if (k < nslots && c < kCols) {
-        const float *src = s_part + k * kSlotStride + c;
-        float sum = src[0];
+    const int k = lane >> 4, c = (lane >> 1) & 7, h = lane & 1;
+    const bool act = k < nslots && c < kCols;
+    float sum = 0.f;
+    if (act) {
+        const float4 *src = reinterpret_cast<const float4 *>(s_part + k * kSlotStride + c * kColStride + 32 * h);
+        float4 t = src[0];
 #pragma unroll
-        for (int o = 1; o < 32; ++o) sum += src[o * kPairStride];
-        atomicAdd(grad + 8 * (size_t)s_gid[k] + (c < 3 ? c : c + 1), sum);
+        for (int o = 1; o < 8; ++o) {
+            const float4 u = src[o];
+            t.x += u.x; t.y += u.y; t.z += u.z; t.w += u.w;
+        }
+        sum = (t.x + t.y) + (t.z + t.w);
     }
+    sum += swizzle<0xB1>(sum);
+    if (act && h == 0) atomicAdd(grad + 8 * (size_t)s_gid[k] + (c < 3 ? c : c + 1), sum);
 }
 
 // Persistent: each wave pops (tile, segment) work items until the list is
@@ -450,7 +445,7 @@ __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t 
 // pixel still live after the segment starts from the checkpoint there, any
 // other pixel from its final state.
 __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
-    __shared__ float s_part[kSlots * kSlotStride];
+    __shared__ __align__(16) float s_part[kSlots * kSlotStride];
     __shared__ uint32_t s_gid[kSlots];
     // the current chunk: record j at s_rec[2j], s_rec[2j + 1]
     __shared__ float4 s_rec[2 * kCompLanes];
@@ -459,7 +454,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     const float alpha_max = a.th.alpha_max;
     const float w_noclamp = in_vgpr(no_clamp_w(alpha_max));
     const int lane = threadIdx.x;
-    float *const my_part = s_part + (lane >> 1) * kPairStride;
+    float *const my_part = s_part + lane;
     const uint32_t nwork = *b.work_count;
 
     for (uint32_t w = blockIdx.x; w < nwork;) {
@@ -617,13 +612,11 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         v6 = fmaf(Ta[p], gI1[p], v6);
                         v7 = fmaf(Ta[p], gI2[p], v7);
                     }
-                    {   // the 2 lanes of a pair hold bitwise-equal sums and store them
-                        // to the same words, which keeps the reduction unconditional
-                        float v[kCols] = {v0, v1, v2, v4, v5, v6, v7};
-                        pair_sums(v);
+                    {
+                        const float v[kCols] = {v0, v1, v2, v4, v5, v6, v7};
                         float *dst = my_part + nslots * kSlotStride;
 #pragma unroll
-                        for (int i = 0; i < kCols; ++i) dst[i] = v[i];
+                        for (int i = 0; i < kCols; ++i) dst[i * kColStride] = v[i];
                     }
                     if (lane == j) s_gid[nslots] = id;
                     if (++nslots == kSlots) {
