@@ -418,11 +418,14 @@ constexpr int kSlotStride = kCols * kColStride;
 
 // Completes the sums of the first nslots slots and adds them to the gradient
 // records: lane L sums half h = L & 1 (32 lanes' values, eight 16-byte reads)
-// of column c = (L >> 1) & 7 < 7 of slot L >> 4, one swizzle adds the other
+// of column c = (L >> 1) & 7 < 7 of slot k = L >> 4, one swizzle adds the other
 // half, and the lane with h = 0 issues the atomic.  Columns 0-2 are quantities
-// 0-2 and columns 3-6 quantities 4-7 (quantity 3 is unused).
-__device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t *s_gid, int nslots, float *grad,
-                                            int lane) {
+// 0-2 and columns 3-6 quantities 4-7 (quantity 3 is unused).  Slot k's item id
+// is s_ids[(slotj >> 7k) & 127]: the wave-uniform slotj holds, per slot, the
+// parity of the chunk its splat came from (which half of the double-buffered
+// s_ids holds that chunk's ids) and the splat's index in the chunk.
+__device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t *s_ids, uint32_t slotj, int nslots,
+                                            float *grad, int lane) {
     const int k = lane >> 4, c = (lane >> 1) & 7, h = lane & 1;
     const bool act = k < nslots && c < kCols;
     float sum = 0.f;
@@ -437,7 +440,10 @@ __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t 
         sum = (t.x + t.y) + (t.z + t.w);
     }
     sum += swizzle<0xB1>(sum);
-    if (act && h == 0) atomicAdd(grad + 8 * (size_t)s_gid[k] + (c < 3 ? c : c + 1), sum);
+    if (act && h == 0) {
+        const uint32_t gid = s_ids[(slotj >> (7 * k)) & 127u];
+        atomicAdd(grad + 8 * (size_t)gid + (c < 3 ? c : c + 1), sum);
+    }
 }
 
 // Persistent: each wave pops (tile, segment) work items until the list is
@@ -446,7 +452,7 @@ __device__ __forceinline__ void flush_slots(const float *s_part, const uint32_t 
 // other pixel from its final state.
 __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
     __shared__ __align__(16) float s_part[kSlots * kSlotStride];
-    __shared__ uint32_t s_gid[kSlots];
+    __shared__ uint32_t s_ids[2 * kCompLanes];
     // the current chunk: record j at s_rec[2j], s_rec[2j + 1]
     __shared__ float4 s_rec[2 * kCompLanes];
     const CompositeArgs &a = b.c;
@@ -502,6 +508,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
 
         // chunks back to front: [cbeg, cbeg + 64) aligned to the segment start
         int nslots = 0;
+        uint32_t slotj = 0, slot_par = 0;    // slot k: bits [7k, 7k + 7) = chunk parity * 64 + record
         if (maxn > seg_beg) {
             const uint32_t sbeg = c.start + seg_beg;
             uint32_t cbeg = sbeg + ((maxn - seg_beg - 1) / kCompLanes) * kCompLanes;
@@ -517,11 +524,17 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
             int lim[kQuad], limg[kQuad];
 #pragma unroll
             for (int p = 0; p < kQuad; ++p) lim[p] = (int)nl[p] - (int)(cbeg - c.start);
+            int par = 0;
             while (true) {
-                const uint32_t id = nid;
+                if (slot_par & (1u << par)) {    // pending slots name ids about to be overwritten
+                    __syncthreads();
+                    flush_slots(s_part, s_ids, slotj, nslots, b.grad, lane);
+                    nslots = 0; slotj = 0; slot_par = 0;
+                }
                 __syncthreads();                 // the previous chunk's broadcasts are done
                 s_rec[2 * lane] = n0;
                 s_rec[2 * lane + 1] = n1;
+                s_ids[par * kCompLanes + lane] = nid;
                 __syncthreads();
                 const bool more = cbeg > sbeg;
                 if (more) load_rec(a, cbeg - kCompLanes + lane, lend, n0, n1, nid);
@@ -618,12 +631,13 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
 #pragma unroll
                         for (int i = 0; i < kCols; ++i) dst[i * kColStride] = v[i];
                     }
-                    if (lane == j) s_gid[nslots] = id;
+                    slotj |= (uint32_t)(par * kCompLanes + j) << (7 * nslots);
+                    slot_par |= 1u << par;
                     if (++nslots == kSlots) {
                         __syncthreads();     // staged sums are written before other lanes read them
-                        flush_slots(s_part, s_gid, kSlots, b.grad, lane);
+                        flush_slots(s_part, s_ids, slotj, kSlots, b.grad, lane);
                         __syncthreads();     // and read before the slots are written again
-                        nslots = 0;
+                        nslots = 0; slotj = 0; slot_par = 0;
                     }
                 };
                 // The chunk is walked back to front in groups of 16 records, each
@@ -648,11 +662,12 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 for (int p = 0; p < kQuad; ++p) lim[p] += kCompLanes;   // the previous chunk
                 if (!more) break;
                 cbeg -= kCompLanes;
+                par ^= 1;
             }
         }
         if (nslots > 0) {
             __syncthreads();
-            flush_slots(s_part, s_gid, nslots, b.grad, lane);
+            flush_slots(s_part, s_ids, slotj, nslots, b.grad, lane);
             __syncthreads();
         }
         w = pop_tile(b.queue);
