@@ -296,3 +296,46 @@ def test_backward_rejects_another_forward_workspace(dpr, mode):
     out = plan.backward(gi, gt)
     torch.cuda.synchronize()
     _check_scene(dpr, sc, cams, params, gI, gT, [to_np(t) for t in out[0]], f"{mode} after refusal")
+
+
+def _sparse_hit_scene():
+    """One 16x16 tile whose list is long but whose walked range holds few blended
+    records: ten wide opaque splats in front (centred at pixel (12, 12)) stop
+    every pixel that the 3900 narrow splats behind them reach, and 26 faint
+    narrow splats at the corner pixel, one every 150 list positions, keep the
+    corner pixels live deep into the list.  The backward then walks thousands
+    of positions in which most 64-record chunks hold no blended record, so a
+    segment's staged sums span several chunks (and are flushed before the item
+    ids of a chunk two back are overwritten)."""
+    W = H = 32
+    f = 32.0
+    cam = Camera(np.eye(3), np.zeros(3), f, f, W / 2.0, H / 2.0, W, H)
+    rng = np.random.default_rng(7)
+    pts = []          # (u, v, z, sigma_px, opacity)
+    for k in range(10):
+        pts.append((12.0, 12.0, 1.90 + 0.001 * k, 3.3, 0.99))
+    for k in range(3900):
+        pts.append((12.0 + rng.uniform(-0.5, 0.5), 12.0 + rng.uniform(-0.5, 0.5), 2.0 + 0.0005 * k, 0.5, 0.5))
+    for j in range(26):
+        pts.append((0.5, 0.5, 2.0 + 0.0005 * (150 * j + 75) + 0.0001, 0.6, 0.7))
+    p = np.array(pts, np.float64)
+    u, v, z, s, o = p.T
+    xyz = np.stack([(u - W / 2.0) * z / f, (v - H / 2.0) * z / f, z], 1).astype(np.float32)
+    sc = Scene(xyz, (0.3 * rng.standard_normal((len(p), 1, 3))).astype(np.float32), o.astype(np.float32),
+               (s * z / f).astype(np.float32))
+    return sc, cam
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_sparse_hits_over_long_lists(dpr, mode):
+    sc, cam = _sparse_hit_scene()
+    params = dpr.RenderParams(bwd_mode=mode)
+    ref_img = oracle.render(sc, cam, oparams(params))
+    # the scene is what it claims: the corner pixel blends its faint splats and
+    # stops deep in the list, the centre stops within the wide front splats
+    assert ref_img.stopped[0, 0] and 5 <= ref_img.ncontrib[0, 0] <= 26
+    assert ref_img.stopped[12, 12] and ref_img.ncontrib[12, 12] <= 10
+    gI, gT = _weights(11, [cam])
+    plan, got = _gpu_grads(dpr, [sc], [(0, cam)], params, gI, gT)
+    compare_images(to_np(plan.images[0]), to_np(plan.trans[0]), ref_img, label=f"sparse {mode}")
+    _check_scene(dpr, sc, [cam], params, gI, gT, got[0], f"sparse {mode}")
