@@ -230,11 +230,11 @@ struct StageScope {
     int stage;
     hipStream_t st;
     StageScope(dpr_plan *p_, int s, hipStream_t st_) : p(p_), stage(s), st(st_) {
-        if ((p->timed >> stage) & 1u) hipEventRecord(p->ev.a[stage], st);
+        if ((p->timed >> stage) & 1u) (void)hipEventRecord(p->ev.a[stage], st);   // timing only: not fatal
     }
     ~StageScope() {
         if ((p->timed >> stage) & 1u) {
-            hipEventRecord(p->ev.b[stage], st);
+            (void)hipEventRecord(p->ev.b[stage], st);
             p->ev.ran[stage] = true;
         }
     }

@@ -176,7 +176,6 @@ __global__ __launch_bounds__(kFwdThreads) void k_composite(CompositeArgs a) {
     const uint32_t cap = in_vgpr(a.th.max_splats > 0 ? a.th.max_splats : 0xFFFFFFFFu);
     if (a.tile_base[a.total_tiles] > a.pair_cap) return;   // the pair lists do not fit the workspace
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const char *b0 = reinterpret_cast<const char *>(s_r0[wave]), *b1 = reinterpret_cast<const char *>(s_r1[wave]);
     // block (or popped) index -> tile: through the longest-first order when there is one
     for (uint32_t idx = blockIdx.x; idx < a.total_tiles;) {
         const uint32_t tile = a.tile_order ? a.tile_order[idx] : (PERSISTENT ? idx : xcd_remap(idx, a.total_tiles));
