@@ -176,7 +176,10 @@ struct KnnGrid {
 };
 
 // One thread per query (queries in cell order).  best[] holds the K smallest
-// (distance bits << 32 | index) keys in ascending order.
+// (distance bits << 32 | index) keys in ascending order.  KMAX (8, 16 or 32,
+// at least K) sizes the list, so that an insertion takes KMAX predicated
+// steps rather than always 32.
+template <int KMAX>
 __global__ __launch_bounds__(kHyThreads) void k_knn(KnnGrid g) {
     const uint32_t t = blockIdx.x * kHyThreads + threadIdx.x;
     if (t >= g.m) return;
@@ -191,9 +194,9 @@ __global__ __launch_bounds__(kHyThreads) void k_knn(KnnGrid g) {
         if (ext > 0.f) hmin = fminf(hmin, ext / (float)G);
     }
     const float *pp = g.xyz + 3 * (size_t)p;
-    uint64_t best[kKnnMax];
+    uint64_t best[KMAX];
 #pragma unroll
-    for (int k = 0; k < kKnnMax; ++k) best[k] = ~0ull;
+    for (int k = 0; k < KMAX; ++k) best[k] = ~0ull;
     const int K = g.keff;
     uint64_t worst = ~0ull;           // best[K - 1]
     int found = 0;
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(kHyThreads) void k_knn(KnnGrid g) {
                         if (x64 >= worst) continue;
                         // insert into the sorted prefix: keep the smaller, carry the larger on
 #pragma unroll
-                        for (int k = 0; k < kKnnMax; ++k) {
+                        for (int k = 0; k < KMAX; ++k) {
                             if (k < K) {
                                 const uint64_t lo = best[k] < x64 ? best[k] : x64;
                                 x64 = best[k] < x64 ? x64 : best[k];
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(kHyThreads) void k_knn(KnnGrid g) {
                             }
                         }
 #pragma unroll
-                        for (int k = 0; k < kKnnMax; ++k)
+                        for (int k = 0; k < KMAX; ++k)
                             if (k == K - 1) worst = best[k];
                     }
                 }
@@ -381,7 +384,9 @@ hipError_t launch_knn(const float *xyz, uint32_t m, int K, int32_t *idx, float *
     g.keff = (int)std::min<uint64_t>((uint64_t)K, (uint64_t)m - 1);
     g.idx = idx;
     g.d2 = d2;
-    hipLaunchKernelGGL(k_knn, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, g);
+    if (g.K <= 8) hipLaunchKernelGGL(k_knn<8>, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, g);
+    else if (g.K <= 16) hipLaunchKernelGGL(k_knn<16>, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, g);
+    else hipLaunchKernelGGL(k_knn<kKnnMax>, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, g);
     return hipGetLastError();
 }
 
