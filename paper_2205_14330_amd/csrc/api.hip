@@ -63,7 +63,7 @@ struct Sizes {
 };
 
 struct PlanLayout {
-    Region views, scenes, u32tab, rec, keys, vals, keys_alt, vals_alt, rect, hist, part, cnt, segs, tile_total,
+    Region views, scenes, u32tab, rec, keys, vals, keys_alt, vals_alt, rect, bin, hist, part, cnt, segs, tile_total,
         tile_base, tile_order, bucket_cnt, block_sum;
     uint64_t total = 0;
 };
@@ -81,6 +81,7 @@ PlanLayout plan_layout(const Sizes &s) {
     p.keys_alt = L.add(4 * s.items);
     p.vals_alt = L.add(4 * s.items);
     p.rect = L.add(8 * s.items);
+    p.bin = L.add(sizeof(BinRec) * s.items);
     const uint64_t nh = 256ull * s.sort_blocks;
     p.hist = L.add(4 * (nh + 1));
     const uint64_t np = std::max(scan_partials(nh), scan_partials(s.tiles)) + 2;
@@ -656,7 +657,8 @@ int plan_forward_impl(const dpr_scene *scenes, int32_t n_scenes, const dpr_view 
     }
     {
         StageScope sc_(p, DPR_STAGE_TILE_COUNT, st);
-        STAGE_TRY(launch_tile_count(tb, (uint32_t)s.chunks, vals, rect, rec, p->th.lambda, cnt, st));
+        STAGE_TRY(launch_tile_count(tb, (uint32_t)s.chunks, vals, rect, rec, p->th.lambda, cnt,
+                                    reinterpret_cast<BinRec *>(w + lay.bin.off), st));
     }
     {
         StageScope sc_(p, DPR_STAGE_TILE_SCAN, st);
@@ -730,9 +732,7 @@ int launch_forward(dpr_plan *p, void *ws, uint64_t layout_pairs, uint32_t pair_c
     const PlanLayout &lay = p->lay;
     {
         StageScope sc_(p, DPR_STAGE_EMIT, st);
-        HIP_TRY(launch_tile_emit(tb, (uint32_t)p->sz.chunks, reinterpret_cast<const uint32_t *>(p->pws + lay.vals.off),
-                                 reinterpret_cast<const uint2 *>(p->pws + lay.rect.off),
-                                 reinterpret_cast<const SplatRec *>(p->pws + lay.rec.off), p->th.lambda,
+        HIP_TRY(launch_tile_emit(tb, (uint32_t)p->sz.chunks, reinterpret_cast<const BinRec *>(p->pws + lay.bin.off),
                                  reinterpret_cast<const uint32_t *>(p->pws + lay.cnt.off),
                                  reinterpret_cast<const uint32_t *>(p->pws + lay.tile_base.off),
                                  reinterpret_cast<uint32_t *>(w + f.pairs.off),

@@ -46,28 +46,64 @@ __device__ __forceinline__ ChunkInfo chunk_info(const Tables &tb, uint32_t b) {
     return ci;
 }
 
+constexpr int kCountPer = kChunkItems / kCountThreads;    // items per count thread
+static_assert(kChunkItems % kCountThreads == 0, "whole items per count thread");
+
+// The thread's items are gathered once (ids, rectangles, then the splat
+// records of the non-empty ones, each step's loads all in flight together),
+// their binning records written in depth order, then binned band by band
+// from registers.
 __global__ __launch_bounds__(kCountThreads) void k_tile_count(Tables tb, const uint32_t *order, const uint2 *rect,
                                                                const SplatRec *rec, float lambda, uint32_t *cnt,
-                                                               uint32_t band_tiles) {
+                                                               BinRec *bin, uint32_t band_tiles) {
     extern __shared__ uint32_t s_h[];
     const ChunkInfo ci = chunk_info(tb, blockIdx.x);
+    uint32_t g[kCountPer];
+    uint2 rc[kCountPer];
+    float4 r0[kCountPer];
+    float thr[kCountPer];
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const uint32_t s = ci.beg + threadIdx.x + (uint32_t)k * kCountThreads;
+        g[k] = s < ci.end ? order[s] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const uint32_t s = ci.beg + threadIdx.x + (uint32_t)k * kCountThreads;
+        rc[k] = s < ci.end ? rect[g[k]] : make_uint2(0u, 0u);     // outside the chunk: an empty rectangle
+    }
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        r0[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        thr[k] = 0.f;
+        if ((rc[k].y & 0xFFFFu) > (rc[k].x & 0xFFFFu) && (rc[k].y >> 16) > (rc[k].x >> 16)) {
+            r0[k] = reinterpret_cast<const float4 *>(rec + g[k])[0];
+            thr[k] = reinterpret_cast<const float4 *>(rec + g[k])[1].x + lambda;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const uint32_t s = ci.beg + threadIdx.x + (uint32_t)k * kCountThreads;
+        if (s < ci.end) {
+            uint4 *dst = reinterpret_cast<uint4 *>(bin + s);
+            dst[0] = make_uint4(rc[k].x, rc[k].y, g[k], __float_as_uint(thr[k]));
+            dst[1] = make_uint4(__float_as_uint(r0[k].x), __float_as_uint(r0[k].y), __float_as_uint(r0[k].z),
+                                __float_as_uint(r0[k].w));
+        }
+    }
     for (uint32_t band = 0; band < ci.ntiles; band += band_tiles) {
         const uint32_t bend = min(band + band_tiles, ci.ntiles);
         for (uint32_t t = threadIdx.x; t < bend - band; t += kCountThreads) s_h[t] = 0;
         __syncthreads();
-        for (uint32_t s = ci.beg + threadIdx.x; s < ci.end; s += kCountThreads) {
-            const uint32_t g = order[s];
-            const uint2 rc = rect[g];
-            const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
-            if (x1 <= x0 || y1 <= y0) continue;
-            const float4 r0 = reinterpret_cast<const float4 *>(rec + g)[0];
-            const float thr = reinterpret_cast<const float4 *>(rec + g)[1].x + lambda;
+#pragma unroll
+        for (int k = 0; k < kCountPer; ++k) {
+            const uint32_t x0 = rc[k].x & 0xFFFFu, y0 = rc[k].x >> 16, x1 = rc[k].y & 0xFFFFu, y1 = rc[k].y >> 16;
             for (uint32_t ty = y0; ty < y1; ++ty) {
                 const uint32_t rowb = ty * (uint32_t)ci.tiles_x;
                 if (rowb + x1 <= band || rowb + x0 >= bend) continue;
                 for (uint32_t tx = x0; tx < x1; ++tx) {
                     const uint32_t t = rowb + tx;
-                    if (t >= band && t < bend && splat_touches_tile(r0.x, r0.y, r0.z, r0.w, thr, tx, ty))
+                    if (t >= band && t < bend && splat_touches_tile(r0[k].x, r0[k].y, r0[k].z, r0[k].w, thr[k], tx, ty))
                         atomicAdd(&s_h[t - band], 1u);
                 }
             }
@@ -305,9 +341,9 @@ constexpr int kEmitBand = 512;                 // tiles per band (at most)
 constexpr int kEmitWords = kChunkItems / 32;   // bitmap words per tile
 constexpr int kEmitTilesPerThread = (kEmitBand + kEmitThreads - 1) / kEmitThreads;
 static_assert(kChunkItems % 32 == 0 && kEmitWords <= 32, "whole bitmap words, one summary word");
+static_assert(kEmitThreads == kChunkItems, "one item per emission thread");
 
-__global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uint32_t *order, const uint2 *rect,
-                                                             const SplatRec *rec, float lambda, const uint32_t *pre,
+__global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const BinRec *bin, const uint32_t *pre,
                                                              const uint32_t *tile_base, uint32_t *pairs,
                                                              uint32_t *zero4, uint32_t pair_cap) {
     // word w of band tile b at s_bits[w * kEmitBand + b]: the write phase's
@@ -315,17 +351,23 @@ __global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uin
     __shared__ uint32_t s_bits[kEmitWords * kEmitBand];
     __shared__ uint32_t s_sum[kEmitBand];
     __shared__ uint32_t s_g[kChunkItems];
-    __shared__ uint2 s_rect[kChunkItems];
     if (tile_base[tb.total_tiles] > pair_cap) return;     // the pair lists do not fit the workspace
     const ChunkInfo ci = chunk_info(tb, emit_chunk_of_block(blockIdx.x, gridDim.x));
     const uint32_t tid = threadIdx.x;
     const uint32_t n = ci.end - ci.beg;
     if (blockIdx.x == 0 && tid < 4u) zero4[tid] = 0u;
-    for (uint32_t i = tid; i < n; i += kEmitThreads) {
-        const uint32_t g = order[ci.beg + i];
-        s_g[i] = g;
-        s_rect[i] = rect[g];
+    // thread i holds item i of the chunk (its binning record, read contiguously)
+    const uint32_t i = tid;
+    uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb = ra;
+    if (i < n) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(bin + ci.beg + i);
+        ra = src[0];
+        rb = src[1];
+        s_g[i] = ra.z;
     }
+    const float thr = __uint_as_float(ra.w);
+    const float spx = __uint_as_float(rb.x), spy = __uint_as_float(rb.y);
+    const float sa = __uint_as_float(rb.z), sb = __uint_as_float(rb.w);
     {
         // the bitmaps start clear; the write phase clears the words it reads
         uint4 *const z = reinterpret_cast<uint4 *>(s_bits);
@@ -351,20 +393,16 @@ __global__ __launch_bounds__(kEmitThreads) void k_tile_emit(Tables tb, const uin
                 }
             }
             __syncthreads();              // the bitmaps are clear; the staged items are published
-            for (uint32_t i = tid; i < n; i += kEmitThreads) {
-                const uint2 rc = s_rect[i];
-                const uint32_t x0 = max(rc.x & 0xFFFFu, c0), y0 = max(rc.x >> 16, r0);
-                const uint32_t x1 = min(rc.y & 0xFFFFu, c1), y1 = min(rc.y >> 16, r1);
-                if (x1 <= x0 || y1 <= y0) continue;
-                const float4 *rr_ = reinterpret_cast<const float4 *>(rec + s_g[i]);
-                const float4 sh = rr_[0];
-                const float thr = rr_[1].x + lambda;
+            {
+                // an item outside the chunk has an empty rectangle
+                const uint32_t x0 = max(ra.x & 0xFFFFu, c0), y0 = max(ra.x >> 16, r0);
+                const uint32_t x1 = min(ra.y & 0xFFFFu, c1), y1 = min(ra.y >> 16, r1);
                 const uint32_t bit = 1u << (i & 31u), word = i >> 5, wbit = 1u << word;
                 uint32_t *const bits = s_bits + word * (uint32_t)kEmitBand;
                 for (uint32_t ty = y0; ty < y1; ++ty) {
                     const uint32_t rowb = (ty - r0) * bw - c0;
                     for (uint32_t cx = x0; cx < x1; ++cx) {
-                        if (splat_touches_tile(sh.x, sh.y, sh.z, sh.w, thr, cx, ty)) {
+                        if (splat_touches_tile(spx, spy, sa, sb, thr, cx, ty)) {
                             atomicOr(&bits[rowb + cx], bit);
                             atomicOr(&s_sum[rowb + cx], wbit);
                         }
@@ -402,21 +440,21 @@ static uint32_t band_for(const Tables &tb) {
 }
 
 hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                             const uint2 *rect, const SplatRec *rec, float lambda, uint32_t *cnt, hipStream_t st) {
+                             const uint2 *rect, const SplatRec *rec, float lambda, uint32_t *cnt, BinRec *bin,
+                             hipStream_t st) {
     if (chunks == 0) return hipSuccess;
     const uint32_t band = band_for(tb);
     hipLaunchKernelGGL(k_tile_count, dim3(chunks), dim3(kCountThreads), (size_t)band * 4, st, tb, order, rect, rec,
-                       lambda, cnt, band);
+                       lambda, cnt, bin, band);
     return hipGetLastError();
 }
 
-hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                            const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
+hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const BinRec *bin, const uint32_t *pre,
                             const uint32_t *tile_base, uint32_t *pairs, uint32_t *zero4, uint32_t pair_cap,
                             hipStream_t st) {
     if (chunks == 0) return launch_fill_u32(zero4, 0u, 4, st);     // no items: no pairs
-    hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitThreads), 0, st, tb, order, rect, rec, lambda, pre,
-                       tile_base, pairs, zero4, pair_cap);
+    hipLaunchKernelGGL(k_tile_emit, dim3(chunks), dim3(kEmitThreads), 0, st, tb, bin, pre, tile_base, pairs, zero4,
+                       pair_cap);
     return hipGetLastError();
 }
 

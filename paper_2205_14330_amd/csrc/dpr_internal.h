@@ -89,6 +89,17 @@ struct __align__(16) SplatRec {
     float w, cr, cg, cb;    // w = log2(o); colour
 };
 
+// Binning record of one item in depth order (32 bytes), written by the tile
+// count and read by the emission: the item's tile rectangle, its id and
+// everything the (splat, tile) test reads, so the emission reads its items
+// contiguously instead of gathering two records per item by id.
+struct __align__(16) BinRec {
+    uint32_t rx, ry;        // tile rectangle (x0 | y0 << 16, x1 | y1 << 16)
+    uint32_t g;             // item id
+    float thr;              // w + lambda, the bound of the (splat, tile) test
+    float px, py, a, b;     // centre and axis coefficients of the splat record
+};
+
 // Index of the segment containing x: largest s < n with starts[s] <= x.
 __device__ __forceinline__ int find_segment(const uint32_t *starts, int n, uint32_t x) {
     int lo = 0, hi = n - 1;
@@ -204,8 +215,10 @@ hipError_t launch_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint64_t *
 uint64_t scan_partials(uint64_t n);
 
 // Binning.  cnt is chunk-major per view: cnt[cnt_off + c * tiles + t].
+// Also writes bin[s], the binning record of sorted item s.
 hipError_t launch_tile_count(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                             const uint2 *rect, const SplatRec *rec, float lambda, uint32_t *cnt, hipStream_t st);
+                             const uint2 *rect, const SplatRec *rec, float lambda, uint32_t *cnt, BinRec *bin,
+                             hipStream_t st);
 // In place: cnt[c][t] -> sum of cnt[c'][t] over c' < c; tile_total[tile] = column sum;
 // tile_base = exclusive scan of tile_total (tiles + 1 entries, the last = pair
 // count mod 2^32, the exact count in *total64); order = the tiles longest list
@@ -216,8 +229,7 @@ hipError_t launch_tile_colscan(const Tables &tb, uint32_t *cnt, uint32_t *segs, 
                                uint64_t *total64, hipStream_t st);
 // Also clears the 4 words at zero4 (the compositing counters that follow it).
 // With more than pair_cap pairs in the plan (tile_base[total tiles]) it does nothing.
-hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const uint32_t *order,
-                            const uint2 *rect, const SplatRec *rec, float lambda, const uint32_t *pre,
+hipError_t launch_tile_emit(const Tables &tb, uint32_t chunks, const BinRec *bin, const uint32_t *pre,
                             const uint32_t *tile_base, uint32_t *pairs, uint32_t *zero4, uint32_t pair_cap,
                             hipStream_t st);
 
