@@ -471,7 +471,11 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
         const float4 *ck = b.ckpt + ckpt_slot(c.start, tile, item.y + 1) * kTilePix;
         // per pixel: T (recovered front-to-back transmittance), dL/dI, and
         // D = dL/dI . B + dL/dT * T_final with B = sum over the blended splats
-        // behind of T_k alpha_k c_k, so that dL/dalpha_i = T_i (dL/dI . c_i) - D / (1 - alpha_i)
+        // behind of T_k alpha_k c_k, so that dL/dalpha_i = T_i (dL/dI . c_i) - D / (1 - alpha_i).
+        // The walk keeps E = D / T_after (T_after: the transmittance behind
+        // splat i, T_i (1 - alpha_i)) instead of D: then dL/dalpha_i =
+        // T_i (dL/dI . c_i - E) and, one splat further forward,
+        // E <- E + alpha_i (dL/dI . c_i - E), a convex step for alpha in [0, 1].
         float ux[kQuad], uy[kQuad], T[kQuad], gI0[kQuad], gI1[kQuad], gI2[kQuad], D[kQuad];
         uint32_t nl[kQuad];
         uint32_t mymax = 0;
@@ -500,6 +504,7 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                 }
                 mymax = max(mymax, min(nl[p], seg_end));
             }
+            D[p] = D[p] / T[p];      // E; T > 0 (a product of factors 1 - alpha >= 1 - alpha_max)
         }
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) mymax = max(mymax, (uint32_t)__shfl_xor((int)mymax, d, 64));
@@ -597,9 +602,9 @@ __global__ __launch_bounds__(kCompLanes) void k_composite_bwd(BackwardArgs b) {
                         T[p] = T[p] * iom;                       // T in front of this splat
                         Ta[p] = T[p] * alpha[p];
                         const float gc = fmaf(gI0[p], s.cr, fmaf(gI1[p], s.cg, gI2[p] * s.cb));
-                        const float dA = fmaf(T[p], gc, -D[p] * iom);   // dL/dalpha
-                        D[p] = fmaf(Ta[p], gc, D[p]);
-                        gw[p] = dA * alpha[p];                           // dL/de / ln 2
+                        const float t = gc - D[p];                       // dL/dalpha = T t (D holds E)
+                        gw[p] = Ta[p] * t;                               // dL/de / ln 2
+                        D[p] = fmaf(alpha[p], t, D[p]);
                     }
                     if (near_max) {
                         const float am = in_vgpr(alpha_max);
