@@ -240,8 +240,18 @@ __global__ __launch_bounds__(THREADS) void k_radix_hist(SEG seg, const uint32_t 
     const SortSeg sg = seg();
     for (uint32_t d = threadIdx.x; d < 256u; d += THREADS) h[d] = 0;
     __syncthreads();
-    for (uint32_t i = sg.beg + threadIdx.x; i < sg.end; i += THREADS)
-        atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    // eight keys per thread loaded together, then counted
+    for (uint32_t i0 = sg.beg + threadIdx.x; i0 < sg.end; i0 += 8u * THREADS) {
+        uint32_t kk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * THREADS;
+            kk[u] = i < sg.end ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + (uint32_t)u * THREADS < sg.end) atomicAdd(&h[(kk[u] >> shift) & 255u], 1u);
+    }
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < 256u; d += THREADS)
         hist[sg.hist_off + (uint64_t)d * sg.nsb + sg.lb] = h[d];
@@ -275,12 +285,21 @@ __global__ __launch_bounds__(THREADS) void k_radix_scatter(SEG seg, const uint32
 
     if (tid < 256u) s_run[tid] = 0;
     uint32_t k_[ITEMS], v_[ITEMS], r_[ITEMS];
+    // the thread's keys and values, all loads in flight together (the
+    // ranking rounds below are separated by barriers, past which the
+    // compiler does not move loads)
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = sg.beg + (uint32_t)r * THREADS + tid;
         const bool valid = idx < sg.end;
-        const uint32_t key = valid ? keys_in[idx] : 0u;
-        const uint32_t val = valid ? vals_in[idx] : 0u;
+        k_[r] = valid ? keys_in[idx] : 0u;
+        v_[r] = valid ? vals_in[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = sg.beg + (uint32_t)r * THREADS + tid;
+        const bool valid = idx < sg.end;
+        const uint32_t key = k_[r];
         const uint32_t d = (key >> shift) & 255u;
 #pragma unroll
         for (int q = 0; q < 4; ++q) s_wcnt[wave][lane + 64 * q] = 0;
@@ -307,8 +326,6 @@ __global__ __launch_bounds__(THREADS) void k_radix_scatter(SEG seg, const uint32
             s_run[tid] = acc;
         }
         __syncthreads();
-        k_[r] = key;
-        v_[r] = val;
         r_[r] = valid ? s_wcnt[wave][d] + lrank : 0xFFFFFFFFu;
         __syncthreads();
     }
@@ -399,14 +416,21 @@ __global__ __launch_bounds__(THREADS) void k_radix_scatter_wm(SEG seg, const uin
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     uint32_t k_[ITEMS], v_[ITEMS], r_[ITEMS];
     const uint32_t wbeg = sg.beg + wave * (uint32_t)(ITEMS * 64);
+    // the wave's keys and values, all loads in flight together (the ranking
+    // rounds below are separated by fences, past which the compiler does not
+    // move loads)
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = wbeg + (uint32_t)r * 64u + lane;
         const bool valid = idx < sg.end;
-        const uint32_t key = valid ? keys_in[idx] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
-        k_[r] = key;
+        k_[r] = valid ? keys_in[idx] : 0u;
         v_[r] = valid ? vals_in[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = wbeg + (uint32_t)r * 64u + lane;
+        const bool valid = idx < sg.end;
+        const uint32_t d = (k_[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
