@@ -121,30 +121,58 @@ struct CloudOut {
     float *xyz, *sh, *op, *rad;
 };
 
+// Per-point attribute rows: 3 position floats, K3 SH floats, opacity and
+// radius.  The kernels below walk whole rows (all K3 SH floats of a row
+// loaded together); K3 = 3 (degree + 1)^2 is a template argument so the rows
+// unroll, and HY_K3_DISPATCH picks the instance.  An FP64 accumulator per
+// attribute adds its terms in the same order as a per-attribute loop would.
+template <int K3>
+struct RowSum {
+    double x[3], sh[K3], op, rad;
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] = 0.0;
+#pragma unroll
+        for (int a = 0; a < K3; ++a) sh[a] = 0.0;
+        op = rad = 0.0;
+    }
+    __device__ __forceinline__ void add(const float *xyz, const float *shp, const float *opp, const float *radp,
+                                        size_t j) {
+        float v[3 + K3 + 2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[a] = xyz[3 * j + a];
+#pragma unroll
+        for (int a = 0; a < K3; ++a) v[3 + a] = shp[(size_t)K3 * j + a];
+        v[3 + K3] = opp[j];
+        v[4 + K3] = radp[j];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] += (double)v[a];
+#pragma unroll
+        for (int a = 0; a < K3; ++a) sh[a] += (double)v[3 + a];
+        op += (double)v[3 + K3];
+        rad += (double)v[4 + K3];
+    }
+    __device__ __forceinline__ void store_mean(const CloudOut &c, size_t o, double cnt) const {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c.xyz[3 * o + a] = (float)(x[a] / cnt);
+#pragma unroll
+        for (int a = 0; a < K3; ++a) c.sh[(size_t)K3 * o + a] = (float)(sh[a] / cnt);
+        c.op[o] = (float)(op / cnt);
+        c.rad[o] = (float)(rad / cnt);
+    }
+};
+
 // one thread per voxel: FP64 sums over its points in ascending index order
+template <int K3>
 __global__ __launch_bounds__(kHyThreads) void k_voxel_average(const uint32_t *starts, uint32_t m, const uint32_t *order,
-                                                             CloudIn in, int k3, CloudOut out) {
+                                                             CloudIn in, CloudOut out) {
     const uint32_t v = blockIdx.x * kHyThreads + threadIdx.x;
     if (v >= m) return;
     const uint32_t b = starts[v], e = starts[v + 1];
-    const double cnt = (double)(e - b);
-    for (int a = 0; a < 3; ++a) {
-        double s = 0.0;
-        for (uint32_t q = b; q < e; ++q) s += (double)in.xyz[3 * (size_t)order[q] + a];
-        out.xyz[3 * (size_t)v + a] = (float)(s / cnt);
-    }
-    for (int a = 0; a < k3; ++a) {
-        double s = 0.0;
-        for (uint32_t q = b; q < e; ++q) s += (double)in.sh[(size_t)k3 * order[q] + a];
-        out.sh[(size_t)k3 * v + a] = (float)(s / cnt);
-    }
-    double so = 0.0, sr = 0.0;
-    for (uint32_t q = b; q < e; ++q) {
-        so += (double)in.op[order[q]];
-        sr += (double)in.rad[order[q]];
-    }
-    out.op[v] = (float)(so / cnt);
-    out.rad[v] = (float)(sr / cnt);
+    RowSum<K3> acc;
+    acc.clear();
+    for (uint32_t q = b; q < e; ++q) acc.add(in.xyz, in.sh, in.op, in.rad, order[q]);
+    acc.store_mean(out, v, (double)(e - b));
 }
 
 // cell_start[c] = first sorted position with key >= c, for c in [0, ncells]
@@ -270,48 +298,55 @@ __global__ __launch_bounds__(kHyThreads) void k_spread_keep(const float *d2, uin
     keep[i] = (delta > eps) ? 0u : 1u;
 }
 
+template <int K3>
 __global__ __launch_bounds__(kHyThreads) void k_gather_kept(const uint32_t *keep, const uint32_t *pos, uint32_t m,
-                                                           CloudIn in, int k3, CloudOut out) {
+                                                           CloudIn in, CloudOut out) {
     const uint32_t i = blockIdx.x * kHyThreads + threadIdx.x;
     if (i >= m || !keep[i]) return;
     const uint32_t o = pos[i];
-    for (int a = 0; a < 3; ++a) out.xyz[3 * (size_t)o + a] = in.xyz[3 * (size_t)i + a];
-    for (int a = 0; a < k3; ++a) out.sh[(size_t)k3 * o + a] = in.sh[(size_t)k3 * i + a];
-    out.op[o] = in.op[i];
-    out.rad[o] = in.rad[i];
+    float v[3 + K3 + 2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = in.xyz[3 * (size_t)i + a];
+#pragma unroll
+    for (int a = 0; a < K3; ++a) v[3 + a] = in.sh[(size_t)K3 * i + a];
+    v[3 + K3] = in.op[i];
+    v[4 + K3] = in.rad[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out.xyz[3 * (size_t)o + a] = v[a];
+#pragma unroll
+    for (int a = 0; a < K3; ++a) out.sh[(size_t)K3 * o + a] = v[3 + a];
+    out.op[o] = v[3 + K3];
+    out.rad[o] = v[4 + K3];
 }
 
 // generated point i (written at m + i) = FP64 average of point i's neighbours, in neighbour order
-__global__ __launch_bounds__(kHyThreads) void k_generate(CloudOut c, uint32_t m, int k3, const int32_t *idx, int K,
-                                                        int keff) {
+template <int K3>
+__global__ __launch_bounds__(kHyThreads) void k_generate(CloudOut c, uint32_t m, const int32_t *idx, int K, int keff) {
     const uint32_t i = blockIdx.x * kHyThreads + threadIdx.x;
     if (i >= m) return;
     const int32_t *nb = idx + (size_t)i * K;
-    const double cnt = (double)keff;
-    const size_t o = (size_t)m + i;
-    for (int a = 0; a < 3; ++a) {
-        double s = 0.0;
-        for (int q = 0; q < keff; ++q) s += (double)c.xyz[3 * (size_t)nb[q] + a];
-        c.xyz[3 * o + a] = (float)(s / cnt);
-    }
-    for (int a = 0; a < k3; ++a) {
-        double s = 0.0;
-        for (int q = 0; q < keff; ++q) s += (double)c.sh[(size_t)k3 * nb[q] + a];
-        c.sh[(size_t)k3 * o + a] = (float)(s / cnt);
-    }
-    double so = 0.0, sr = 0.0;
-    for (int q = 0; q < keff; ++q) {
-        so += (double)c.op[nb[q]];
-        sr += (double)c.rad[nb[q]];
-    }
-    c.op[o] = (float)(so / cnt);
-    c.rad[o] = (float)(sr / cnt);
+    RowSum<K3> acc;
+    acc.clear();
+    for (int q = 0; q < keff; ++q) acc.add(c.xyz, c.sh, c.op, c.rad, (size_t)nb[q]);
+    acc.store_mean(c, (size_t)m + i, (double)keff);
 }
 
 // ---------------------------------------------------------------------------
 // host sequencing
 // ---------------------------------------------------------------------------
 static uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kHyThreads - 1) / kHyThreads); }
+
+// Launches KERNEL<K3> for the SH row length k3 = 3 (degree + 1)^2, degree 0..3.
+#define HY_K3_DISPATCH(k3, KERNEL, ...)                                                        \
+    do {                                                                                         \
+        switch (k3) {                                                                            \
+        case 3: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;                               \
+        case 12: hipLaunchKernelGGL(KERNEL<12>, __VA_ARGS__); break;                             \
+        case 27: hipLaunchKernelGGL(KERNEL<27>, __VA_ARGS__); break;                             \
+        case 48: hipLaunchKernelGGL(KERNEL<48>, __VA_ARGS__); break;                             \
+        default: return hipErrorInvalidValue;                                                    \
+        }                                                                                        \
+    } while (0)
 
 static int key_bits(uint64_t ncells) {
     int b = 0;
@@ -405,7 +440,7 @@ hipError_t launch_voxel_reduce(const float *xyz, const float *sh, const float *o
     const uint32_t m = (uint32_t)*m_host;
     CloudIn in{xyz, sh, op, rad};
     CloudOut out{oxyz, osh, oop, orad};
-    hipLaunchKernelGGL(k_voxel_average, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, s.starts, m, svals, in, k3,
+    HY_K3_DISPATCH(k3, k_voxel_average, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, s.starts, m, svals, in,
                        out);
     return hipGetLastError();
 }
@@ -424,7 +459,7 @@ hipError_t launch_filter_generate(const float *xyz, const float *sh, const float
     if (e != hipSuccess) return e;
     CloudIn in{xyz, sh, op, rad};
     CloudOut out{oxyz, osh, oop, orad};
-    hipLaunchKernelGGL(k_gather_kept, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, s.flags, s.seg, m, in, k3, out);
+    HY_K3_DISPATCH(k3, k_gather_kept, dim3(blocks_for(m)), dim3(kHyThreads), 0, st, s.flags, s.seg, m, in, out);
     e = read_count(s.total64, kept_host, st);
     if (e != hipSuccess) return e;
     const uint32_t mk = (uint32_t)*kept_host;
@@ -433,7 +468,7 @@ hipError_t launch_filter_generate(const float *xyz, const float *sh, const float
     e = launch_knn(oxyz, mk, K, s.idx, s.d2, s, st);
     if (e != hipSuccess) return e;
     const int keff2 = (int)std::min<uint64_t>((uint64_t)K, (uint64_t)mk - 1);
-    hipLaunchKernelGGL(k_generate, dim3(blocks_for(mk)), dim3(kHyThreads), 0, st, out, mk, k3, s.idx, K, keff2);
+    HY_K3_DISPATCH(k3, k_generate, dim3(blocks_for(mk)), dim3(kHyThreads), 0, st, out, mk, s.idx, K, keff2);
     *count_host = 2ull * mk;
     return hipGetLastError();
 }
