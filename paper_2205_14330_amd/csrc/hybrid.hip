@@ -65,11 +65,33 @@ __global__ __launch_bounds__(kHyThreads) void k_bbox_partial(const float *xyz, u
     }
 }
 
-__global__ void k_bbox_final(const float *part, uint32_t nb, float *box) {
+// One block of kHyThreads threads over nb <= kHyBoxBlocks partials (min and
+// max are exact in any order, so the box is that of one sequential pass).
+__global__ __launch_bounds__(kHyThreads) void k_bbox_final(const float *part, uint32_t nb, float *box) {
+    __shared__ float s[6][kHyThreads / 64];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t b = threadIdx.x; b < nb; b += kHyThreads) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], part[6 * b + a]);
+            hi[a] = fmaxf(hi[a], part[6 * b + 3 + a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], d, 64));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], d, 64));
+        }
+    }
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) { s[a][threadIdx.x >> 6] = lo[a]; s[3 + a][threadIdx.x >> 6] = hi[a]; }
+    __syncthreads();
     if (threadIdx.x < 6) {
-        float v = part[threadIdx.x];
-        for (uint32_t b = 1; b < nb; ++b)
-            v = threadIdx.x < 3 ? fminf(v, part[6 * b + threadIdx.x]) : fmaxf(v, part[6 * b + threadIdx.x]);
+        float v = s[threadIdx.x][0];
+        for (int w = 1; w < kHyThreads / 64; ++w)
+            v = threadIdx.x < 3 ? fminf(v, s[threadIdx.x][w]) : fmaxf(v, s[threadIdx.x][w]);
         box[threadIdx.x] = v;
     }
 }
@@ -379,7 +401,7 @@ HyScratchBytes hy_scratch_bytes(uint64_t n, int K) {
 static hipError_t bbox(const float *xyz, uint32_t n, HyScratch &s, hipStream_t st) {
     const uint32_t nb = std::min<uint32_t>(blocks_for(n), kHyBoxBlocks);
     hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kHyThreads), 0, st, xyz, n, s.box_part);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, s.box_part, nb, s.box);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kHyThreads), 0, st, s.box_part, nb, s.box);
     return hipGetLastError();
 }
 
