@@ -163,12 +163,20 @@ __global__ __launch_bounds__(kColThreads) void k_col_segscan(Tables tb, uint32_t
     const ColCtx c = col_ctx(tb);
     uint64_t mine = 0;
     if (c.ok) {
+        // 16 segment sums loaded before any is overwritten (the loads then
+        // wait once per batch, not once per segment)
         uint32_t run = 0;
-        for (uint32_t s = 0; s < c.nseg; ++s) {
-            uint32_t *p = segs + c.seg_off + (uint64_t)s * c.ntiles + c.t;
-            const uint32_t v = *p;
-            *p = run;
-            run += v;
+        for (uint32_t s0 = 0; s0 < c.nseg; s0 += 16u) {
+            uint32_t *const p = segs + c.seg_off + (uint64_t)s0 * c.ntiles + c.t;
+            uint32_t v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = s0 + u < c.nseg ? p[(uint64_t)u * c.ntiles] : 0u;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (s0 + u < c.nseg) {
+                    p[(uint64_t)u * c.ntiles] = run;
+                    run += v[u];
+                }
         }
         tile_total[c.gtile] = run;
         atomicAdd(&s_b[order_bucket(run)], 1u);
@@ -212,12 +220,17 @@ __global__ __launch_bounds__(kColThreads) void k_col_finish(Tables tb, uint32_t 
         if (c.ok && s < c.nseg) {
             const uint32_t c0 = s * kSegChunks, c1 = min(c0 + (uint32_t)kSegChunks, c.nchunks);
             uint32_t run = segs[c.seg_off + (uint64_t)s * c.ntiles + c.t];
-            for (uint32_t k = c0; k < c1; ++k) {
-                uint32_t *p = cnt + c.cnt_off + (uint64_t)k * c.ntiles + c.t;
-                const uint32_t v = *p;
-                *p = run;
-                run += v;
-            }
+            // the segment's counts loaded before any is overwritten
+            uint32_t *const p = cnt + c.cnt_off + (uint64_t)c0 * c.ntiles + c.t;
+            uint32_t v[kSegChunks];
+#pragma unroll
+            for (int u = 0; u < kSegChunks; ++u) v[u] = c0 + u < c1 ? p[(uint64_t)u * c.ntiles] : 0u;
+#pragma unroll
+            for (int u = 0; u < kSegChunks; ++u)
+                if (c0 + u < c1) {
+                    p[(uint64_t)u * c.ntiles] = run;
+                    run += v[u];
+                }
         }
     }
     if (blockIdx.y != 0) return;
