@@ -150,6 +150,7 @@ __global__ __launch_bounds__(kLossSumThreads) void k_loss_sum(LossBatch bt) {
     const int v = blockIdx.x;
     const uint32_t b0 = bt.block_start[v], b1 = bt.block_start[v + 1];
     double s = 0.0;
+#pragma unroll 8
     for (uint32_t b = b0 + threadIdx.x; b < b1; b += kLossSumThreads) s += (double)bt.partial[b];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
