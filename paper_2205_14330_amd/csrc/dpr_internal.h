@@ -99,7 +99,6 @@ struct __align__(16) BinRec {
     float thr;              // w + lambda, the bound of the (splat, tile) test
     float px, py, a, b;     // centre and axis coefficients of the splat record
 };
-static_assert(sizeof(BinRec) == 32, "a binning record is read and written as two 16-byte words");
 
 // Index of the segment containing x: largest s < n with starts[s] <= x.
 __device__ __forceinline__ int find_segment(const uint32_t *starts, int n, uint32_t x) {
