@@ -108,6 +108,19 @@ def test_hybrid_update_matches_oracle(dpr, name, N, K, eps):
     _assert_cloud_equal(got, ref, f"{name} N={N} K={K}")
 
 
+@pytest.mark.parametrize("deg", [0, 1, 3])
+def test_other_sh_degrees_match_oracle(dpr, deg):
+    """The row kernels have one instance per SH row length (3, 12, 27 and 48
+    floats); the other cases use degree 2."""
+    from paper_2205_14330_amd.hybrid import hybrid_update, voxel_reduce
+    c = _cloud_np(_clouds()["clusters"], deg=deg, seed=5)
+    _assert_cloud_equal(voxel_reduce(_to_gpu(c), 32), oracle.voxel_reduce(c, 32), f"voxels deg={deg}")
+    got, counts = hybrid_update(_to_gpu(c), 32, 8, 0.01)
+    red, keep, ref = oracle.hybrid_update(c, 32, 8, 0.01)
+    assert counts["voxels"] == red.n and counts["kept"] == int(keep.sum())
+    _assert_cloud_equal(got, ref, f"update deg={deg}")
+
+
 @pytest.mark.parametrize("n", [1, 2])
 def test_hybrid_update_tiny_clouds(dpr, n):
     from paper_2205_14330_amd.hybrid import hybrid_update

@@ -120,6 +120,20 @@ def test_hybrid_update(exe, tmp_path, name, N, K, eps):
     _assert_equal(_read_cloud(tmp_path, count, 27), ref, f"{name} N={N} K={K}")
 
 
+@pytest.mark.parametrize("deg", [0, 1, 3])
+def test_hybrid_update_other_sh_degrees(exe, tmp_path, deg):
+    """The row kernels have one instance per SH row length (3, 12, 27 and 48
+    floats); the other cases use degree 2."""
+    xyz = np.asarray(workloads.hybrid_clouds()["clusters"], np.float32)
+    c = oracle.Cloud(xyz, *workloads.point_attributes(xyz.shape[0], deg, 5))
+    k3 = 3 * (deg + 1) ** 2
+    _run(exe, tmp_path, "hybrid", _arrays(c), 32, 8, _eps_arg(0.01), k3)
+    m, kept, count = (int(v) for v in open(tmp_path / "counts.txt").read().split())
+    red, keep, ref = oracle.hybrid_update(c, 32, 8, 0.01)
+    assert (m, kept, count) == (red.n, int(keep.sum()), ref.n)
+    _assert_equal(_read_cloud(tmp_path, count, k3), ref, f"deg={deg}")
+
+
 @pytest.mark.parametrize("n", [1, 2])
 def test_hybrid_update_tiny_clouds(exe, tmp_path, n):
     c = _cloud(np.arange(3 * n, dtype=np.float32).reshape(n, 3), seed=0)
